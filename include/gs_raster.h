@@ -1,0 +1,215 @@
+/*
+ * gs_raster.h -- C ABI of the MI355X (gfx950) scale-aware, differentiable 2D
+ * Gaussian rasterizer of GSASR (arXiv 2501.06838, Sec. 3.1, Eq. 1-4,
+ * Algorithm 1).
+ *
+ * The library renders, for each image of a batch, the super-resolved image
+ *     I_SR(x, y; s) = sum_i alpha_i c_i f_i(x/s, y/s)            (Eq. 1, 2, 4)
+ * on the HR grid x in [0, out_w-1], y in [0, out_h-1], where f_i is the
+ * bivariate normal density of Eq. 2 and each Gaussian only touches the HR
+ * pixels inside its support box (Algorithm 1's strict window test, with the
+ * half-window equal to R standard deviations per axis; R = 3 on the exact
+ * path):
+ *     { x : s (mu_x - R sigma_x) < x < s (mu_x + R sigma_x) } x (same for y).
+ * It also returns the gradients of a loss w.r.t. every Gaussian property
+ * (the paper's renderer is differentiable, Sec. 3.1 "Fast Rasterization").
+ *
+ * Conventions shared by every entry point
+ *   - Units: mu and the covariance are in LR pixels, LR pixel centres at
+ *     integer coordinates (Eq. 3 samples integer x in [0, W-1]).  HR pixel
+ *     (x, y) samples the Gaussians at (x/s, y/s) (Eq. 4).
+ *   - HR size: out_h = floor(s H + 0.5), out_w = floor(s W + 0.5) in FP64
+ *     (Algorithm 1 allocates an sH x sW image; a non-integer product is
+ *     rounded half up).
+ *   - Covariance: Cholesky factor L = [[l11, 0], [l21, l22]] of Sigma, i.e.
+ *     sigma_x = l11, sigma_y = sqrt(l21^2 + l22^2), rho = l21 / sigma_y
+ *     (Sec. 3.1's sigma_x, sigma_y, rho).  l11 > 0 and l22 > 0; a Gaussian
+ *     violating that, or holding a non-finite value, has no support: it adds
+ *     nothing, gets zero gradients, and is counted (gs_diagnostics).
+ *   - Memory: every array argument named "device" is device memory owned by
+ *     the caller, FP32, C-contiguous.  gs_image arrays are host memory.  The
+ *     library allocates nothing on the device and keeps no global state:
+ *     calls on different streams with different workspaces may run
+ *     concurrently.
+ *   - Streams: stream is a hipStream_t passed as void* (NULL = default
+ *     stream).  Every device entry point only enqueues work on it and returns
+ *     without synchronising, unless marked "synchronising".
+ *   - Errors: arguments that can be checked on the host make the call return
+ *     an error with nothing enqueued.  Data-dependent problems never fault:
+ *     pair-list overflow is flagged in the workspace (see gs_diagnostics).
+ */
+#ifndef GS_RASTER_H
+#define GS_RASTER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GS_ABI_VERSION 1
+
+typedef int32_t gs_status;
+enum {
+    GS_OK = 0,
+    GS_E_INVALID = -1,     /* bad argument (host-checked), nothing enqueued  */
+    GS_E_CAPACITY = -2,    /* (tile, Gaussian) pairs exceeded pair_capacity  */
+    GS_E_DEVICE = -3,      /* a HIP runtime call failed                       */
+    GS_E_UNSUPPORTED = -4, /* valid but unsupported configuration             */
+    GS_E_WORKSPACE = -5    /* workspace missing or smaller than required      */
+};
+
+/* One image of a batch (host memory).  Its Gaussians are entries
+ * [g_begin, g_begin + g_count) of the packed Gaussian arrays; its output is
+ * the planar block [3][out_h][out_w] starting at element out_offset of the
+ * output (and of the upstream gradient).  Images may not overlap in either. */
+typedef struct {
+    int32_t lr_h, lr_w;   /* H, W >= 1                                       */
+    double scale;         /* s: finite, > 0                                  */
+    int64_t g_begin;      /* first Gaussian of this image                    */
+    int64_t g_count;      /* number of Gaussians (may be 0)                  */
+    int64_t out_offset;   /* element offset of the [3][out_h][out_w] block   */
+} gs_image;
+
+/* Launch configuration.  Zero fields take defaults. */
+typedef struct {
+    int32_t tile;          /* square HR tile side: 8, 16 (default) or 32     */
+    int32_t lds_batch;     /* Gaussians staged in LDS per round: 64, 128 or
+                              256 (default 256; at most the tile's threads)  */
+    int32_t flags;         /* GS_FLAG_*                                      */
+    int32_t reserved;
+    int64_t pair_capacity; /* max (tile, Gaussian) pairs the workspace holds;
+                              0 = n_gauss * 16 (use gs_count_pairs to size)  */
+} gs_config;
+
+/* flags */
+#define GS_FLAG_PERSISTENT 0x1 /* render with persistent work-queue kernels  */
+
+/* ABI version of the loaded library (GS_ABI_VERSION). */
+int32_t gs_abi_version(void);
+
+/* Short English text for a status code (static storage). */
+const char* gs_status_string(gs_status st);
+
+/* HR size of one image: out_h = floor(s H + 0.5), out_w = floor(s W + 0.5)
+ * (Algorithm 1's sH x sW image).  GS_E_INVALID if H, W < 1, s not finite or
+ * <= 0, or out_h * out_w >= 2^31. */
+gs_status gs_output_size(int32_t H, int32_t W, double s, int32_t* out_h, int32_t* out_w);
+
+/* Bytes of device workspace needed by gs_raster_forward / backward for this
+ * batch layout (cfg may be NULL for defaults).  The workspace holds the
+ * per-Gaussian render records, the (tile, Gaussian) pair lists before and
+ * after sorting, the per-tile ranges and the backward's per-Gaussian
+ * accumulators; it is written by the forward and read by the matching
+ * backward, so it must persist between the two. */
+gs_status gs_workspace_size(const gs_config* cfg, const gs_image* images, int32_t n_img,
+                            int64_t n_gauss, size_t* bytes);
+
+/* Forward render (Eq. 4 with Algorithm 1's truncated support) of a batch.
+ *   mean    device [n_gauss][2]  (mu_x, mu_y)
+ *   chol    device [n_gauss][3]  (l11, l21, l22)
+ *   color   device [n_gauss][3]  peak RGB c (not clamped)
+ *   opacity device [n_gauss]     alpha (not clamped)
+ *   radius  device [n_gauss] support half-widths R_i in standard deviations
+ *           (the pruned path), or NULL for R = 3 everywhere (exact path)
+ *   out     device, each image's [3][out_h][out_w] block at its out_offset;
+ *           every pixel of every block is written (background 0).
+ * Kernels: per-Gaussian support box and tile count, prefix sum, pair
+ * emission, device radix sort of (tile, Gaussian) keys, per-tile ranges, and
+ * the per-tile render.  Within a tile, Gaussians are summed in ascending
+ * index, so the result is bitwise deterministic for a given configuration. */
+gs_status gs_raster_forward(const gs_config* cfg, const gs_image* images, int32_t n_img,
+                            const float* mean, const float* chol, const float* color,
+                            const float* opacity, const float* radius, int64_t n_gauss,
+                            void* workspace, size_t ws_bytes, float* out, void* stream);
+
+/* First stage of gs_raster_forward: support boxes, tile counts, prefix sum,
+ * pair emission, radix sort and per-tile ranges, all into the workspace.
+ * Arguments as for gs_raster_forward. */
+gs_status gs_raster_bin(const gs_config* cfg, const gs_image* images, int32_t n_img,
+                        const float* mean, const float* chol, const float* color,
+                        const float* opacity, const float* radius, int64_t n_gauss,
+                        void* workspace, size_t ws_bytes, void* stream);
+
+/* Second stage of gs_raster_forward: the per-tile render (one kernel) from
+ * the workspace left by gs_raster_bin into out (layout as for
+ * gs_raster_forward). */
+gs_status gs_raster_render(const gs_config* cfg, const gs_image* images, int32_t n_img,
+                           int64_t n_gauss, void* workspace, size_t ws_bytes, float* out,
+                           void* stream);
+
+/* Backward of gs_raster_forward for upstream gradient grad_out = dL/dI
+ * (device, same layout as out).  Uses the workspace left by the forward of
+ * the same inputs.  Writes (overwrites) dL/d(mean) [n][2], dL/d(chol) [n][3],
+ * dL/d(color) [n][3] and dL/d(opacity) [n] (all device).  The support box is
+ * held fixed (its derivative is zero almost everywhere).  Per-tile partial
+ * sums are reduced in LDS before FP32 global atomics, so the result is not
+ * bitwise deterministic. */
+gs_status gs_raster_backward(const gs_config* cfg, const gs_image* images, int32_t n_img,
+                             const float* mean, const float* chol, const float* color,
+                             const float* opacity, const float* radius, int64_t n_gauss,
+                             void* workspace, size_t ws_bytes, const float* grad_out,
+                             float* grad_mean, float* grad_chol, float* grad_color,
+                             float* grad_opacity, void* stream);
+
+/* First stage of gs_raster_backward: the per-tile backward render (one
+ * kernel).  Accumulates, per Gaussian, the eight sums the gradients are made
+ * of into the workspace (they start at zero after a forward and after every
+ * gs_raster_gradients).  grad_out: device, layout of out. */
+gs_status gs_raster_render_backward(const gs_config* cfg, const gs_image* images,
+                                    int32_t n_img, int64_t n_gauss, void* workspace,
+                                    size_t ws_bytes, const float* grad_out, void* stream);
+
+/* Second stage of gs_raster_backward: per Gaussian, turns the accumulated
+ * sums into dL/d(mean, chol, color, opacity) (overwritten) and clears them. */
+gs_status gs_raster_gradients(const gs_config* cfg, const gs_image* images, int32_t n_img,
+                              const float* chol, const float* color, const float* opacity,
+                              int64_t n_gauss, void* workspace, size_t ws_bytes,
+                              float* grad_mean, float* grad_chol, float* grad_color,
+                              float* grad_opacity, void* stream);
+
+/* L1 training loss (Sec. 3.2, "Rendering": rendered SR image against the HR target)
+ * and its gradient: grad = sign(img - target) / numel with sign(0) = 0.
+ * img, target, grad: device [numel]; loss_sum: device double, the sum of
+ * |img - target| is atomically ADDED to it (zero it first to get one batch). */
+gs_status gs_l1_loss_grad(const float* img, const float* target, int64_t numel,
+                          float* grad, double* loss_sum, void* stream);
+
+/* Synchronising.  Counts of the last forward in this workspace: total
+ * (tile, Gaussian) pairs, overflow flag (pairs > capacity: the output of
+ * that forward is undefined), Gaussians flagged for invalid values, and the
+ * number of in-support (HR pixel, Gaussian) pairs (the sum of the support
+ * box areas: the work the method itself must do).  Any output pointer may be
+ * NULL.  Returns GS_E_CAPACITY when the overflow flag is set. */
+gs_status gs_diagnostics(const gs_config* cfg, const gs_image* images, int32_t n_img,
+                         int64_t n_gauss, const void* workspace, size_t ws_bytes,
+                         int64_t* n_pairs, int32_t* overflow, int64_t* n_invalid,
+                         int64_t* n_support, void* stream);
+
+/* Synchronising.  Exact number of (tile, Gaussian) pairs the forward of
+ * these Gaussians would emit: runs the support/count kernels in the given
+ * workspace (which only needs gs_workspace_size with pair_capacity = 1) and
+ * reads the total back.  Use it to size pair_capacity. */
+gs_status gs_count_pairs(const gs_config* cfg, const gs_image* images, int32_t n_img,
+                         const float* mean, const float* chol, const float* radius,
+                         int64_t n_gauss, void* workspace, size_t ws_bytes,
+                         int64_t* n_pairs, void* stream);
+
+/* Synchronising.  Copies the tile lists of the last forward to the host:
+ * ranges_host [n_tiles][2] = [begin, end) into gids_host (empty tiles
+ * [0, 0)); gids_host [max_pairs] the Gaussian indices, tile after tile, in
+ * ascending index within a tile.  Tiles are numbered row-major within an
+ * image and image after image.  n_tiles_out and n_pairs_out receive the
+ * sizes; pass NULL arrays to query them.  GS_E_CAPACITY if the lists
+ * overflowed, GS_E_INVALID if max_pairs is too small. */
+gs_status gs_tile_lists(const gs_config* cfg, const gs_image* images, int32_t n_img,
+                        int64_t n_gauss, const void* workspace, size_t ws_bytes,
+                        int32_t* ranges_host, int32_t* gids_host, int64_t max_pairs,
+                        int64_t* n_tiles_out, int64_t* n_pairs_out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GS_RASTER_H */

@@ -293,3 +293,34 @@ int64_t or_support_pairs(int32_t H, int32_t W, double s, int64_t n,
     }
     return total;
 }
+
+/* Values of the HR image of one image at selected pixels (xs[k], ys[k]):
+ * Eq. 4 summed over every Gaussian whose support box holds the pixel, in
+ * ascending Gaussian order.  out [3][npix].  Used to check renders too large
+ * to evaluate whole. */
+void or_pixel_values(int32_t H, int32_t W, double s, int64_t n,
+                     const double* mean, const double* chol, const double* color,
+                     const double* opacity, const double* radius,
+                     int64_t npix, const int32_t* xs, const int32_t* ys, double* out)
+{
+    int32_t oh, ow;
+    memset(out, 0, sizeof(double) * 3 * (size_t)npix);
+    if (or_output_size(H, W, s, &oh, &ow) != 0) return;
+    for (int64_t i = 0; i < n; ++i) {
+        const double mx = mean[2 * i], my = mean[2 * i + 1];
+        const double l11 = chol[3 * i], l21 = chol[3 * i + 1], l22 = chol[3 * i + 2];
+        int32_t r[4];
+        if (!or_support_rect(s, ow, oh, mx, my, l11, l21, l22, radius_of(radius, i), r)) continue;
+        if (!isfinite(opacity[i]) || !isfinite(color[3 * i]) || !isfinite(color[3 * i + 1]) ||
+            !isfinite(color[3 * i + 2]))
+            continue;
+        double sx, sy, rho;
+        chol_to_eq2(l11, l21, l22, &sx, &sy, &rho);
+        for (int64_t k = 0; k < npix; ++k) {
+            const int32_t x = xs[k], y = ys[k];
+            if (x < r[0] || x > r[1] || y < r[2] || y > r[3]) continue;
+            double f = eq2_density((double)x / s - mx, (double)y / s - my, sx, sy, rho);
+            for (int c = 0; c < 3; ++c) out[c * npix + k] += opacity[i] * color[3 * i + c] * f;
+        }
+    }
+}

@@ -62,6 +62,10 @@ def lib():
         L.or_support_pairs.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                        ctypes.c_int64, _D, _D, _D, _I32]
         L.or_support_pairs.restype = ctypes.c_int64
+        L.or_pixel_values.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                      ctypes.c_int64, _D, _D, _D, _D, _D, ctypes.c_int64,
+                                      _I32, _I32, _D]
+        L.or_pixel_values.restype = None
         _lib = L
     return _lib
 
@@ -125,6 +129,18 @@ def backward(H, W, s, mean, chol, color, opacity, grad_out, radius=None):
     lib().or_backward(H, W, float(s), n, _p(mean), _p(chol), _p(color), _p(opacity),
                       _p(rad), _p(g), _p(gm), _p(gc), _p(gcol), _p(gop))
     return gm, gc, gcol, gop
+
+
+def pixel_values(H, W, s, mean, chol, color, opacity, xs, ys, radius=None):
+    """Image values [3, npix] at HR pixels (xs[k], ys[k]) of one image."""
+    mean, chol, color, opacity = _d(mean), _d(chol), _d(color), _d(opacity)
+    rad = None if radius is None else _d(radius)
+    xs = np.ascontiguousarray(xs, dtype=np.int32)
+    ys = np.ascontiguousarray(ys, dtype=np.int32)
+    out = np.zeros((3, xs.size), dtype=np.float64)
+    lib().or_pixel_values(H, W, float(s), mean.shape[0], _p(mean), _p(chol), _p(color),
+                          _p(opacity), _p(rad), xs.size, _p(xs, _I32), _p(ys, _I32), _p(out))
+    return out
 
 
 def tile_lists(H, W, s, mean, chol, tw, th, radius=None):
@@ -207,7 +223,7 @@ def support_pairs_batch(wl, radius=None):
 
 def l1_loss_and_grad(images, targets):
     """Mean absolute error over every element of the batch and its gradient
-    sign(I - T) / numel (sign(0) = 0), the training loss of Sec. 3.3."""
+    sign(I - T) / numel (sign(0) = 0), the training loss of Sec. 3.2 ("Rendering")."""
     numel = sum(int(np.asarray(t).size) for t in targets)
     loss = 0.0
     grads = []

@@ -1,0 +1,9 @@
+"""MI355X (gfx950) scale-aware differentiable 2D Gaussian rasterizer of GSASR
+(arXiv 2501.06838, Sec. 3.1, Eq. 1-4, Algorithm 1).
+
+The compute path is the HIP library ``libgsraster.so`` (C ABI in
+include/gs_raster.h); this package only marshals arguments to it.
+"""
+from .raster import GSRasterize, RasterPlan, l1_loss_grad, rasterize  # noqa: F401
+
+__all__ = ["GSRasterize", "RasterPlan", "rasterize", "l1_loss_grad"]

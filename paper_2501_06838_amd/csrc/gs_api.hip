@@ -1,0 +1,331 @@
+// Host side of the C ABI declared in include/gs_raster.h: argument
+// validation, workspace layout, kernel sequencing on the caller's stream.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "gs_internal.h"
+
+namespace gs {
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int64_t kMaxPairs = 2147483647LL;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+gs_status size_of(int32_t H, int32_t W, double s, int32_t* oh, int32_t* ow) {
+    if (H < 1 || W < 1 || !std::isfinite(s) || !(s > 0.0)) return GS_E_INVALID;
+    const double h = floor(s * (double)H + 0.5);
+    const double w = floor(s * (double)W + 0.5);
+    if (!(h >= 1.0) || !(w >= 1.0) || h * w >= 2147483648.0) return GS_E_INVALID;
+    *oh = (int32_t)h;
+    *ow = (int32_t)w;
+    return GS_OK;
+}
+
+// Validates the batch description and computes the workspace layout and the
+// device image table.
+gs_status make_layout(const gs_config* cfg, const gs_image* images, int32_t n_img,
+                      int64_t n_gauss, Layout* L, std::vector<ImgDev>* table) {
+    if (n_img < 1 || images == nullptr || n_gauss < 0) return GS_E_INVALID;
+    Layout l;
+    l.tile = (cfg && cfg->tile) ? cfg->tile : 16;
+    if (l.tile != 8 && l.tile != 16 && l.tile != 32) return GS_E_UNSUPPORTED;
+    const int threads = l.tile * l.tile >= 256 ? 256 : l.tile * l.tile;
+    l.lds_batch = (cfg && cfg->lds_batch) ? cfg->lds_batch : threads;
+    if (l.lds_batch != threads) return GS_E_UNSUPPORTED;
+    l.flags = cfg ? cfg->flags : 0;
+    l.n_img = n_img;
+    l.n_gauss = n_gauss;
+
+    table->assign(n_img, ImgDev{});
+    int64_t tiles = 0, prev_end = 0;
+    std::vector<std::pair<int64_t, int64_t>> blocks;
+    for (int k = 0; k < n_img; ++k) {
+        const gs_image& im = images[k];
+        int32_t oh, ow;
+        if (size_of(im.lr_h, im.lr_w, im.scale, &oh, &ow) != GS_OK) return GS_E_INVALID;
+        if (im.g_begin < 0 || im.g_count < 0 || im.g_begin < prev_end ||
+            im.g_begin + im.g_count > n_gauss)
+            return GS_E_INVALID;  // Gaussian ranges ascending and disjoint
+        prev_end = im.g_begin + im.g_count;
+        if (im.out_offset < 0) return GS_E_INVALID;
+        blocks.emplace_back(im.out_offset, im.out_offset + 3LL * oh * ow);
+        ImgDev& d = (*table)[k];
+        d.out_w = ow;
+        d.out_h = oh;
+        d.tiles_x = (ow + l.tile - 1) / l.tile;
+        d.tiles_y = (oh + l.tile - 1) / l.tile;
+        d.out_offset = im.out_offset;
+        d.g_begin = im.g_begin;
+        d.g_count = im.g_count;
+        d.tile_base = tiles;
+        d.scale = im.scale;
+        tiles += (int64_t)d.tiles_x * d.tiles_y;
+    }
+    std::sort(blocks.begin(), blocks.end());
+    for (size_t k = 1; k < blocks.size(); ++k)
+        if (blocks[k].first < blocks[k - 1].second) return GS_E_INVALID;  // outputs overlap
+    if (tiles >= kMaxPairs) return GS_E_UNSUPPORTED;
+    l.n_tiles = tiles;
+
+    int64_t cap = (cfg && cfg->pair_capacity) ? cfg->pair_capacity : n_gauss * 16;
+    if (cap < 1) cap = 1;
+    if (cap > kMaxPairs) return GS_E_UNSUPPORTED;
+    l.cap = cap;
+    int bits = 0;
+    while (bits < 32 && ((int64_t)1 << bits) < tiles) ++bits;
+    l.n_passes = (bits + kRadixBits - 1) / kRadixBits;
+    l.nblk_g = (int32_t)std::max<int64_t>(1, (n_gauss + kBlockG - 1) / kBlockG);
+    l.nblk_sort = (int32_t)std::max<int64_t>(1, (cap + kSortTile - 1) / kSortTile);
+
+    // Capacity-independent sections first, so a small workspace can run the
+    // counting kernels of a larger layout.
+    size_t off = 0;
+    l.off_header = off; off = align_up(off + sizeof(WsHeader));
+    l.off_imgs = off; off = align_up(off + sizeof(ImgDev) * (size_t)n_img);
+    l.off_recs = off; off = align_up(off + sizeof(GRec) * (size_t)n_gauss);
+    l.off_counts = off; off = align_up(off + sizeof(int32_t) * (size_t)n_gauss);
+    l.off_offsets = off;
+    l.off_blocksums = off; off = align_up(off + sizeof(int64_t) * (size_t)l.nblk_g);
+    l.off_ranges = off; off = align_up(off + sizeof(int2) * (size_t)tiles);
+    l.off_moments = off; off = align_up(off + sizeof(float) * 8 * (size_t)n_gauss);
+    l.off_keys0 = off; off = align_up(off + sizeof(uint32_t) * (size_t)cap);
+    l.off_vals0 = off; off = align_up(off + sizeof(uint32_t) * (size_t)cap);
+    l.off_keys1 = off; off = align_up(off + sizeof(uint32_t) * (size_t)cap);
+    l.off_vals1 = off; off = align_up(off + sizeof(uint32_t) * (size_t)cap);
+    l.off_hist = off; off = align_up(off + sizeof(int32_t) * ((size_t)kRadix * l.nblk_sort + kRadix));
+    l.total = off;
+    *L = l;
+    return GS_OK;
+}
+
+// Bytes of the capacity-independent prefix of a layout.
+size_t counting_bytes(const Layout& L) { return L.off_keys0; }
+
+gs_status check_gauss_ptrs(int64_t n, const float* a, const float* b, const float* c,
+                           const float* d) {
+    if (n > 0 && (!a || !b || !c || !d)) return GS_E_INVALID;
+    return GS_OK;
+}
+
+gs_status dev(hipError_t e) { return e == hipSuccess ? GS_OK : GS_E_DEVICE; }
+
+#define GS_TRY(x)                                 \
+    do {                                          \
+        const gs_status _s = (x);                 \
+        if (_s != GS_OK) return _s;               \
+    } while (0)
+
+gs_status run_binning(const Layout& L, const Ws& w, const std::vector<ImgDev>& table,
+                      const float* mean, const float* chol, const float* color,
+                      const float* opacity, const float* radius, hipStream_t st) {
+    GS_TRY(dev(launch_setup(L, w, table.data(), st)));
+    GS_TRY(dev(launch_support(L, w, mean, chol, color, opacity, radius, st)));
+    GS_TRY(dev(launch_scan(L, w, st)));
+    GS_TRY(dev(launch_emit(L, w, st)));
+    GS_TRY(dev(launch_sort(L, w, st)));
+    GS_TRY(dev(launch_ranges(L, w, st)));
+    return GS_OK;
+}
+
+}  // namespace
+}  // namespace gs
+
+using namespace gs;
+
+extern "C" {
+
+int32_t gs_abi_version(void) { return GS_ABI_VERSION; }
+
+const char* gs_status_string(gs_status st) {
+    switch (st) {
+        case GS_OK: return "ok";
+        case GS_E_INVALID: return "invalid argument";
+        case GS_E_CAPACITY: return "pair capacity exceeded";
+        case GS_E_DEVICE: return "HIP runtime error";
+        case GS_E_UNSUPPORTED: return "unsupported configuration";
+        case GS_E_WORKSPACE: return "workspace missing or too small";
+        default: return "unknown status";
+    }
+}
+
+gs_status gs_output_size(int32_t H, int32_t W, double s, int32_t* out_h, int32_t* out_w) {
+    if (!out_h || !out_w) return GS_E_INVALID;
+    return size_of(H, W, s, out_h, out_w);
+}
+
+gs_status gs_workspace_size(const gs_config* cfg, const gs_image* images, int32_t n_img,
+                            int64_t n_gauss, size_t* bytes) {
+    if (!bytes) return GS_E_INVALID;
+    Layout L;
+    std::vector<ImgDev> table;
+    GS_TRY(make_layout(cfg, images, n_img, n_gauss, &L, &table));
+    *bytes = L.total;
+    return GS_OK;
+}
+
+gs_status gs_raster_bin(const gs_config* cfg, const gs_image* images, int32_t n_img,
+                        const float* mean, const float* chol, const float* color,
+                        const float* opacity, const float* radius, int64_t n_gauss,
+                        void* workspace, size_t ws_bytes, void* stream) {
+    Layout L;
+    std::vector<ImgDev> table;
+    GS_TRY(make_layout(cfg, images, n_img, n_gauss, &L, &table));
+    GS_TRY(check_gauss_ptrs(n_gauss, mean, chol, color, opacity));
+    if (!workspace || ws_bytes < L.total) return GS_E_WORKSPACE;
+    return run_binning(L, bind(L, workspace), table, mean, chol, color, opacity, radius,
+                       static_cast<hipStream_t>(stream));
+}
+
+gs_status gs_raster_render(const gs_config* cfg, const gs_image* images, int32_t n_img,
+                           int64_t n_gauss, void* workspace, size_t ws_bytes, float* out,
+                           void* stream) {
+    Layout L;
+    std::vector<ImgDev> table;
+    GS_TRY(make_layout(cfg, images, n_img, n_gauss, &L, &table));
+    if (!out) return GS_E_INVALID;
+    if (!workspace || ws_bytes < L.total) return GS_E_WORKSPACE;
+    return dev(launch_render_fwd(L, bind(L, workspace), out, static_cast<hipStream_t>(stream)));
+}
+
+gs_status gs_raster_forward(const gs_config* cfg, const gs_image* images, int32_t n_img,
+                            const float* mean, const float* chol, const float* color,
+                            const float* opacity, const float* radius, int64_t n_gauss,
+                            void* workspace, size_t ws_bytes, float* out, void* stream) {
+    if (!out) return GS_E_INVALID;
+    GS_TRY(gs_raster_bin(cfg, images, n_img, mean, chol, color, opacity, radius, n_gauss,
+                         workspace, ws_bytes, stream));
+    return gs_raster_render(cfg, images, n_img, n_gauss, workspace, ws_bytes, out, stream);
+}
+
+gs_status gs_raster_render_backward(const gs_config* cfg, const gs_image* images,
+                                    int32_t n_img, int64_t n_gauss, void* workspace,
+                                    size_t ws_bytes, const float* grad_out, void* stream) {
+    Layout L;
+    std::vector<ImgDev> table;
+    GS_TRY(make_layout(cfg, images, n_img, n_gauss, &L, &table));
+    if (!grad_out) return GS_E_INVALID;
+    if (!workspace || ws_bytes < L.total) return GS_E_WORKSPACE;
+    return dev(launch_render_bwd(L, bind(L, workspace), grad_out,
+                                 static_cast<hipStream_t>(stream)));
+}
+
+gs_status gs_raster_gradients(const gs_config* cfg, const gs_image* images, int32_t n_img,
+                              const float* chol, const float* color, const float* opacity,
+                              int64_t n_gauss, void* workspace, size_t ws_bytes,
+                              float* grad_mean, float* grad_chol, float* grad_color,
+                              float* grad_opacity, void* stream) {
+    Layout L;
+    std::vector<ImgDev> table;
+    GS_TRY(make_layout(cfg, images, n_img, n_gauss, &L, &table));
+    if (n_gauss > 0 && (!chol || !color || !opacity || !grad_mean || !grad_chol ||
+                        !grad_color || !grad_opacity))
+        return GS_E_INVALID;
+    if (!workspace || ws_bytes < L.total) return GS_E_WORKSPACE;
+    return dev(launch_finalize(L, bind(L, workspace), chol, color, opacity, grad_mean,
+                               grad_chol, grad_color, grad_opacity,
+                               static_cast<hipStream_t>(stream)));
+}
+
+gs_status gs_raster_backward(const gs_config* cfg, const gs_image* images, int32_t n_img,
+                             const float* mean, const float* chol, const float* color,
+                             const float* opacity, const float* radius, int64_t n_gauss,
+                             void* workspace, size_t ws_bytes, const float* grad_out,
+                             float* grad_mean, float* grad_chol, float* grad_color,
+                             float* grad_opacity, void* stream) {
+    (void)radius;
+    GS_TRY(check_gauss_ptrs(n_gauss, mean, chol, color, opacity));
+    GS_TRY(gs_raster_render_backward(cfg, images, n_img, n_gauss, workspace, ws_bytes,
+                                     grad_out, stream));
+    return gs_raster_gradients(cfg, images, n_img, chol, color, opacity, n_gauss, workspace,
+                               ws_bytes, grad_mean, grad_chol, grad_color, grad_opacity,
+                               stream);
+}
+
+gs_status gs_l1_loss_grad(const float* img, const float* target, int64_t numel,
+                          float* grad, double* loss_sum, void* stream) {
+    if (numel < 0) return GS_E_INVALID;
+    if (numel > 0 && (!img || !target || !grad || !loss_sum)) return GS_E_INVALID;
+    return dev(launch_l1(img, target, numel, grad, loss_sum, static_cast<hipStream_t>(stream)));
+}
+
+gs_status gs_diagnostics(const gs_config* cfg, const gs_image* images, int32_t n_img,
+                         int64_t n_gauss, const void* workspace, size_t ws_bytes,
+                         int64_t* n_pairs, int32_t* overflow, int64_t* n_invalid,
+                         int64_t* n_support, void* stream) {
+    Layout L;
+    std::vector<ImgDev> table;
+    GS_TRY(make_layout(cfg, images, n_img, n_gauss, &L, &table));
+    if (!workspace || ws_bytes < counting_bytes(L)) return GS_E_WORKSPACE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    WsHeader h;
+    GS_TRY(dev(hipMemcpyAsync(&h, static_cast<const char*>(workspace) + L.off_header,
+                              sizeof h, hipMemcpyDeviceToHost, st)));
+    GS_TRY(dev(hipStreamSynchronize(st)));
+    if (n_pairs) *n_pairs = h.n_pairs;
+    if (overflow) *overflow = h.overflow;
+    if (n_invalid) *n_invalid = h.n_invalid;
+    if (n_support) *n_support = h.n_support;
+    return h.overflow ? GS_E_CAPACITY : GS_OK;
+}
+
+gs_status gs_count_pairs(const gs_config* cfg, const gs_image* images, int32_t n_img,
+                         const float* mean, const float* chol, const float* radius,
+                         int64_t n_gauss, void* workspace, size_t ws_bytes,
+                         int64_t* n_pairs, void* stream) {
+    if (!n_pairs) return GS_E_INVALID;
+    Layout L;
+    std::vector<ImgDev> table;
+    gs_config c = cfg ? *cfg : gs_config{};
+    c.pair_capacity = 1;
+    GS_TRY(make_layout(&c, images, n_img, n_gauss, &L, &table));
+    if (n_gauss > 0 && (!mean || !chol)) return GS_E_INVALID;
+    if (!workspace || ws_bytes < counting_bytes(L)) return GS_E_WORKSPACE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const Ws w = bind(L, workspace);
+    // colour and opacity do not change the box: passed as NULL, the support
+    // kernel leaves the record's amplitudes at zero.  Only the counting
+    // kernels run, so nothing past the capacity-independent prefix is touched.
+    GS_TRY(dev(launch_setup(L, w, table.data(), st)));
+    GS_TRY(dev(launch_support(L, w, mean, chol, nullptr, nullptr, radius, st)));
+    GS_TRY(dev(launch_scan(L, w, st)));
+    WsHeader h;
+    GS_TRY(dev(hipMemcpyAsync(&h, static_cast<char*>(workspace) + L.off_header, sizeof h,
+                              hipMemcpyDeviceToHost, st)));
+    GS_TRY(dev(hipStreamSynchronize(st)));
+    *n_pairs = h.n_pairs;
+    return GS_OK;
+}
+
+gs_status gs_tile_lists(const gs_config* cfg, const gs_image* images, int32_t n_img,
+                        int64_t n_gauss, const void* workspace, size_t ws_bytes,
+                        int32_t* ranges_host, int32_t* gids_host, int64_t max_pairs,
+                        int64_t* n_tiles_out, int64_t* n_pairs_out, void* stream) {
+    Layout L;
+    std::vector<ImgDev> table;
+    GS_TRY(make_layout(cfg, images, n_img, n_gauss, &L, &table));
+    if (!workspace || ws_bytes < L.total) return GS_E_WORKSPACE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const char* b = static_cast<const char*>(workspace);
+    WsHeader h;
+    GS_TRY(dev(hipMemcpyAsync(&h, b + L.off_header, sizeof h, hipMemcpyDeviceToHost, st)));
+    GS_TRY(dev(hipStreamSynchronize(st)));
+    if (n_tiles_out) *n_tiles_out = L.n_tiles;
+    if (n_pairs_out) *n_pairs_out = h.n_pairs;
+    if (h.overflow) return GS_E_CAPACITY;
+    if (ranges_host)
+        GS_TRY(dev(hipMemcpyAsync(ranges_host, b + L.off_ranges, sizeof(int2) * L.n_tiles,
+                                  hipMemcpyDeviceToHost, st)));
+    if (gids_host) {
+        if (max_pairs < h.n_pairs) return GS_E_INVALID;
+        GS_TRY(dev(hipMemcpyAsync(gids_host, b + L.sorted_vals(), sizeof(uint32_t) * h.n_pairs,
+                                  hipMemcpyDeviceToHost, st)));
+    }
+    return dev(hipStreamSynchronize(st));
+}
+
+}  // extern "C"

@@ -1,0 +1,423 @@
+// Per-Gaussian support and tile binning for the gfx950 rasterizer:
+//   setup    - image table into the workspace, counters zeroed
+//   support  - per Gaussian (FP64): support box, tile range, tile count and
+//              the FP32 render record
+//   scan     - exclusive prefix sum of the tile counts (per-block sums in the
+//              support kernel, one workgroup over the block sums, local scans
+//              in the emission kernel)
+//   emit     - (tile id, Gaussian id) pairs, Gaussian-major, ascending id
+//   sort     - stable LSD radix sort of the pairs by tile id (8-bit digits)
+//   ranges   - [begin, end) of every tile in the sorted pairs
+//
+// The support box follows Algorithm 1's strict window test with the window
+// replaced by R standard deviations per axis, evaluated in HR pixels:
+//   { x integer : s (mu_x - R sigma_x) < x < s (mu_x + R sigma_x) }
+// with the FP64 operation sequence below (no fused multiply-add), so that
+// the box, the tile lists and the per-tile counts are exactly reproducible.
+#include "gs_internal.h"
+
+namespace gs {
+
+namespace {
+
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Inclusive scan of one int64 value per thread across a workgroup of
+// kBlockG threads.  `tmp` holds kBlockG / 64 entries.
+__device__ __forceinline__ int64_t block_inclusive_scan(int64_t v, int64_t* tmp) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int o = 1; o < 64; o <<= 1) {
+        int64_t u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
+    }
+    if (lane == 63) tmp[wave] = v;
+    __syncthreads();
+    int64_t carry = 0;
+    for (int k = 0; k < wave; ++k) carry += tmp[k];
+    __syncthreads();
+    return v + carry;
+}
+
+__global__ void k_setup(ImgChunk chunk, int first, int count, ImgDev* dst, WsHeader* hdr,
+                        int zero_header) {
+    int t = threadIdx.x;
+    if (t < count) dst[first + t] = chunk.img[t];
+    if (zero_header && t == 0) {
+        hdr->n_pairs = 0;
+        hdr->n_invalid = 0;
+        hdr->n_support = 0;
+        hdr->overflow = 0;
+        hdr->pad0 = 0;
+        for (int k = 0; k < 4; ++k) hdr->work[k] = 0;
+    }
+}
+
+__device__ __forceinline__ int find_image(const ImgDev* imgs, int n_img, int64_t i) {
+    // last image with g_begin <= i (images are validated ascending, disjoint)
+    int lo = 0, hi = n_img - 1, ans = -1;
+    while (lo <= hi) {
+        int mid = (lo + hi) >> 1;
+        if (imgs[mid].g_begin <= i) { ans = mid; lo = mid + 1; } else { hi = mid - 1; }
+    }
+    if (ans >= 0 && i >= imgs[ans].g_begin + imgs[ans].g_count) ans = -1;
+    return ans;
+}
+
+__device__ __forceinline__ bool finite_d(double v) { return __builtin_isfinite(v); }
+
+// Support box in HR pixels, clipped to the image (see the file comment).
+// Returns false when the box is empty or the parameters are invalid.
+__device__ bool support_box(double s, int out_w, int out_h, double mx, double my,
+                            double l11, double l21, double l22, double R, int* box) {
+#pragma clang fp contract(off)
+    if (!finite_d(mx) || !finite_d(my) || !finite_d(l11) || !finite_d(l21) ||
+        !finite_d(l22) || !finite_d(R))
+        return false;
+    if (!(l11 > 0.0) || !(l22 > 0.0) || !(R > 0.0)) return false;
+    const double sx = l11;
+    const double sy = __dsqrt_rn(l21 * l21 + l22 * l22);
+    const double lo_x = s * (mx - R * sx);
+    const double hi_x = s * (mx + R * sx);
+    const double lo_y = s * (my - R * sy);
+    const double hi_y = s * (my + R * sy);
+    double x0 = __builtin_floor(lo_x) + 1.0, x1 = __builtin_ceil(hi_x) - 1.0;
+    double y0 = __builtin_floor(lo_y) + 1.0, y1 = __builtin_ceil(hi_y) - 1.0;
+    if (x0 < 0.0) x0 = 0.0;
+    if (y0 < 0.0) y0 = 0.0;
+    if (x1 > (double)(out_w - 1)) x1 = (double)(out_w - 1);
+    if (y1 > (double)(out_h - 1)) y1 = (double)(out_h - 1);
+    if (x0 > x1 || y0 > y1) return false;
+    box[0] = (int)x0; box[1] = (int)x1; box[2] = (int)y0; box[3] = (int)y1;
+    return true;
+}
+
+// One thread per Gaussian: box, record, tile count; per-block count sums.
+// Also clears the per-tile ranges (grid-stride) for the range kernel.
+__global__ __launch_bounds__(kBlockG) void k_support(
+    const ImgDev* __restrict__ imgs, int n_img, int64_t n_gauss, int tile,
+    const float* __restrict__ mean, const float* __restrict__ chol,
+    const float* __restrict__ color, const float* __restrict__ opacity,
+    const float* __restrict__ radius, GRec* __restrict__ recs, int32_t* __restrict__ counts,
+    int64_t* __restrict__ blocksums, int2* __restrict__ ranges, int64_t n_tiles,
+    float4* __restrict__ moments, WsHeader* __restrict__ hdr) {
+    __shared__ int64_t tmp[kBlockG / 64];
+    const int64_t i = (int64_t)blockIdx.x * kBlockG + threadIdx.x;
+
+    for (int64_t t = i; t < n_tiles; t += (int64_t)gridDim.x * kBlockG)
+        ranges[t] = make_int2(0, 0);
+
+    int cnt = 0;
+    int64_t area = 0;
+    if (i < n_gauss) {
+        GRec r;
+        r.x0 = 0; r.x1 = -1; r.y0 = 0; r.y1 = -1;
+        r.fx = r.fy = 0.f; r.kx = r.ky = 0;
+        r.a = r.e = r.g = 0.f;
+        r.A[0] = r.A[1] = r.A[2] = 0.f;
+        r.pad = 0;
+        const int k = find_image(imgs, n_img, i);
+        r.img = k;
+        bool bad = false;
+        if (k >= 0) {
+            const ImgDev im = imgs[k];
+            const double s = im.scale;
+            const double mx = mean[2 * i], my = mean[2 * i + 1];
+            const double l11 = chol[3 * i], l21 = chol[3 * i + 1], l22 = chol[3 * i + 2];
+            const double R = radius ? (double)radius[i] : 3.0;
+            int box[4];
+            const bool shape_ok = finite_d(mx) && finite_d(my) && finite_d(l11) &&
+                                  finite_d(l21) && finite_d(l22) && l11 > 0.0 && l22 > 0.0;
+            bad = !shape_ok;
+            if (support_box(s, im.out_w, im.out_h, mx, my, l11, l21, l22, R, box)) {
+                // colour / opacity may be NULL when only the pairs are counted
+                const double al = opacity ? (double)opacity[i] : 0.0;
+                const double c0 = color ? (double)color[3 * i] : 0.0;
+                const double c1 = color ? (double)color[3 * i + 1] : 0.0;
+                const double c2 = color ? (double)color[3 * i + 2] : 0.0;
+                const bool amp_ok = finite_d(al) && finite_d(c0) && finite_d(c1) && finite_d(c2);
+                bad = bad || !amp_ok;
+                r.x0 = box[0]; r.x1 = box[1]; r.y0 = box[2]; r.y1 = box[3];
+                const double cx = s * mx, cy = s * my;
+                const double lim = 1073741824.0;  // keep the integer part in int32
+                const double kx = __builtin_floor(fmin(fmax(cx, -lim), lim));
+                const double ky = __builtin_floor(fmin(fmax(cy, -lim), lim));
+                r.kx = (int)kx; r.ky = (int)ky;
+                r.fx = (float)(cx - kx);
+                r.fy = (float)(cy - ky);
+                r.a = (float)(kZScale / (s * l11));
+                r.e = (float)(kZScale / (s * l22));
+                r.g = (float)(kZScale * l21 / (s * l11 * l22));
+                const double K = 1.0 / (2.0 * 3.14159265358979323846 * l11 * l22);
+                if (amp_ok) {
+                    r.A[0] = (float)(al * c0 * K);
+                    r.A[1] = (float)(al * c1 * K);
+                    r.A[2] = (float)(al * c2 * K);
+                } else {
+                    r.pad = 1;  // listed in tiles but contributes and receives nothing
+                }
+                const int tx0 = r.x0 / tile, tx1 = r.x1 / tile;
+                const int ty0 = r.y0 / tile, ty1 = r.y1 / tile;
+                cnt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+                area = (int64_t)(r.x1 - r.x0 + 1) * (r.y1 - r.y0 + 1);
+            }
+        }
+        if (bad) atomicAdd((unsigned long long*)&hdr->n_invalid, 1ull);
+        recs[i] = r;
+        counts[i] = cnt;
+        // backward accumulators start at zero (the gradient kernel re-zeroes
+        // them after reading, so every backward of this forward starts clean)
+        if (moments) {
+            moments[2 * i] = make_float4(0.f, 0.f, 0.f, 0.f);
+            moments[2 * i + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    }
+    __shared__ int64_t tmp_area[kBlockG / 64];
+    const int64_t v = wave_sum_i64((int64_t)cnt);
+    const int64_t va = wave_sum_i64(area);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) { tmp[wave] = v; tmp_area[wave] = va; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t s = 0, sa = 0;
+        for (int k = 0; k < kBlockG / 64; ++k) { s += tmp[k]; sa += tmp_area[k]; }
+        blocksums[blockIdx.x] = s;
+        if (sa) atomicAdd((unsigned long long*)&hdr->n_support, (unsigned long long)sa);
+    }
+}
+
+// One workgroup: exclusive scan of the per-block sums in place; total pairs
+// and the overflow flag into the header.
+__global__ __launch_bounds__(kBlockG) void k_scan_blocks(int64_t* __restrict__ blocksums,
+                                                         int nblk, int64_t cap,
+                                                         WsHeader* __restrict__ hdr) {
+    __shared__ int64_t tmp[kBlockG / 64];
+    int64_t carry = 0;
+    for (int base = 0; base < nblk; base += kBlockG) {
+        const int j = base + threadIdx.x;
+        const int64_t v = j < nblk ? blocksums[j] : 0;
+        const int64_t inc = block_inclusive_scan(v, tmp);
+        if (j < nblk) blocksums[j] = carry + inc - v;
+        __shared__ int64_t last;
+        if (threadIdx.x == kBlockG - 1) last = inc;
+        __syncthreads();
+        carry += last;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        hdr->n_pairs = carry;
+        hdr->overflow = carry > cap ? 1 : 0;
+    }
+}
+
+// One thread per Gaussian: local exclusive scan + block offset, then the
+// Gaussian's pairs in tile row-major order.  Pairs past the capacity are
+// dropped (the overflow flag is already set).
+__global__ __launch_bounds__(kBlockG) void k_emit(
+    const ImgDev* __restrict__ imgs, const GRec* __restrict__ recs,
+    const int32_t* __restrict__ counts, const int64_t* __restrict__ blocksums,
+    int64_t n_gauss, int tile, int64_t cap, uint32_t* __restrict__ keys,
+    uint32_t* __restrict__ vals) {
+    __shared__ int64_t tmp[kBlockG / 64];
+    const int64_t i = (int64_t)blockIdx.x * kBlockG + threadIdx.x;
+    const int cnt = i < n_gauss ? counts[i] : 0;
+    const int64_t inc = block_inclusive_scan((int64_t)cnt, tmp);
+    if (cnt == 0) return;
+    int64_t off = blocksums[blockIdx.x] + inc - cnt;
+    const GRec r = recs[i];
+    const ImgDev im = imgs[r.img];
+    const int tx0 = r.x0 / tile, tx1 = r.x1 / tile;
+    const int ty0 = r.y0 / tile, ty1 = r.y1 / tile;
+    for (int ty = ty0; ty <= ty1; ++ty) {
+        for (int tx = tx0; tx <= tx1; ++tx) {
+            if (off < cap) {
+                keys[off] = (uint32_t)(im.tile_base + (int64_t)ty * im.tiles_x + tx);
+                vals[off] = (uint32_t)i;
+            }
+            ++off;
+        }
+    }
+}
+
+__device__ __forceinline__ int64_t pairs_in_use(const WsHeader* hdr, int64_t cap) {
+    const int64_t p = hdr->n_pairs;
+    return p < cap ? p : cap;
+}
+
+// Per sort block: histogram of the digit at `shift`.  hist is digit-major:
+// hist[d * nblk + b].
+__global__ __launch_bounds__(kSortThreads) void k_sort_hist(
+    const uint32_t* __restrict__ keys, const WsHeader* __restrict__ hdr, int64_t cap,
+    int shift, int nblk, int32_t* __restrict__ hist) {
+    __shared__ int32_t cnt[kRadix];
+    const int t = threadIdx.x;
+    cnt[t] = 0;
+    __syncthreads();
+    const int64_t P = pairs_in_use(hdr, cap);
+    const int64_t start = (int64_t)blockIdx.x * kSortTile;
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) {
+        const int64_t idx = start + (int64_t)k * kSortThreads + t;
+        if (idx < P) atomicAdd(&cnt[(keys[idx] >> shift) & (kRadix - 1)], 1);
+    }
+    __syncthreads();
+    hist[(int64_t)t * nblk + blockIdx.x] = cnt[t];
+}
+
+// One workgroup per digit: exclusive scan of that digit's row over blocks,
+// row total into totals[d].
+__global__ __launch_bounds__(kBlockG) void k_sort_rowscan(int32_t* __restrict__ hist,
+                                                          int nblk,
+                                                          int32_t* __restrict__ totals) {
+    __shared__ int64_t tmp[kBlockG / 64];
+    __shared__ int64_t last;
+    int32_t* row = hist + (int64_t)blockIdx.x * nblk;
+    int64_t carry = 0;
+    for (int base = 0; base < nblk; base += kBlockG) {
+        const int j = base + threadIdx.x;
+        const int64_t v = j < nblk ? row[j] : 0;
+        const int64_t inc = block_inclusive_scan(v, tmp);
+        if (j < nblk) row[j] = (int32_t)(carry + inc - v);
+        if (threadIdx.x == kBlockG - 1) last = inc;
+        __syncthreads();
+        carry += last;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) totals[blockIdx.x] = (int32_t)carry;
+}
+
+// Stable scatter of one sort block.  Keys are ranked 256 at a time in index
+// order: within a wave by matching the digit bit by bit with ballots, across
+// the block's four waves through LDS counts.
+__global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
+    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
+    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
+    const int32_t* __restrict__ hist, const int32_t* __restrict__ totals,
+    const WsHeader* __restrict__ hdr, int64_t cap, int shift, int nblk) {
+    constexpr int kWaves = kSortThreads / 64;
+    __shared__ int32_t base[kRadix];
+    __shared__ int32_t wcnt[kWaves][kRadix];
+    __shared__ int64_t tmp[kBlockG / 64];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int64_t P = pairs_in_use(hdr, cap);
+    const int64_t start = (int64_t)blockIdx.x * kSortTile;
+    if (start >= P) return;  // uniform per block
+
+    // digit base = sum of lower digits' totals + this digit's earlier blocks
+    {
+        const int64_t tot = totals[t];
+        const int64_t inc = block_inclusive_scan(tot, tmp);
+        base[t] = (int32_t)(inc - tot) + hist[(int64_t)t * nblk + blockIdx.x];
+    }
+    for (int k = 0; k < kWaves; ++k) wcnt[k][t] = 0;
+    __syncthreads();
+
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int round = 0; round < kSortItems; ++round) {
+        const int64_t idx = start + (int64_t)round * kSortThreads + t;
+        const bool valid = idx < P;
+        uint32_t key = 0, val = 0;
+        if (valid) { key = keys_in[idx]; val = vals_in[idx]; }
+        const int d = (key >> shift) & (kRadix - 1);
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < kRadixBits; ++b) {
+            const bool bit = (d >> b) & 1;
+            const uint64_t bal = __ballot(bit);
+            peers &= bit ? bal : ~bal;
+        }
+        const int rank = __popcll(peers & lt_mask);
+        if (valid && rank == 0) wcnt[wave][d] = __popcll(peers);
+        __syncthreads();
+        if (valid) {
+            int pos = base[d] + rank;
+            for (int k = 0; k < wave; ++k) pos += wcnt[k][d];
+            keys_out[pos] = key;
+            vals_out[pos] = val;
+        }
+        __syncthreads();
+        int add = 0;
+        for (int k = 0; k < kWaves; ++k) { add += wcnt[k][t]; wcnt[k][t] = 0; }
+        base[t] += add;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kBlockG) void k_ranges(const uint32_t* __restrict__ keys,
+                                                    const WsHeader* __restrict__ hdr,
+                                                    int64_t cap, int2* __restrict__ ranges) {
+    const int64_t p = (int64_t)blockIdx.x * kBlockG + threadIdx.x;
+    const int64_t P = pairs_in_use(hdr, cap);
+    if (p >= P) return;
+    const uint32_t k = keys[p];
+    if (p == 0 || keys[p - 1] != k) ranges[k].x = (int)p;
+    if (p == P - 1 || keys[p + 1] != k) ranges[k].y = (int)(p + 1);
+}
+
+inline int blocks_for(int64_t n, int per) { return (int)((n + per - 1) / per); }
+
+}  // namespace
+
+hipError_t launch_setup(const Layout& L, const Ws& w, const ImgDev* host_imgs,
+                        hipStream_t st) {
+    for (int first = 0; first < L.n_img || first == 0; first += kSetupChunk) {
+        const int count = (L.n_img - first) < kSetupChunk ? (L.n_img - first) : kSetupChunk;
+        ImgChunk chunk;
+        for (int k = 0; k < kSetupChunk; ++k) chunk.img[k] = ImgDev{};
+        for (int k = 0; k < count; ++k) chunk.img[k] = host_imgs[first + k];
+        hipLaunchKernelGGL(k_setup, dim3(1), dim3(64), 0, st, chunk, first,
+                           count > 0 ? count : 0, w.imgs, w.hdr, first == 0 ? 1 : 0);
+        if (L.n_img == 0) break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_support(const Layout& L, const Ws& w, const float* mean,
+                          const float* chol, const float* color, const float* opacity,
+                          const float* radius, hipStream_t st) {
+    hipLaunchKernelGGL(k_support, dim3(L.nblk_g), dim3(kBlockG), 0, st, w.imgs, L.n_img,
+                       L.n_gauss, L.tile, mean, chol, color, opacity, radius, w.recs,
+                       w.counts, reinterpret_cast<int64_t*>(w.blocksums), w.ranges,
+                       L.n_tiles, reinterpret_cast<float4*>(w.moments), w.hdr);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan(const Layout& L, const Ws& w, hipStream_t st) {
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kBlockG), 0, st,
+                       reinterpret_cast<int64_t*>(w.blocksums), L.nblk_g, L.cap, w.hdr);
+    return hipGetLastError();
+}
+
+hipError_t launch_emit(const Layout& L, const Ws& w, hipStream_t st) {
+    hipLaunchKernelGGL(k_emit, dim3(L.nblk_g), dim3(kBlockG), 0, st, w.imgs, w.recs,
+                       w.counts, reinterpret_cast<const int64_t*>(w.blocksums), L.n_gauss,
+                       L.tile, L.cap, w.keys[0], w.vals[0]);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort(const Layout& L, const Ws& w, hipStream_t st) {
+    int32_t* totals = w.hist + (int64_t)kRadix * L.nblk_sort;
+    for (int pass = 0; pass < L.n_passes; ++pass) {
+        const int src = pass & 1, dst = src ^ 1;
+        const int shift = pass * kRadixBits;
+        hipLaunchKernelGGL(k_sort_hist, dim3(L.nblk_sort), dim3(kSortThreads), 0, st,
+                           w.keys[src], w.hdr, L.cap, shift, L.nblk_sort, w.hist);
+        hipLaunchKernelGGL(k_sort_rowscan, dim3(kRadix), dim3(kBlockG), 0, st, w.hist,
+                           L.nblk_sort, totals);
+        hipLaunchKernelGGL(k_sort_scatter, dim3(L.nblk_sort), dim3(kSortThreads), 0, st,
+                           w.keys[src], w.vals[src], w.keys[dst], w.vals[dst], w.hist,
+                           totals, w.hdr, L.cap, shift, L.nblk_sort);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_ranges(const Layout& L, const Ws& w, hipStream_t st) {
+    const uint32_t* keys = (L.n_passes & 1) ? w.keys[1] : w.keys[0];
+    hipLaunchKernelGGL(k_ranges, dim3(blocks_for(L.cap, kBlockG)), dim3(kBlockG), 0, st,
+                       keys, w.hdr, L.cap, w.ranges);
+    return hipGetLastError();
+}
+
+}  // namespace gs

@@ -1,0 +1,143 @@
+// Internal device structures and launchers of the gfx950 rasterizer library.
+// Not part of the C ABI (include/gs_raster.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "gs_raster.h"
+
+namespace gs {
+
+constexpr int kSetupChunk = 32;        // images per table-writer launch
+constexpr int kBlockG = 256;           // threads of per-Gaussian kernels
+constexpr int kSortThreads = 256;      // radix sort workgroup
+constexpr int kSortItems = 16;         // keys per thread per sort block
+constexpr int kSortTile = kSortThreads * kSortItems;
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+
+// exp(-q/2) = exp2(-(kc z)^2) with kc = sqrt(log2(e) / 2); the render
+// records carry z pre-multiplied by kc so the kernels call exp2 directly.
+constexpr double kZScale = 0.84932180028801904272;
+
+// Per-image table, resident in the workspace (64 B).
+struct ImgDev {
+    int32_t out_w, out_h;
+    int32_t tiles_x, tiles_y;
+    int64_t out_offset;     // element offset of [3][out_h][out_w]
+    int64_t g_begin, g_count;
+    int64_t tile_base;      // first global tile id of this image
+    double scale;
+    int64_t pad;
+};
+static_assert(sizeof(ImgDev) == 64, "ImgDev layout");
+
+// Per-Gaussian render record written by the support kernel (64 B).
+//   HR centre s*mu = (kx + fx, ky + fy), kx = floor(s*mu_x), fx in [0, 1).
+//   For an HR pixel at integer (x, y): X = (x - kx) - fx, Y = (y - ky) - fy,
+//   z1 = a X, z2 = e Y - g X, contribution A_c * exp2(-(z1^2 + z2^2)).
+struct GRec {
+    float fx, fy;
+    int32_t kx, ky;
+    float a, e, g;
+    float A[3];
+    int32_t x0, x1, y0, y1;  // support box, inclusive; x0 > x1 means none
+    int32_t img;
+    int32_t pad;
+};
+static_assert(sizeof(GRec) == 64, "GRec layout");
+
+// Device counters at the start of the workspace (256 B reserved).
+struct WsHeader {
+    int64_t n_pairs;      // pairs the emission produced (may exceed capacity)
+    int64_t n_invalid;    // Gaussians without support because of bad values
+    int64_t n_support;    // in-support (pixel, Gaussian) pairs: sum of box areas
+    int32_t overflow;     // n_pairs > capacity
+    int32_t pad0;
+    uint32_t work[4];     // persistent-kernel work counters
+};
+
+// Host-side workspace layout for one batch shape.
+struct Layout {
+    int32_t n_img = 0;
+    int32_t tile = 16;
+    int32_t lds_batch = 256;
+    int32_t flags = 0;
+    int64_t n_gauss = 0;
+    int64_t n_tiles = 0;
+    int64_t cap = 0;          // pair capacity
+    int32_t nblk_g = 0;       // blocks of per-Gaussian kernels
+    int32_t nblk_sort = 0;    // blocks of the sort at full capacity
+    int32_t n_passes = 0;     // radix passes over the tile-id bits
+    size_t off_header = 0, off_imgs = 0, off_recs = 0, off_counts = 0, off_offsets = 0,
+           off_blocksums = 0, off_keys0 = 0, off_vals0 = 0, off_keys1 = 0, off_vals1 = 0,
+           off_hist = 0, off_ranges = 0, off_moments = 0, total = 0;
+    // buffer holding the sorted result after n_passes ping-pong passes
+    size_t sorted_keys() const { return (n_passes & 1) ? off_keys1 : off_keys0; }
+    size_t sorted_vals() const { return (n_passes & 1) ? off_vals1 : off_vals0; }
+};
+
+// Device pointers into one workspace.
+struct Ws {
+    WsHeader* hdr;
+    ImgDev* imgs;
+    GRec* recs;
+    int32_t* counts;
+    int32_t* offsets;
+    int32_t* blocksums;
+    uint32_t* keys[2];
+    uint32_t* vals[2];
+    int32_t* hist;
+    int2* ranges;
+    float* moments;
+};
+
+inline Ws bind(const Layout& L, void* base) {
+    char* b = static_cast<char*>(base);
+    Ws w;
+    w.hdr = reinterpret_cast<WsHeader*>(b + L.off_header);
+    w.imgs = reinterpret_cast<ImgDev*>(b + L.off_imgs);
+    w.recs = reinterpret_cast<GRec*>(b + L.off_recs);
+    w.counts = reinterpret_cast<int32_t*>(b + L.off_counts);
+    w.offsets = reinterpret_cast<int32_t*>(b + L.off_offsets);
+    w.blocksums = reinterpret_cast<int32_t*>(b + L.off_blocksums);
+    w.keys[0] = reinterpret_cast<uint32_t*>(b + L.off_keys0);
+    w.vals[0] = reinterpret_cast<uint32_t*>(b + L.off_vals0);
+    w.keys[1] = reinterpret_cast<uint32_t*>(b + L.off_keys1);
+    w.vals[1] = reinterpret_cast<uint32_t*>(b + L.off_vals1);
+    w.hist = reinterpret_cast<int32_t*>(b + L.off_hist);
+    w.ranges = reinterpret_cast<int2*>(b + L.off_ranges);
+    w.moments = reinterpret_cast<float*>(b + L.off_moments);
+    return w;
+}
+
+// Table chunk passed by value to the table-writer kernel.
+struct ImgChunk {
+    ImgDev img[kSetupChunk];
+};
+
+// ---- launchers (gs_binning.hip) ------------------------------------------
+hipError_t launch_setup(const Layout& L, const Ws& w, const ImgDev* host_imgs,
+                        hipStream_t st);
+hipError_t launch_support(const Layout& L, const Ws& w, const float* mean,
+                          const float* chol, const float* color, const float* opacity,
+                          const float* radius, hipStream_t st);
+hipError_t launch_scan(const Layout& L, const Ws& w, hipStream_t st);
+hipError_t launch_emit(const Layout& L, const Ws& w, hipStream_t st);
+hipError_t launch_sort(const Layout& L, const Ws& w, hipStream_t st);
+hipError_t launch_ranges(const Layout& L, const Ws& w, hipStream_t st);
+
+// ---- launchers (gs_render.hip) -------------------------------------------
+hipError_t launch_render_fwd(const Layout& L, const Ws& w, float* out, hipStream_t st);
+hipError_t launch_render_bwd(const Layout& L, const Ws& w, const float* grad_out,
+                             hipStream_t st);
+hipError_t launch_finalize(const Layout& L, const Ws& w, const float* chol,
+                           const float* color, const float* opacity, float* grad_mean,
+                           float* grad_chol, float* grad_color, float* grad_opacity,
+                           hipStream_t st);
+hipError_t launch_l1(const float* img, const float* target, int64_t numel, float* grad,
+                     double* loss_sum, hipStream_t st);
+
+}  // namespace gs

@@ -1,0 +1,312 @@
+"""GPU parity of the HIP rasterizer against the FP64 oracle (through the C ABI).
+
+Bars: tile lists and counts bit-exact; forward within 1e-5 relative per
+element; gradients within 1e-3 (per tensor, see _gpu.assert_grad_close).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import oracle as O
+from tests._gpu import (assert_forward_close, assert_grad_close, plan_for, render, say,
+                        to_dev)
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_images(wl, radius=None):
+    return O.forward_batch(wl, radius)
+
+
+def _gpu_images(plan, out):
+    return [im.cpu().numpy() for im in plan.split(out)]
+
+
+# ------------------------------------------------------------- tile lists
+
+TILE_CASES = [
+    ("tiny_T8", lambda: synth.tiny(H=6, W=7, s=2.6, seed=6, extra_frac=0.3), 8),
+    ("tiny_T16_3img", lambda: synth.tiny(H=9, W=5, s=3.3, seed=7, n_images=3), 16),
+    ("tiny_T32", lambda: synth.tiny(H=13, W=11, s=5.5, seed=8, sigma=(0.8, 0.5)), 32),
+    ("config0_T16", lambda: synth.config0(), 16),
+    ("config0_T8", lambda: synth.config0(), 8),
+    ("config1x4_T16", lambda: synth.config1(n_images=4), 16),
+    ("config1x2_T32", lambda: synth.config1(n_images=2), 32),
+    ("config3x6_T16", lambda: synth.config3(n_images=6), 16),
+]
+
+
+@pytest.mark.parametrize("name,make,tile", TILE_CASES, ids=[c[0] for c in TILE_CASES])
+def test_tile_lists_bit_exact(name, make, tile):
+    wl = make()
+    say("tile lists", name, "tile", tile, "n", wl.n_gauss)
+    plan, ws, _ = render(wl, tile)
+    ranges, gids = plan.tile_lists(ws)
+    r_ref, g_ref = O.tile_lists_batch(wl, tile, tile)
+    assert np.array_equal(ranges, r_ref)
+    assert np.array_equal(gids, g_ref)
+    npairs, overflow, n_invalid, n_support = plan.diagnostics(ws, support=True)
+    assert npairs == len(g_ref) and overflow == 0 and n_invalid == 0
+    assert n_support == O.support_pairs_batch(wl)
+
+
+# ---------------------------------------------------------------- forward
+
+FWD_CASES = [
+    ("tiny_s1", lambda: synth.tiny(H=7, W=9, s=1.0, seed=3), 16),
+    ("tiny_s1.5_T8", lambda: synth.tiny(H=7, W=9, s=1.5, seed=3), 8),
+    ("tiny_s3.7_T32", lambda: synth.tiny(H=7, W=9, s=3.7, seed=3), 32),
+    ("tiny_wide", lambda: synth.tiny(H=10, W=12, s=6.25, seed=5, sigma=(0.8, 0.5),
+                                     extra_frac=0.5), 16),
+    ("config0_T16", lambda: synth.config0(), 16),
+    ("config0_T32", lambda: synth.config0(), 32),
+    ("config1_T16", lambda: synth.config1(), 16),
+    ("config3x4_T16", lambda: synth.config3(n_images=4), 16),
+]
+
+
+@pytest.mark.parametrize("name,make,tile", FWD_CASES, ids=[c[0] for c in FWD_CASES])
+def test_forward_parity(name, make, tile):
+    wl = make()
+    say("forward", name, "tile", tile, "n", wl.n_gauss)
+    plan, ws, out = render(wl, tile)
+    got = _gpu_images(plan, out)
+    ref = _oracle_images(wl)
+    for g, r in zip(got, ref):
+        assert_forward_close(g, r)
+
+
+def test_single_isotropic_gaussian_closed_form():
+    """One isotropic Gaussian: alpha c exp(-r^2 / 2 sigma^2) / (2 pi sigma^2)
+    inside the box, 0 outside."""
+    s, sig, alpha = 3.0, 0.7, 0.8
+    wl = synth.Workload("iso", [synth.Image(8, 9, s, 0, 1)],
+                        np.float32([[4.3, 3.6]]), np.float32([[sig, 0.0, sig]]),
+                        np.float32([[0.2, 0.5, 1.0]]), np.float32([alpha]))
+    say("closed form")
+    plan, ws, out = render(wl, 16)
+    img = plan.split(out)[0].cpu().numpy()
+    m = np.float64(wl.mean[0])
+    sg = float(np.float32(sig))
+    ys, xs = np.meshgrid(np.arange(img.shape[1]), np.arange(img.shape[2]), indexing="ij")
+    dx, dy = xs / s - m[0], ys / s - m[1]
+    inside = (np.abs(dx) < 3 * sg) & (np.abs(dy) < 3 * sg)
+    val = float(np.float32(alpha)) * np.exp(-(dx ** 2 + dy ** 2) / (2 * sg * sg)) / (2 * math.pi * sg * sg)
+    ref = np.where(inside, val, 0.0)[None] * np.float64(wl.color[0])[:, None, None]
+    assert_forward_close(img, ref)
+
+
+@pytest.mark.parametrize("which", ["config2a", "config2b"])
+def test_full_size_sampled(which):
+    """DIV2K-sized renders at full size: tile lists bit-exact, pair count
+    exact, and 3000 sampled pixels against the oracle's per-pixel sums."""
+    wl = synth.by_name(which)
+    say("full size", which, "n", wl.n_gauss)
+    plan, ws, out = render(wl, 16)
+    im = wl.images[0]
+    ranges, gids = plan.tile_lists(ws)
+    r_ref, g_ref = O.tile_lists_batch(wl, 16, 16)
+    assert np.array_equal(ranges, r_ref) and np.array_equal(gids, g_ref)
+    img = plan.split(out)[0].cpu().numpy()
+    rng = np.random.default_rng(11)
+    ys = rng.integers(0, img.shape[1], 3000)
+    xs = rng.integers(0, img.shape[2], 3000)
+    ref = O.pixel_values(im.lr_h, im.lr_w, im.scale, wl.mean, wl.chol, wl.color, wl.opacity,
+                         xs, ys)
+    assert_forward_close(img[:, ys, xs], ref)
+    assert np.isfinite(img).all()
+
+
+def test_forward_deterministic_and_permutation():
+    wl = synth.config1(n_images=2)
+    say("determinism")
+    plan, ws, out1 = render(wl, 16)
+    _, _, out2 = render(wl, 16, plan=plan)
+    assert torch.equal(out1, out2)
+    perm = np.concatenate([np.random.default_rng(k).permutation(im.g_count) + im.g_begin
+                           for k, im in enumerate(wl.images)])
+    wp = synth.Workload("perm", wl.images, wl.mean[perm], wl.chol[perm], wl.color[perm],
+                        wl.opacity[perm])
+    _, _, out3 = render(wp, 16)
+    a, b = out1.cpu().double(), out3.cpu().double()
+    assert ((a - b).abs() <= 1e-6 * a.abs() + 1e-30).all()
+
+
+def test_zero_gaussians_and_offimage():
+    wl = synth.tiny(H=5, W=4, s=2.0, seed=1)
+    wl.mean[:] = 1000.0  # every support box off the image
+    say("off image")
+    plan, ws, out = render(wl, 16)
+    assert (out == 0).all()
+    empty = synth.Workload("empty", [synth.Image(5, 4, 2.0, 0, 0)], np.zeros((0, 2), np.float32),
+                           np.zeros((0, 3), np.float32), np.zeros((0, 3), np.float32),
+                           np.zeros(0, np.float32))
+    say("no gaussians")
+    plan, ws, out = render(empty, 16)
+    assert out.numel() == 3 * 10 * 8 and (out == 0).all()
+
+
+def test_invalid_gaussians_skipped_and_counted():
+    wl = synth.tiny(H=6, W=6, s=2.5, seed=4)
+    wl.chol[0, 0] = -1.0            # l11 <= 0
+    wl.chol[1, 2] = 0.0             # l22 = 0
+    wl.mean[2, 0] = np.nan
+    wl.color[3, 1] = np.inf         # listed in tiles, contributes nothing
+    say("invalid")
+    plan, ws, out = render(wl, 16)
+    _, overflow, n_invalid = plan.diagnostics(ws)
+    assert n_invalid == 4 and overflow == 0
+    ref = _oracle_images(wl)[0]
+    assert_forward_close(plan.split(out)[0].cpu().numpy(), ref)
+    r_ref, g_ref = O.tile_lists_batch(wl, 16, 16)
+    ranges, gids = plan.tile_lists(ws)
+    assert np.array_equal(gids, g_ref)
+    m, c, col, op = to_dev(wl)
+    G = torch.ones(plan.out_numel, device="cuda")
+    gm, gc, gcol, gop = plan.backward(m, c, col, op, ws, G)
+    for g in (gm, gc, gcol, gop):
+        assert torch.isfinite(g).all()
+        assert (g[:4] == 0).all()
+
+
+def test_capacity_overflow_flagged_and_regrown():
+    wl = synth.tiny(H=8, W=8, s=4.0, seed=9)
+    plan = plan_for(wl, 8, pair_capacity=5)
+    m, c, col, op = to_dev(wl)
+    ws = plan.new_workspace()
+    out = plan.new_output()
+    say("overflow")
+    plan.forward(m, c, col, op, ws, out)
+    npairs, overflow, _ = plan.diagnostics(ws)
+    assert overflow == 1 and npairs > 5
+    assert npairs == plan.count_pairs(m, c)
+    # the differentiable path regrows and re-renders
+    img = __import__("paper_2501_06838_amd").rasterize(m, c, col, op, plan)
+    assert plan.capacity == npairs
+    assert_forward_close(plan.split(img)[0].cpu().numpy(), _oracle_images(wl)[0])
+
+
+def test_radius_support_path():
+    """Per-Gaussian support radius (the pruned path) against the oracle."""
+    wl = synth.config1(n_images=2)
+    R = np.random.default_rng(3).uniform(1.0, 3.0, wl.n_gauss).astype(np.float32)
+    say("radius path")
+    plan, ws, out = render(wl, 16, radius=R)
+    r_ref, g_ref = O.tile_lists_batch(wl, 16, 16, radius=R)
+    ranges, gids = plan.tile_lists(ws)
+    assert np.array_equal(ranges, r_ref) and np.array_equal(gids, g_ref)
+    for g, r in zip(_gpu_images(plan, out), _oracle_images(wl, R)):
+        assert_forward_close(g, r)
+
+
+# --------------------------------------------------------------- backward
+
+def test_l1_loss_kernel():
+    import paper_2501_06838_amd as P
+    rng = np.random.default_rng(0)
+    a = rng.uniform(0, 1, 100003).astype(np.float32)
+    b = rng.uniform(0, 1, 100003).astype(np.float32)
+    b[:50] = a[:50]  # sign(0) = 0
+    say("l1")
+    loss, g = P.l1_loss_grad(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda())
+    ref_loss, ref_g = O.l1_loss_and_grad([a], [b])
+    assert abs(loss.item() - ref_loss) <= 1e-12 * ref_loss
+    np.testing.assert_array_equal(g.cpu().numpy(), np.float32(ref_g[0]))
+
+
+@pytest.mark.parametrize("tile", [16, 8, 32])
+def test_backward_parity_config1(tile):
+    """Config-1 batch with the L1 loss: gradients of every Gaussian property
+    against the FP64 oracle (same upstream gradient on both sides)."""
+    wl = synth.config1(n_images=16 if tile == 16 else 3)
+    say("backward", tile, wl.n_gauss)
+    plan, ws, out = render(wl, tile)
+    ref_imgs = _oracle_images(wl)
+    _, grads = O.l1_loss_and_grad(ref_imgs, wl.target[:len(wl.images)])
+    G = plan.pack([torch.from_numpy(np.float32(g)) for g in grads]).cuda()
+    m, c, col, op = to_dev(wl)
+    gm, gc, gcol, gop = plan.backward(m, c, col, op, ws, G)
+    torch.cuda.synchronize()
+    rm, rc, rcol, rop = O.backward_batch(wl, [np.float64(np.float32(g)) for g in grads])
+    assert_grad_close(gm.cpu().numpy(), rm, name="mean")
+    assert_grad_close(gc.cpu().numpy(), rc, name="chol")
+    assert_grad_close(gcol.cpu().numpy(), rcol, name="color")
+    assert_grad_close(gop.cpu().numpy(), rop, name="opacity")
+
+
+def test_backward_central_differences_fp32():
+    """FP32 central differences of L = sum(G * I) on the GPU path itself, for
+    60 parameters of a config-1 image (boxes that move under +-h skipped)."""
+    wl = synth.config1(n_images=1)
+    plan = plan_for(wl, 16)
+    m, c, col, op = to_dev(wl)
+    plan.ensure_capacity(m, c, headroom=1.2)
+    ws = plan.new_workspace()
+    out = plan.new_output()
+    say("fd")
+    Gn = np.random.default_rng(5).normal(size=plan.out_numel).astype(np.float32)
+    G = torch.from_numpy(Gn).cuda()
+    plan.forward(m, c, col, op, ws, out)
+    grads = [g.cpu().numpy().copy() for g in plan.backward(m, c, col, op, ws, G)]
+    params = [m, c, col, op]
+    rng = np.random.default_rng(6)
+    im = wl.images[0]
+    base_rects = O.support_rects(im.lr_h, im.lr_w, im.scale, wl.mean, wl.chol)[0]
+    checked = 0
+    worst = 0.0
+    for _ in range(200):
+        if checked >= 60:
+            break
+        k = int(rng.integers(0, 4))
+        p = params[k]
+        flat = p.view(-1)
+        j = int(rng.integers(0, flat.numel()))
+        i_g = j // (p.shape[1] if p.dim() > 1 else 1)
+        old = float(flat[j])
+        h = 1e-2 if k == 0 else 1e-2 * max(abs(old), 0.1)
+        ok = True
+        vals = []
+        for sgn in (1, -1):
+            flat[j] = old + sgn * h
+            if k in (0, 1):
+                mm, cc = wl.mean.copy(), wl.chol.copy()
+                (mm if k == 0 else cc).reshape(-1)[j] = np.float32(old + sgn * h)
+                rr = O.support_rects(im.lr_h, im.lr_w, im.scale, mm, cc)[0]
+                ok = ok and np.array_equal(rr[i_g], base_rects[i_g])
+            plan.forward(m, c, col, op, ws, out)
+            vals.append(out.clone())
+        flat[j] = old
+        if not ok:
+            continue
+        dL = float((G.double() * (vals[0].double() - vals[1].double())).sum()) / (2 * h)
+        g = grads[k].reshape(-1)[j]
+        err = abs(dL - g) / max(abs(dL), 1e-3 * max(np.abs(grads[k]).max(), 1e-12))
+        worst = max(worst, err)
+        checked += 1
+    assert checked >= 40
+    assert worst < 1e-2, worst
+
+
+def test_autograd_matches_direct():
+    import paper_2501_06838_amd as P
+    wl = synth.config1(n_images=2)
+    plan = plan_for(wl, 16)
+    m, c, col, op = (t.clone().requires_grad_(True) for t in to_dev(wl))
+    say("autograd")
+    out = P.rasterize(m, c, col, op, plan)
+    tgt = plan.pack([torch.from_numpy(t) for t in wl.target]).cuda()
+    loss = (out - tgt).abs().mean()
+    loss.backward()
+    ref_imgs = _oracle_images(wl)
+    np.testing.assert_allclose(out.detach().cpu().numpy(),
+                               np.concatenate([r.ravel() for r in ref_imgs]), rtol=1e-5,
+                               atol=1e-30)
+    G = torch.sign(out.detach() - tgt) / out.numel()
+    rm, rc, rcol, rop = O.backward_batch(wl, [g.cpu().double().numpy() for g in plan.split(G)])
+    assert_grad_close(m.grad.cpu().numpy(), rm, name="mean")
+    assert_grad_close(c.grad.cpu().numpy(), rc, name="chol")
+    assert_grad_close(col.grad.cpu().numpy(), rcol, name="color")
+    assert_grad_close(op.grad.cpu().numpy(), rop, name="opacity")

@@ -26,8 +26,8 @@ def brute_force(H, W, s, mean, chol, color, opacity, R=3.0):
     the bivariate normal density); membership by the strict per-pixel box test
     s*(mu - R*sigma) < x < s*(mu + R*sigma) evaluated pixel by pixel."""
     oh, ow = _out_size(H, W, s)
-    mean, chol = np.float64(mean), np.float64(chol)
-    color, opacity = np.float64(color), np.float64(opacity)
+    mean, chol = np.asarray(mean, np.float64), np.asarray(chol, np.float64)
+    color, opacity = np.asarray(color, np.float64), np.asarray(opacity, np.float64)
     ys, xs = np.meshgrid(np.arange(oh, dtype=np.float64), np.arange(ow, dtype=np.float64),
                          indexing="ij")
     pts = np.stack([xs.ravel() / s, ys.ravel() / s], axis=1)
@@ -324,3 +324,33 @@ def test_l1_loss_grad_and_psnr():
     np.testing.assert_array_equal(g[0], np.array([[1, -1], [0, -1]]) / 4)
     x = np.full((3, 4, 4), 0.3)
     assert abs(O.psnr([x + 1e-3], [x]) - 60.0) < 1e-9
+
+
+def test_pixel_values_equal_full_render():
+    wl = synth.tiny(H=9, W=8, s=3.3, seed=17, extra_frac=0.25)
+    img = O.forward(9, 8, 3.3, wl.mean, wl.chol, wl.color, wl.opacity)
+    rng = np.random.default_rng(1)
+    ys = rng.integers(0, img.shape[1], 200)
+    xs = rng.integers(0, img.shape[2], 200)
+    vals = O.pixel_values(9, 8, 3.3, wl.mean, wl.chol, wl.color, wl.opacity, xs, ys)
+    np.testing.assert_allclose(vals, img[:, ys, xs], rtol=1e-13, atol=1e-300)
+
+
+def test_radius_support_shrinks_box():
+    """A per-Gaussian radius R replaces 3 in the box half-width: R = 3 equals
+    the default, a smaller R gives a subset of the pixels with identical
+    values there (brute force with R)."""
+    wl = synth.tiny(H=6, W=7, s=2.9, seed=23)
+    n = wl.n_gauss
+    a = O.forward(6, 7, 2.9, wl.mean, wl.chol, wl.color, wl.opacity)
+    b = O.forward(6, 7, 2.9, wl.mean, wl.chol, wl.color, wl.opacity, radius=np.full(n, 3.0))
+    np.testing.assert_array_equal(a, b)
+    R = np.random.default_rng(2).uniform(0.5, 3.0, n)
+    c = O.forward(6, 7, 2.9, wl.mean, wl.chol, wl.color, wl.opacity, radius=R)
+    ref = np.zeros_like(c)
+    for i in range(n):
+        part, _ = brute_force(6, 7, 2.9, wl.mean[i:i + 1], wl.chol[i:i + 1], wl.color[i:i + 1],
+                              wl.opacity[i:i + 1], R=R[i])
+        ref += part
+    np.testing.assert_allclose(c, ref, rtol=1e-12, atol=1e-300)
+    assert (c <= a + 1e-15).all()
