@@ -131,7 +131,7 @@ class RasterPlan:
     def ensure_capacity(self, mean, chol, radius=None, headroom: float = 1.0) -> int:
         """Sizes the pair capacity from the exact count (synchronising)."""
         need = self.count_pairs(mean, chol, radius)
-        if need > self.capacity:
+        if need > self.capacity or self.capacity <= 0:
             self.capacity = max(1, int(math.ceil(need * headroom)))
         return need
 
