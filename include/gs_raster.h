@@ -169,6 +169,32 @@ gs_status gs_raster_gradients(const gs_config* cfg, const gs_image* images, int3
                               float* grad_mean, float* grad_chol, float* grad_color,
                               float* grad_opacity, void* stream);
 
+/* Backward render fused with the L1 training loss (Sec. 3.2, "Rendering"):
+ * the upstream gradient sign(out - target) / numel (numel = all output
+ * elements of the batch, sign(0) = 0) is formed per tile from the rendered
+ * image `out` of the matching forward and `target` (device, layout of out)
+ * and never stored; each tile's sum |out - target| is kept in the workspace
+ * for gs_l1_loss_value.  Otherwise as gs_raster_render_backward. */
+gs_status gs_raster_render_backward_l1(const gs_config* cfg, const gs_image* images,
+                                       int32_t n_img, int64_t n_gauss, void* workspace,
+                                       size_t ws_bytes, const float* out, const float* target,
+                                       void* stream);
+
+/* Mean L1 loss of the last gs_raster_render_backward_l1 in this workspace,
+ * written to *loss (device double). */
+gs_status gs_l1_loss_value(const gs_config* cfg, const gs_image* images, int32_t n_img,
+                           int64_t n_gauss, const void* workspace, size_t ws_bytes,
+                           double* loss, void* stream);
+
+/* gs_raster_render_backward_l1 + gs_raster_gradients (+ gs_l1_loss_value
+ * when loss is not NULL): the training step's backward for the L1 loss. */
+gs_status gs_raster_backward_l1(const gs_config* cfg, const gs_image* images, int32_t n_img,
+                                const float* chol, const float* color, const float* opacity,
+                                int64_t n_gauss, void* workspace, size_t ws_bytes,
+                                const float* out, const float* target, float* grad_mean,
+                                float* grad_chol, float* grad_color, float* grad_opacity,
+                                double* loss, void* stream);
+
 /* L1 training loss (Sec. 3.2, "Rendering": rendered SR image against the HR target)
  * and its gradient: grad = sign(img - target) / numel with sign(0) = 0.
  * img, target, grad: device [numel]; loss_sum: device double, the sum of

@@ -25,7 +25,8 @@ EXPORTED = (
     "gs_abi_version", "gs_status_string", "gs_output_size", "gs_workspace_size",
     "gs_raster_forward", "gs_raster_backward", "gs_l1_loss_grad", "gs_diagnostics",
     "gs_count_pairs", "gs_tile_lists", "gs_raster_bin", "gs_raster_render",
-    "gs_raster_render_backward", "gs_raster_gradients",
+    "gs_raster_render_backward", "gs_raster_gradients", "gs_raster_render_backward_l1",
+    "gs_l1_loss_value", "gs_raster_backward_l1",
 )
 
 
@@ -99,6 +100,14 @@ def lib():
         L.gs_raster_gradients.argtypes = [_cfgp, _imgp, _i32, _vp, _vp, _vp, _i64, _vp, _sz,
                                           _vp, _vp, _vp, _vp, _vp]
         L.gs_raster_gradients.restype = _i32
+        L.gs_raster_render_backward_l1.argtypes = [_cfgp, _imgp, _i32, _i64, _vp, _sz, _vp,
+                                                   _vp, _vp]
+        L.gs_raster_render_backward_l1.restype = _i32
+        L.gs_l1_loss_value.argtypes = [_cfgp, _imgp, _i32, _i64, _vp, _sz, _vp, _vp]
+        L.gs_l1_loss_value.restype = _i32
+        L.gs_raster_backward_l1.argtypes = [_cfgp, _imgp, _i32, _vp, _vp, _vp, _i64, _vp, _sz,
+                                            _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+        L.gs_raster_backward_l1.restype = _i32
         if L.gs_abi_version() != 1:
             raise ImportError("libgsraster ABI version mismatch")
         _lib = L

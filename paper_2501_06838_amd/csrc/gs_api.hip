@@ -31,6 +31,7 @@ gs_status size_of(int32_t H, int32_t W, double s, int32_t* oh, int32_t* ow) {
 gs_status make_layout(const gs_config* cfg, const gs_image* images, int32_t n_img,
                       int64_t n_gauss, Layout* L, std::vector<ImgDev>* table) {
     if (n_img < 1 || images == nullptr || n_gauss < 0) return GS_E_INVALID;
+    if (n_gauss > 2147483647LL) return GS_E_UNSUPPORTED;  // Gaussian ids are 32-bit
     Layout l;
     l.tile = (cfg && cfg->tile) ? cfg->tile : 16;
     if (l.tile != 8 && l.tile != 16 && l.tile != 32) return GS_E_UNSUPPORTED;
@@ -90,9 +91,10 @@ gs_status make_layout(const gs_config* cfg, const gs_image* images, int32_t n_im
     l.off_recs = off; off = align_up(off + sizeof(GRec) * (size_t)n_gauss);
     l.off_counts = off; off = align_up(off + sizeof(int32_t) * (size_t)n_gauss);
     l.off_offsets = off;
-    l.off_blocksums = off; off = align_up(off + sizeof(int64_t) * (size_t)l.nblk_g);
+    l.off_blocksums = off; off = align_up(off + sizeof(BlockSums) * (size_t)l.nblk_g);
     l.off_ranges = off; off = align_up(off + sizeof(int2) * (size_t)tiles);
     l.off_moments = off; off = align_up(off + sizeof(float) * 8 * (size_t)n_gauss);
+    l.off_tile_loss = off; off = align_up(off + sizeof(double) * (size_t)tiles);
     l.off_keys0 = off; off = align_up(off + sizeof(uint32_t) * (size_t)cap);
     l.off_vals0 = off; off = align_up(off + sizeof(uint32_t) * (size_t)cap);
     l.off_keys1 = off; off = align_up(off + sizeof(uint32_t) * (size_t)cap);
@@ -101,6 +103,13 @@ gs_status make_layout(const gs_config* cfg, const gs_image* images, int32_t n_im
     l.total = off;
     *L = l;
     return GS_OK;
+}
+
+// Number of output elements (3 per HR pixel) over the whole batch.
+int64_t batch_numel(const std::vector<ImgDev>& table) {
+    int64_t n = 0;
+    for (const ImgDev& d : table) n += 3LL * d.out_w * d.out_h;
+    return n;
 }
 
 // Bytes of the capacity-independent prefix of a layout.
@@ -123,9 +132,8 @@ gs_status dev(hipError_t e) { return e == hipSuccess ? GS_OK : GS_E_DEVICE; }
 gs_status run_binning(const Layout& L, const Ws& w, const std::vector<ImgDev>& table,
                       const float* mean, const float* chol, const float* color,
                       const float* opacity, const float* radius, hipStream_t st) {
-    GS_TRY(dev(launch_setup(L, w, table.data(), st)));
-    GS_TRY(dev(launch_support(L, w, mean, chol, color, opacity, radius, st)));
-    GS_TRY(dev(launch_scan(L, w, st)));
+    GS_TRY(dev(launch_support(L, w, table.data(), mean, chol, color, opacity, radius, false,
+                              st)));
     GS_TRY(dev(launch_emit(L, w, st)));
     GS_TRY(dev(launch_sort(L, w, st)));
     GS_TRY(dev(launch_ranges(L, w, st)));
@@ -214,6 +222,31 @@ gs_status gs_raster_render_backward(const gs_config* cfg, const gs_image* images
                                  static_cast<hipStream_t>(stream)));
 }
 
+gs_status gs_raster_render_backward_l1(const gs_config* cfg, const gs_image* images,
+                                       int32_t n_img, int64_t n_gauss, void* workspace,
+                                       size_t ws_bytes, const float* out, const float* target,
+                                       void* stream) {
+    Layout L;
+    std::vector<ImgDev> table;
+    GS_TRY(make_layout(cfg, images, n_img, n_gauss, &L, &table));
+    if (!out || !target) return GS_E_INVALID;
+    if (!workspace || ws_bytes < L.total) return GS_E_WORKSPACE;
+    return dev(launch_render_bwd_l1(L, bind(L, workspace), out, target, batch_numel(table),
+                                    static_cast<hipStream_t>(stream)));
+}
+
+gs_status gs_l1_loss_value(const gs_config* cfg, const gs_image* images, int32_t n_img,
+                           int64_t n_gauss, const void* workspace, size_t ws_bytes,
+                           double* loss, void* stream) {
+    Layout L;
+    std::vector<ImgDev> table;
+    GS_TRY(make_layout(cfg, images, n_img, n_gauss, &L, &table));
+    if (!loss) return GS_E_INVALID;
+    if (!workspace || ws_bytes < L.total) return GS_E_WORKSPACE;
+    return dev(launch_sum_loss(L, bind(L, const_cast<void*>(workspace)), batch_numel(table),
+                               loss, static_cast<hipStream_t>(stream)));
+}
+
 gs_status gs_raster_gradients(const gs_config* cfg, const gs_image* images, int32_t n_img,
                               const float* chol, const float* color, const float* opacity,
                               int64_t n_gauss, void* workspace, size_t ws_bytes,
@@ -244,6 +277,22 @@ gs_status gs_raster_backward(const gs_config* cfg, const gs_image* images, int32
     return gs_raster_gradients(cfg, images, n_img, chol, color, opacity, n_gauss, workspace,
                                ws_bytes, grad_mean, grad_chol, grad_color, grad_opacity,
                                stream);
+}
+
+gs_status gs_raster_backward_l1(const gs_config* cfg, const gs_image* images, int32_t n_img,
+                                const float* chol, const float* color, const float* opacity,
+                                int64_t n_gauss, void* workspace, size_t ws_bytes,
+                                const float* out, const float* target, float* grad_mean,
+                                float* grad_chol, float* grad_color, float* grad_opacity,
+                                double* loss, void* stream) {
+    GS_TRY(gs_raster_render_backward_l1(cfg, images, n_img, n_gauss, workspace, ws_bytes, out,
+                                        target, stream));
+    GS_TRY(gs_raster_gradients(cfg, images, n_img, chol, color, opacity, n_gauss, workspace,
+                               ws_bytes, grad_mean, grad_chol, grad_color, grad_opacity,
+                               stream));
+    if (loss)
+        GS_TRY(gs_l1_loss_value(cfg, images, n_img, n_gauss, workspace, ws_bytes, loss, stream));
+    return GS_OK;
 }
 
 gs_status gs_l1_loss_grad(const float* img, const float* target, int64_t numel,
@@ -290,9 +339,8 @@ gs_status gs_count_pairs(const gs_config* cfg, const gs_image* images, int32_t n
     // colour and opacity do not change the box: passed as NULL, the support
     // kernel leaves the record's amplitudes at zero.  Only the counting
     // kernels run, so nothing past the capacity-independent prefix is touched.
-    GS_TRY(dev(launch_setup(L, w, table.data(), st)));
-    GS_TRY(dev(launch_support(L, w, mean, chol, nullptr, nullptr, radius, st)));
-    GS_TRY(dev(launch_scan(L, w, st)));
+    GS_TRY(dev(launch_support(L, w, table.data(), mean, chol, nullptr, nullptr, radius, true,
+                              st)));
     WsHeader h;
     GS_TRY(dev(hipMemcpyAsync(&h, static_cast<char*>(workspace) + L.off_header, sizeof h,
                               hipMemcpyDeviceToHost, st)));

@@ -14,6 +14,8 @@
 //   { x integer : s (mu_x - R sigma_x) < x < s (mu_x + R sigma_x) }
 // with the FP64 operation sequence below (no fused multiply-add), so that
 // the box, the tile lists and the per-tile counts are exactly reproducible.
+#include <algorithm>
+
 #include "gs_internal.h"
 
 namespace gs {
@@ -41,25 +43,18 @@ __device__ __forceinline__ int64_t block_inclusive_scan(int64_t v, int64_t* tmp)
     return v + carry;
 }
 
-__global__ void k_setup(ImgChunk chunk, int first, int count, ImgDev* dst, WsHeader* hdr,
-                        int zero_header) {
-    int t = threadIdx.x;
+__global__ void k_setup(ImgChunk chunk, int first, int count, ImgDev* dst) {
+    const int t = threadIdx.x;
     if (t < count) dst[first + t] = chunk.img[t];
-    if (zero_header && t == 0) {
-        hdr->n_pairs = 0;
-        hdr->n_invalid = 0;
-        hdr->n_support = 0;
-        hdr->overflow = 0;
-        hdr->pad0 = 0;
-        for (int k = 0; k < 4; ++k) hdr->work[k] = 0;
-    }
 }
 
-__device__ __forceinline__ int find_image(const ImgDev* imgs, int n_img, int64_t i) {
-    // last image with g_begin <= i (images are validated ascending, disjoint)
+// Last image with g_begin <= i (images are validated ascending and
+// disjoint); -1 if i falls in no image.
+template <typename Table>
+__device__ __forceinline__ int find_image(const Table& imgs, int n_img, int64_t i) {
     int lo = 0, hi = n_img - 1, ans = -1;
     while (lo <= hi) {
-        int mid = (lo + hi) >> 1;
+        const int mid = (lo + hi) >> 1;
         if (imgs[mid].g_begin <= i) { ans = mid; lo = mid + 1; } else { hi = mid - 1; }
     }
     if (ans >= 0 && i >= imgs[ans].g_begin + imgs[ans].g_count) ans = -1;
@@ -94,23 +89,30 @@ __device__ bool support_box(double s, int out_w, int out_h, double mx, double my
     return true;
 }
 
-// One thread per Gaussian: box, record, tile count; per-block count sums.
-// Also clears the per-tile ranges (grid-stride) for the range kernel.
+// One thread per Gaussian: box, record, tile count; per-block sums of the
+// pair counts, in-support areas and invalid flags.  Also clears the per-tile
+// ranges and the backward accumulators (grid-stride / per Gaussian).  With a
+// by-value image table (kArgTable, batches of at most kSetupChunk images) the
+// first block also writes the table into the workspace for later kernels.
+template <bool kArgTable>
 __global__ __launch_bounds__(kBlockG) void k_support(
-    const ImgDev* __restrict__ imgs, int n_img, int64_t n_gauss, int tile,
+    ImgChunk arg_imgs, ImgDev* __restrict__ imgs, int n_img, int64_t n_gauss, int tile,
     const float* __restrict__ mean, const float* __restrict__ chol,
     const float* __restrict__ color, const float* __restrict__ opacity,
     const float* __restrict__ radius, GRec* __restrict__ recs, int32_t* __restrict__ counts,
-    int64_t* __restrict__ blocksums, int2* __restrict__ ranges, int64_t n_tiles,
-    float4* __restrict__ moments, WsHeader* __restrict__ hdr) {
-    __shared__ int64_t tmp[kBlockG / 64];
+    BlockSums* __restrict__ blocksums, int2* __restrict__ ranges, int64_t n_tiles,
+    float4* __restrict__ moments) {
+    __shared__ int64_t tmp[3][kBlockG / 64];
     const int64_t i = (int64_t)blockIdx.x * kBlockG + threadIdx.x;
 
+    if (kArgTable && blockIdx.x == 0 && threadIdx.x < n_img)
+        imgs[threadIdx.x] = arg_imgs.img[threadIdx.x];
     for (int64_t t = i; t < n_tiles; t += (int64_t)gridDim.x * kBlockG)
         ranges[t] = make_int2(0, 0);
 
     int cnt = 0;
     int64_t area = 0;
+    int bad = 0;
     if (i < n_gauss) {
         GRec r;
         r.x0 = 0; r.x1 = -1; r.y0 = 0; r.y1 = -1;
@@ -118,11 +120,10 @@ __global__ __launch_bounds__(kBlockG) void k_support(
         r.a = r.e = r.g = 0.f;
         r.A[0] = r.A[1] = r.A[2] = 0.f;
         r.pad = 0;
-        const int k = find_image(imgs, n_img, i);
+        const int k = kArgTable ? find_image(arg_imgs.img, n_img, i) : find_image(imgs, n_img, i);
         r.img = k;
-        bool bad = false;
         if (k >= 0) {
-            const ImgDev im = imgs[k];
+            const ImgDev im = kArgTable ? arg_imgs.img[k] : imgs[k];
             const double s = im.scale;
             const double mx = mean[2 * i], my = mean[2 * i + 1];
             const double l11 = chol[3 * i], l21 = chol[3 * i + 1], l22 = chol[3 * i + 2];
@@ -130,7 +131,7 @@ __global__ __launch_bounds__(kBlockG) void k_support(
             int box[4];
             const bool shape_ok = finite_d(mx) && finite_d(my) && finite_d(l11) &&
                                   finite_d(l21) && finite_d(l22) && l11 > 0.0 && l22 > 0.0;
-            bad = !shape_ok;
+            bad = shape_ok ? 0 : 1;
             if (support_box(s, im.out_w, im.out_h, mx, my, l11, l21, l22, R, box)) {
                 // colour / opacity may be NULL when only the pairs are counted
                 const double al = opacity ? (double)opacity[i] : 0.0;
@@ -138,7 +139,7 @@ __global__ __launch_bounds__(kBlockG) void k_support(
                 const double c1 = color ? (double)color[3 * i + 1] : 0.0;
                 const double c2 = color ? (double)color[3 * i + 2] : 0.0;
                 const bool amp_ok = finite_d(al) && finite_d(c0) && finite_d(c1) && finite_d(c2);
-                bad = bad || !amp_ok;
+                if (!amp_ok) bad = 1;
                 r.x0 = box[0]; r.x1 = box[1]; r.y0 = box[2]; r.y1 = box[3];
                 const double cx = s * mx, cy = s * my;
                 const double lim = 1073741824.0;  // keep the integer part in int32
@@ -164,7 +165,6 @@ __global__ __launch_bounds__(kBlockG) void k_support(
                 area = (int64_t)(r.x1 - r.x0 + 1) * (r.y1 - r.y0 + 1);
             }
         }
-        if (bad) atomicAdd((unsigned long long*)&hdr->n_invalid, 1ull);
         recs[i] = r;
         counts[i] = cnt;
         // backward accumulators start at zero (the gradient kernel re-zeroes
@@ -174,58 +174,104 @@ __global__ __launch_bounds__(kBlockG) void k_support(
             moments[2 * i + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
     }
-    __shared__ int64_t tmp_area[kBlockG / 64];
-    const int64_t v = wave_sum_i64((int64_t)cnt);
-    const int64_t va = wave_sum_i64(area);
+    const int64_t v0 = wave_sum_i64((int64_t)cnt);
+    const int64_t v1 = wave_sum_i64(area);
+    const int64_t v2 = wave_sum_i64((int64_t)bad);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) { tmp[wave] = v; tmp_area[wave] = va; }
+    if (lane == 0) { tmp[0][wave] = v0; tmp[1][wave] = v1; tmp[2][wave] = v2; }
     __syncthreads();
     if (threadIdx.x == 0) {
-        int64_t s = 0, sa = 0;
-        for (int k = 0; k < kBlockG / 64; ++k) { s += tmp[k]; sa += tmp_area[k]; }
-        blocksums[blockIdx.x] = s;
-        if (sa) atomicAdd((unsigned long long*)&hdr->n_support, (unsigned long long)sa);
+        BlockSums b{0, 0, 0};
+        for (int k = 0; k < kBlockG / 64; ++k) {
+            b.pairs += tmp[0][k]; b.support += tmp[1][k]; b.invalid += tmp[2][k];
+        }
+        blocksums[blockIdx.x] = b;
     }
 }
 
-// One workgroup: exclusive scan of the per-block sums in place; total pairs
-// and the overflow flag into the header.
-__global__ __launch_bounds__(kBlockG) void k_scan_blocks(int64_t* __restrict__ blocksums,
-                                                         int nblk, int64_t cap,
+// One workgroup: exclusive scan of the per-block pair counts (in place in
+// .pairs), and the header totals.
+__global__ __launch_bounds__(kBlockG) void k_scan_blocks(BlockSums* __restrict__ bs, int nblk,
+                                                         int64_t cap,
                                                          WsHeader* __restrict__ hdr) {
     __shared__ int64_t tmp[kBlockG / 64];
-    int64_t carry = 0;
+    __shared__ int64_t last;
+    int64_t carry = 0, sup = 0, inv = 0;
     for (int base = 0; base < nblk; base += kBlockG) {
         const int j = base + threadIdx.x;
-        const int64_t v = j < nblk ? blocksums[j] : 0;
+        int64_t v = 0;
+        if (j < nblk) {
+            v = bs[j].pairs;
+            sup += bs[j].support;
+            inv += bs[j].invalid;
+        }
         const int64_t inc = block_inclusive_scan(v, tmp);
-        if (j < nblk) blocksums[j] = carry + inc - v;
-        __shared__ int64_t last;
+        if (j < nblk) bs[j].pairs = carry + inc - v;
         if (threadIdx.x == kBlockG - 1) last = inc;
         __syncthreads();
         carry += last;
         __syncthreads();
     }
+    sup = wave_sum_i64(sup);
+    inv = wave_sum_i64(inv);
+    __shared__ int64_t ts[kBlockG / 64], ti[kBlockG / 64];
+    if ((threadIdx.x & 63) == 0) { ts[threadIdx.x >> 6] = sup; ti[threadIdx.x >> 6] = inv; }
+    __syncthreads();
     if (threadIdx.x == 0) {
+        int64_t a = 0, b = 0;
+        for (int k = 0; k < kBlockG / 64; ++k) { a += ts[k]; b += ti[k]; }
         hdr->n_pairs = carry;
         hdr->overflow = carry > cap ? 1 : 0;
+        hdr->n_support = a;
+        hdr->n_invalid = b;
     }
 }
 
 // One thread per Gaussian: local exclusive scan + block offset, then the
 // Gaussian's pairs in tile row-major order.  Pairs past the capacity are
-// dropped (the overflow flag is already set).
+// dropped (the overflow flag says so).  With kFold the block computes its
+// offset from the unscanned block sums itself, and the last block writes the
+// header totals (k_scan_blocks does both otherwise).
+template <bool kFold>
 __global__ __launch_bounds__(kBlockG) void k_emit(
     const ImgDev* __restrict__ imgs, const GRec* __restrict__ recs,
-    const int32_t* __restrict__ counts, const int64_t* __restrict__ blocksums,
+    const int32_t* __restrict__ counts, const BlockSums* __restrict__ bs, int nblk,
     int64_t n_gauss, int tile, int64_t cap, uint32_t* __restrict__ keys,
-    uint32_t* __restrict__ vals) {
+    uint32_t* __restrict__ vals, WsHeader* __restrict__ hdr) {
     __shared__ int64_t tmp[kBlockG / 64];
+    int64_t base;
+    if (kFold) {
+        const int b = blockIdx.x;
+        const bool last_block = b == nblk - 1;
+        int64_t lower = 0, sup = 0, inv = 0;
+        for (int j = threadIdx.x; j < nblk; j += kBlockG) {
+            if (j < b) lower += bs[j].pairs;
+            if (last_block) { sup += bs[j].support; inv += bs[j].invalid; }
+        }
+        lower = wave_sum_i64(lower);
+        __shared__ int64_t t3[3][kBlockG / 64];
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        if (last_block) { sup = wave_sum_i64(sup); inv = wave_sum_i64(inv); }
+        if (lane == 0) { t3[0][wave] = lower; t3[1][wave] = sup; t3[2][wave] = inv; }
+        __syncthreads();
+        base = 0;
+        int64_t sa = 0, sb = 0;
+        for (int k = 0; k < kBlockG / 64; ++k) { base += t3[0][k]; sa += t3[1][k]; sb += t3[2][k]; }
+        if (last_block && threadIdx.x == 0) {
+            const int64_t total = base + bs[b].pairs;
+            hdr->n_pairs = total;
+            hdr->overflow = total > cap ? 1 : 0;
+            hdr->n_support = sa;
+            hdr->n_invalid = sb;
+        }
+    } else {
+        base = bs[blockIdx.x].pairs;  // scanned by k_scan_blocks
+    }
     const int64_t i = (int64_t)blockIdx.x * kBlockG + threadIdx.x;
     const int cnt = i < n_gauss ? counts[i] : 0;
     const int64_t inc = block_inclusive_scan((int64_t)cnt, tmp);
     if (cnt == 0) return;
-    int64_t off = blocksums[blockIdx.x] + inc - cnt;
+    int64_t off = base + inc - cnt;
     const GRec r = recs[i];
     const ImgDev im = imgs[r.img];
     const int tx0 = r.x0 / tile, tx1 = r.x1 / tile;
@@ -360,40 +406,47 @@ inline int blocks_for(int64_t n, int per) { return (int)((n + per - 1) / per); }
 
 }  // namespace
 
-hipError_t launch_setup(const Layout& L, const Ws& w, const ImgDev* host_imgs,
-                        hipStream_t st) {
-    for (int first = 0; first < L.n_img || first == 0; first += kSetupChunk) {
-        const int count = (L.n_img - first) < kSetupChunk ? (L.n_img - first) : kSetupChunk;
-        ImgChunk chunk;
-        for (int k = 0; k < kSetupChunk; ++k) chunk.img[k] = ImgDev{};
-        for (int k = 0; k < count; ++k) chunk.img[k] = host_imgs[first + k];
-        hipLaunchKernelGGL(k_setup, dim3(1), dim3(64), 0, st, chunk, first,
-                           count > 0 ? count : 0, w.imgs, w.hdr, first == 0 ? 1 : 0);
-        if (L.n_img == 0) break;
+hipError_t launch_support(const Layout& L, const Ws& w, const ImgDev* host_imgs,
+                          const float* mean, const float* chol, const float* color,
+                          const float* opacity, const float* radius, bool count_only,
+                          hipStream_t st) {
+    ImgChunk chunk;
+    for (int k = 0; k < kSetupChunk; ++k) chunk.img[k] = ImgDev{};
+    const bool by_value = L.n_img <= kSetupChunk;
+    if (by_value) {
+        for (int k = 0; k < L.n_img; ++k) chunk.img[k] = host_imgs[k];
+    } else {
+        for (int first = 0; first < L.n_img; first += kSetupChunk) {
+            const int count = std::min(kSetupChunk, L.n_img - first);
+            ImgChunk c;
+            for (int k = 0; k < kSetupChunk; ++k) c.img[k] = k < count ? host_imgs[first + k] : ImgDev{};
+            hipLaunchKernelGGL(k_setup, dim3(1), dim3(64), 0, st, c, first, count, w.imgs);
+        }
     }
-    return hipGetLastError();
-}
-
-hipError_t launch_support(const Layout& L, const Ws& w, const float* mean,
-                          const float* chol, const float* color, const float* opacity,
-                          const float* radius, hipStream_t st) {
-    hipLaunchKernelGGL(k_support, dim3(L.nblk_g), dim3(kBlockG), 0, st, w.imgs, L.n_img,
-                       L.n_gauss, L.tile, mean, chol, color, opacity, radius, w.recs,
-                       w.counts, reinterpret_cast<int64_t*>(w.blocksums), w.ranges,
-                       L.n_tiles, reinterpret_cast<float4*>(w.moments), w.hdr);
-    return hipGetLastError();
-}
-
-hipError_t launch_scan(const Layout& L, const Ws& w, hipStream_t st) {
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kBlockG), 0, st,
-                       reinterpret_cast<int64_t*>(w.blocksums), L.nblk_g, L.cap, w.hdr);
+    float4* mom = reinterpret_cast<float4*>(w.moments);
+    if (by_value)
+        hipLaunchKernelGGL(k_support<true>, dim3(L.nblk_g), dim3(kBlockG), 0, st, chunk, w.imgs,
+                           L.n_img, L.n_gauss, L.tile, mean, chol, color, opacity, radius,
+                           w.recs, w.counts, w.blocksums, w.ranges, L.n_tiles, mom);
+    else
+        hipLaunchKernelGGL(k_support<false>, dim3(L.nblk_g), dim3(kBlockG), 0, st, chunk, w.imgs,
+                           L.n_img, L.n_gauss, L.tile, mean, chol, color, opacity, radius,
+                           w.recs, w.counts, w.blocksums, w.ranges, L.n_tiles, mom);
+    if (count_only || L.nblk_g > kFoldScanBlocks)
+        hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kBlockG), 0, st, w.blocksums, L.nblk_g,
+                           L.cap, w.hdr);
     return hipGetLastError();
 }
 
 hipError_t launch_emit(const Layout& L, const Ws& w, hipStream_t st) {
-    hipLaunchKernelGGL(k_emit, dim3(L.nblk_g), dim3(kBlockG), 0, st, w.imgs, w.recs,
-                       w.counts, reinterpret_cast<const int64_t*>(w.blocksums), L.n_gauss,
-                       L.tile, L.cap, w.keys[0], w.vals[0]);
+    if (L.nblk_g > kFoldScanBlocks)
+        hipLaunchKernelGGL(k_emit<false>, dim3(L.nblk_g), dim3(kBlockG), 0, st, w.imgs, w.recs,
+                           w.counts, w.blocksums, L.nblk_g, L.n_gauss, L.tile, L.cap,
+                           w.keys[0], w.vals[0], w.hdr);
+    else
+        hipLaunchKernelGGL(k_emit<true>, dim3(L.nblk_g), dim3(kBlockG), 0, st, w.imgs, w.recs,
+                           w.counts, w.blocksums, L.nblk_g, L.n_gauss, L.tile, L.cap,
+                           w.keys[0], w.vals[0], w.hdr);
     return hipGetLastError();
 }
 

@@ -10,10 +10,12 @@
 
 namespace gs {
 
-constexpr int kSetupChunk = 32;        // images per table-writer launch
+constexpr int kSetupChunk = 32;        // images per table chunk (kernel argument)
+constexpr int kFoldScanBlocks = 2048;  // up to this many Gaussian blocks the
+                                       // emission kernel scans the block sums itself
 constexpr int kBlockG = 256;           // threads of per-Gaussian kernels
 constexpr int kSortThreads = 256;      // radix sort workgroup
-constexpr int kSortItems = 16;         // keys per thread per sort block
+constexpr int kSortItems = 4;          // keys per thread per sort block
 constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
@@ -49,6 +51,13 @@ struct GRec {
 };
 static_assert(sizeof(GRec) == 64, "GRec layout");
 
+// Per-block partial counts written by the support kernel.
+struct BlockSums {
+    int64_t pairs;    // (tile, Gaussian) pairs of the block's Gaussians
+    int64_t support;  // in-support (pixel, Gaussian) pairs
+    int64_t invalid;  // Gaussians flagged for invalid values
+};
+
 // Device counters at the start of the workspace (256 B reserved).
 struct WsHeader {
     int64_t n_pairs;      // pairs the emission produced (may exceed capacity)
@@ -73,7 +82,7 @@ struct Layout {
     int32_t n_passes = 0;     // radix passes over the tile-id bits
     size_t off_header = 0, off_imgs = 0, off_recs = 0, off_counts = 0, off_offsets = 0,
            off_blocksums = 0, off_keys0 = 0, off_vals0 = 0, off_keys1 = 0, off_vals1 = 0,
-           off_hist = 0, off_ranges = 0, off_moments = 0, total = 0;
+           off_hist = 0, off_ranges = 0, off_moments = 0, off_tile_loss = 0, total = 0;
     // buffer holding the sorted result after n_passes ping-pong passes
     size_t sorted_keys() const { return (n_passes & 1) ? off_keys1 : off_keys0; }
     size_t sorted_vals() const { return (n_passes & 1) ? off_vals1 : off_vals0; }
@@ -86,12 +95,13 @@ struct Ws {
     GRec* recs;
     int32_t* counts;
     int32_t* offsets;
-    int32_t* blocksums;
+    BlockSums* blocksums;
     uint32_t* keys[2];
     uint32_t* vals[2];
     int32_t* hist;
     int2* ranges;
     float* moments;
+    double* tile_loss;
 };
 
 inline Ws bind(const Layout& L, void* base) {
@@ -102,7 +112,7 @@ inline Ws bind(const Layout& L, void* base) {
     w.recs = reinterpret_cast<GRec*>(b + L.off_recs);
     w.counts = reinterpret_cast<int32_t*>(b + L.off_counts);
     w.offsets = reinterpret_cast<int32_t*>(b + L.off_offsets);
-    w.blocksums = reinterpret_cast<int32_t*>(b + L.off_blocksums);
+    w.blocksums = reinterpret_cast<BlockSums*>(b + L.off_blocksums);
     w.keys[0] = reinterpret_cast<uint32_t*>(b + L.off_keys0);
     w.vals[0] = reinterpret_cast<uint32_t*>(b + L.off_vals0);
     w.keys[1] = reinterpret_cast<uint32_t*>(b + L.off_keys1);
@@ -110,6 +120,7 @@ inline Ws bind(const Layout& L, void* base) {
     w.hist = reinterpret_cast<int32_t*>(b + L.off_hist);
     w.ranges = reinterpret_cast<int2*>(b + L.off_ranges);
     w.moments = reinterpret_cast<float*>(b + L.off_moments);
+    w.tile_loss = reinterpret_cast<double*>(b + L.off_tile_loss);
     return w;
 }
 
@@ -119,12 +130,13 @@ struct ImgChunk {
 };
 
 // ---- launchers (gs_binning.hip) ------------------------------------------
-hipError_t launch_setup(const Layout& L, const Ws& w, const ImgDev* host_imgs,
-                        hipStream_t st);
-hipError_t launch_support(const Layout& L, const Ws& w, const float* mean,
-                          const float* chol, const float* color, const float* opacity,
-                          const float* radius, hipStream_t st);
-hipError_t launch_scan(const Layout& L, const Ws& w, hipStream_t st);
+// Support boxes and render records (writes the image table too); with
+// `count_only` the block sums are scanned right away so the header holds the
+// pair total (no emission follows).
+hipError_t launch_support(const Layout& L, const Ws& w, const ImgDev* host_imgs,
+                          const float* mean, const float* chol, const float* color,
+                          const float* opacity, const float* radius, bool count_only,
+                          hipStream_t st);
 hipError_t launch_emit(const Layout& L, const Ws& w, hipStream_t st);
 hipError_t launch_sort(const Layout& L, const Ws& w, hipStream_t st);
 hipError_t launch_ranges(const Layout& L, const Ws& w, hipStream_t st);
@@ -133,6 +145,10 @@ hipError_t launch_ranges(const Layout& L, const Ws& w, hipStream_t st);
 hipError_t launch_render_fwd(const Layout& L, const Ws& w, float* out, hipStream_t st);
 hipError_t launch_render_bwd(const Layout& L, const Ws& w, const float* grad_out,
                              hipStream_t st);
+hipError_t launch_render_bwd_l1(const Layout& L, const Ws& w, const float* out,
+                                const float* target, int64_t numel, hipStream_t st);
+hipError_t launch_sum_loss(const Layout& L, const Ws& w, int64_t numel, double* loss,
+                           hipStream_t st);
 hipError_t launch_finalize(const Layout& L, const Ws& w, const float* chol,
                            const float* color, const float* opacity, float* grad_mean,
                            float* grad_chol, float* grad_color, float* grad_opacity,

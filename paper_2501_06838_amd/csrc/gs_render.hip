@@ -172,11 +172,15 @@ __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_fwd(
     }
 }
 
-template <int T>
+// kL1: the upstream gradient is the L1 loss's, sign(out - target) / numel,
+// formed here from the rendered image and the target (it is never stored),
+// and the tile's share of sum |out - target| goes to tile_loss[tile].
+template <int T, bool kL1>
 __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_bwd(
     const ImgDev* __restrict__ imgs, int n_img, const GRec* __restrict__ recs,
     const uint32_t* __restrict__ gids, const int2* __restrict__ ranges,
-    const float* __restrict__ grad_out, float* __restrict__ moments) {
+    const float* __restrict__ grad_out, const float* __restrict__ target, float inv_numel,
+    double* __restrict__ tile_loss, float* __restrict__ moments) {
     using S = TileShape<T>;
     constexpr int NT = S::kThreads, B = S::kBatch;
     __shared__ float4 gt[T * T];     // upstream gradient of the tile, {g0, g1, g2, 0}
@@ -184,7 +188,7 @@ __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_bwd(
     __shared__ float4 sq1[B];        // {g, A0, A1, A2}
     __shared__ int4 sq2[B];          // {first pixel index, box width, area, -}
     __shared__ int pfx[B + 1];
-    __shared__ float acc[B][8];
+    __shared__ float acc[8][B];      // moment-major: lanes flushing different Gaussians hit different banks
     __shared__ int64_t tmp[NT / 64];
 
     const int t = threadIdx.x;
@@ -194,18 +198,43 @@ __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_bwd(
     const int64_t lt = tile - im.tile_base;
     const int px0 = (int)(lt % im.tiles_x) * T, py0 = (int)(lt / im.tiles_x) * T;
     const int2 rg = ranges[tile];
-    if (rg.y <= rg.x) return;  // uniform: nothing listed in this tile
+    if (!kL1 && rg.y <= rg.x) return;  // uniform: nothing listed in this tile
 
     const int64_t plane = (int64_t)im.out_w * im.out_h;
     const float* g = grad_out + im.out_offset;
+    double lsum = 0.0;
     for (int p = t; p < T * T; p += NT) {
         const int x = px0 + (p % T), y = py0 + (p / T);
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
         if (x < im.out_w && y < im.out_h) {
             const int64_t q = (int64_t)y * im.out_w + x;
-            v = make_float4(g[q], g[plane + q], g[2 * plane + q], 0.f);
+            if (kL1) {
+                const float* tg = target + im.out_offset;
+                float gv[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const float d = g[c * plane + q] - tg[c * plane + q];
+                    gv[c] = d > 0.f ? inv_numel : (d < 0.f ? -inv_numel : 0.f);
+                    lsum += fabs((double)g[c * plane + q] - (double)tg[c * plane + q]);
+                }
+                v = make_float4(gv[0], gv[1], gv[2], 0.f);
+            } else {
+                v = make_float4(g[q], g[plane + q], g[2 * plane + q], 0.f);
+            }
         }
         gt[p] = v;
+    }
+    if (kL1) {
+        for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o, 64);
+        __shared__ double lpart[NT / 64];
+        if ((t & 63) == 0) lpart[t >> 6] = lsum;
+        __syncthreads();
+        if (t == 0) {
+            double sum = 0.0;
+            for (int k = 0; k < NT / 64; ++k) sum += lpart[k];
+            tile_loss[tile] = sum;
+        }
+        if (rg.y <= rg.x) return;  // uniform
     }
 
     for (int base = rg.x; base < rg.y; base += B) {
@@ -241,12 +270,18 @@ __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_bwd(
             if (t == NT - 1) pfx[NT] = carry + v;
         }
 #pragma unroll
-        for (int m = 0; m < 8; ++m) acc[t][m] = 0.f;
+        for (int m = 0; m < 8; ++m) acc[m][t] = 0.f;
         __syncthreads();
 
         const int total = pfx[NT];
         const int L = (total + NT - 1) / NT;
         const int j0 = min(t * L, total), j1 = min(j0 + L, total);
+        // Every lane ends with the partial sums of the last Gaussian of its
+        // chunk in m0..m7 (key k); Gaussians finished strictly inside the
+        // chunk are flushed to LDS on the way (at most one lane of a wave
+        // finishes a given Gaussian, so those adds never collide in a wave).
+        int key = 0x7fffffff;  // lanes without pairs: never merged with a Gaussian
+        float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f, m5 = 0.f, m6 = 0.f, m7 = 0.f;
         if (j0 < j1) {
             // staged entry holding flat pair j0: last k with pfx[k] <= j0
             int lo = 0, hi = nb - 1, k = 0;
@@ -263,7 +298,6 @@ __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_bwd(
             int pix = q2.x + ry * T + rx;
             float X = q0.x + (float)rx, Y = q0.y + (float)ry;
             int left = q2.z - r;  // pairs of this Gaussian still to visit
-            float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f, m5 = 0.f, m6 = 0.f, m7 = 0.f;
             for (int j = j0; j < j1; ++j) {
                 const float4 G = gt[pix];
                 const float z1 = q0.z * X;
@@ -290,20 +324,44 @@ __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_bwd(
                     X = q0.x;
                     Y += 1.0f;
                 }
-                if (--left == 0 || j + 1 == j1) {
-                    float* a = acc[k];
-                    atomicAdd(&a[0], m0); atomicAdd(&a[1], m1); atomicAdd(&a[2], m2);
-                    atomicAdd(&a[3], m3); atomicAdd(&a[4], m4); atomicAdd(&a[5], m5);
-                    atomicAdd(&a[6], m6); atomicAdd(&a[7], m7);
+                if (--left == 0 && j + 1 < j1) {
+                    atomicAdd(&acc[0][k], m0); atomicAdd(&acc[1][k], m1);
+                    atomicAdd(&acc[2][k], m2); atomicAdd(&acc[3][k], m3);
+                    atomicAdd(&acc[4][k], m4); atomicAdd(&acc[5][k], m5);
+                    atomicAdd(&acc[6][k], m6); atomicAdd(&acc[7][k], m7);
                     m0 = m1 = m2 = m3 = m4 = m5 = m6 = m7 = 0.f;
-                    if (j + 1 < j1) {
-                        do { ++k; } while (k < nb - 1 && sq2[k].z == 0);
-                        q0 = sq0[k]; q1 = sq1[k]; q2 = sq2[k];
-                        rx = 0; ry = 0; pix = q2.x;
-                        X = q0.x; Y = q0.y;
-                        left = q2.z;
-                    }
+                    do { ++k; } while (k < nb - 1 && sq2[k].z == 0);
+                    q0 = sq0[k]; q1 = sq1[k]; q2 = sq2[k];
+                    rx = 0; ry = 0; pix = q2.x;
+                    X = q0.x; Y = q0.y;
+                    left = q2.z;
                 }
+            }
+            key = k;
+        }
+        // Chunk ends: lanes sharing a last Gaussian are contiguous in the wave
+        // (keys ascend with the lane), so a segmented suffix sum leaves each
+        // segment's total in its first lane, which alone adds it to LDS.
+        {
+            const int lane = t & 63;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int kk = __shfl_down(key, o, 64);
+                const float v0 = __shfl_down(m0, o, 64), v1 = __shfl_down(m1, o, 64);
+                const float v2 = __shfl_down(m2, o, 64), v3 = __shfl_down(m3, o, 64);
+                const float v4 = __shfl_down(m4, o, 64), v5 = __shfl_down(m5, o, 64);
+                const float v6 = __shfl_down(m6, o, 64), v7 = __shfl_down(m7, o, 64);
+                if (lane + o < 64 && kk == key) {
+                    m0 += v0; m1 += v1; m2 += v2; m3 += v3;
+                    m4 += v4; m5 += v5; m6 += v6; m7 += v7;
+                }
+            }
+            const int kprev = __shfl_up(key, 1, 64);
+            if (j0 < j1 && (lane == 0 || kprev != key)) {
+                atomicAdd(&acc[0][key], m0); atomicAdd(&acc[1][key], m1);
+                atomicAdd(&acc[2][key], m2); atomicAdd(&acc[3][key], m3);
+                atomicAdd(&acc[4][key], m4); atomicAdd(&acc[5][key], m5);
+                atomicAdd(&acc[6][key], m6); atomicAdd(&acc[7][key], m7);
             }
         }
         __syncthreads();
@@ -311,7 +369,7 @@ __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_bwd(
             float* dst = moments + (int64_t)my_gid * 8;
 #pragma unroll
             for (int m = 0; m < 8; ++m) {
-                const float v = acc[t][m];
+                const float v = acc[m][t];
                 if (v != 0.f) atomicAdd(dst + m, v);
             }
         }
@@ -403,9 +461,33 @@ __global__ __launch_bounds__(kBlockG) void k_l1(const float* __restrict__ img,
     }
 }
 
+// One workgroup: mean of the per-tile L1 partial sums.
+__global__ __launch_bounds__(1024) void k_sum_loss(const double* __restrict__ tile_loss,
+                                                   int64_t n_tiles, double inv_numel,
+                                                   double* __restrict__ loss) {
+    __shared__ double part[1024 / 64];
+    double s = 0.0;
+    for (int64_t t = threadIdx.x; t < n_tiles; t += 1024) s += tile_loss[t];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sum = 0.0;
+        for (int k = 0; k < 1024 / 64; ++k) sum += part[k];
+        *loss = sum * inv_numel;
+    }
+}
+
 inline int blocks_for(int64_t n, int per) { return (int)((n + per - 1) / per); }
 
 }  // namespace
+
+hipError_t launch_sum_loss(const Layout& L, const Ws& w, int64_t numel, double* loss,
+                           hipStream_t st) {
+    hipLaunchKernelGGL(k_sum_loss, dim3(1), dim3(1024), 0, st, w.tile_loss, L.n_tiles,
+                       1.0 / (double)numel, loss);
+    return hipGetLastError();
+}
 
 hipError_t launch_render_fwd(const Layout& L, const Ws& w, float* out, hipStream_t st) {
     const uint32_t* gids = (L.n_passes & 1) ? w.vals[1] : w.vals[0];
@@ -429,27 +511,41 @@ hipError_t launch_render_fwd(const Layout& L, const Ws& w, float* out, hipStream
     return hipGetLastError();
 }
 
-hipError_t launch_render_bwd(const Layout& L, const Ws& w, const float* grad_out,
-                             hipStream_t st) {
+template <bool kL1>
+static hipError_t launch_bwd_t(const Layout& L, const Ws& w, const float* grad_out,
+                               const float* target, float inv_numel, hipStream_t st) {
     const uint32_t* gids = (L.n_passes & 1) ? w.vals[1] : w.vals[0];
     const dim3 grid((unsigned)L.n_tiles);
     switch (L.tile) {
         case 8:
-            hipLaunchKernelGGL(k_render_bwd<8>, grid, dim3(TileShape<8>::kThreads), 0, st,
-                               w.imgs, L.n_img, w.recs, gids, w.ranges, grad_out, w.moments);
+            hipLaunchKernelGGL((k_render_bwd<8, kL1>), grid, dim3(TileShape<8>::kThreads), 0, st,
+                               w.imgs, L.n_img, w.recs, gids, w.ranges, grad_out, target,
+                               inv_numel, w.tile_loss, w.moments);
             break;
         case 16:
-            hipLaunchKernelGGL(k_render_bwd<16>, grid, dim3(TileShape<16>::kThreads), 0, st,
-                               w.imgs, L.n_img, w.recs, gids, w.ranges, grad_out, w.moments);
+            hipLaunchKernelGGL((k_render_bwd<16, kL1>), grid, dim3(TileShape<16>::kThreads), 0, st,
+                               w.imgs, L.n_img, w.recs, gids, w.ranges, grad_out, target,
+                               inv_numel, w.tile_loss, w.moments);
             break;
         case 32:
-            hipLaunchKernelGGL(k_render_bwd<32>, grid, dim3(TileShape<32>::kThreads), 0, st,
-                               w.imgs, L.n_img, w.recs, gids, w.ranges, grad_out, w.moments);
+            hipLaunchKernelGGL((k_render_bwd<32, kL1>), grid, dim3(TileShape<32>::kThreads), 0, st,
+                               w.imgs, L.n_img, w.recs, gids, w.ranges, grad_out, target,
+                               inv_numel, w.tile_loss, w.moments);
             break;
         default:
             return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_render_bwd(const Layout& L, const Ws& w, const float* grad_out,
+                             hipStream_t st) {
+    return launch_bwd_t<false>(L, w, grad_out, nullptr, 0.f, st);
+}
+
+hipError_t launch_render_bwd_l1(const Layout& L, const Ws& w, const float* out,
+                                const float* target, int64_t numel, hipStream_t st) {
+    return launch_bwd_t<true>(L, w, out, target, (float)(1.0 / (double)numel), st);
 }
 
 hipError_t launch_finalize(const Layout& L, const Ws& w, const float* chol,
@@ -466,8 +562,10 @@ hipError_t launch_finalize(const Layout& L, const Ws& w, const float* chol,
 hipError_t launch_l1(const float* img, const float* target, int64_t numel, float* grad,
                      double* loss_sum, hipStream_t st) {
     if (numel == 0) return hipSuccess;
-    int nb = blocks_for(numel, kBlockG * 8);
-    if (nb > 4096) nb = 4096;
+    // at most 256 workgroups: each adds one double to *loss_sum, and atomics
+    // on a single address serialise
+    int nb = blocks_for(numel, kBlockG * 4);
+    if (nb > 256) nb = 256;
     hipLaunchKernelGGL(k_l1, dim3(nb), dim3(kBlockG), 0, st, img, target, numel, grad,
                        loss_sum);
     return hipGetLastError();

@@ -192,6 +192,42 @@ class RasterPlan:
                                                   _ptr(grad_out), _stream(stream)),
                 "render backward")
 
+    def render_backward_l1(self, workspace, out, target, stream=None, capacity=None):
+        """Backward render for the L1 loss against `target` (fused gradient)."""
+        cfg = self.config(capacity)
+        N.check(N.lib().gs_raster_render_backward_l1(ctypes.byref(cfg), self._arr,
+                                                     len(self.images), self.n_gauss,
+                                                     _ptr(workspace), workspace.numel(),
+                                                     _ptr(out), _ptr(target), _stream(stream)),
+                "render backward l1")
+
+    def l1_loss_value(self, workspace, loss, stream=None, capacity=None):
+        """Mean L1 loss of the last fused backward into `loss` (0-d float64 tensor)."""
+        cfg = self.config(capacity)
+        N.check(N.lib().gs_l1_loss_value(ctypes.byref(cfg), self._arr, len(self.images),
+                                         self.n_gauss, _ptr(workspace), workspace.numel(),
+                                         _ptr(loss), _stream(stream)), "l1 loss value")
+
+    def backward_l1(self, chol, color, opacity, workspace, out, target, grads=None, loss=None,
+                    stream=None, capacity=None):
+        """Training-step backward for the L1 loss: gradients (and the loss)."""
+        n = self.n_gauss
+        _check_param(out, "out", (self.out_numel,))
+        _check_param(target, "target", (self.out_numel,))
+        if grads is None:
+            dev = out.device
+            grads = (torch.empty(n, 2, device=dev), torch.empty(n, 3, device=dev),
+                     torch.empty(n, 3, device=dev), torch.empty(n, device=dev))
+        gm, gc, gcol, gop = grads
+        cfg = self.config(capacity)
+        N.check(N.lib().gs_raster_backward_l1(ctypes.byref(cfg), self._arr, len(self.images),
+                                              _ptr(chol), _ptr(color), _ptr(opacity), n,
+                                              _ptr(workspace), workspace.numel(), _ptr(out),
+                                              _ptr(target), _ptr(gm), _ptr(gc), _ptr(gcol),
+                                              _ptr(gop), _ptr(loss), _stream(stream)),
+                "backward l1")
+        return grads
+
     def gradients(self, chol, color, opacity, workspace, grads, stream=None, capacity=None):
         gm, gc, gcol, gop = grads
         cfg = self.config(capacity)
