@@ -121,15 +121,10 @@ def main():
     ws = plan.new_workspace(dev)
     out = plan.new_output(dev)
     target = plan.pack([t(x) for x in wl.target])
-    grad_img = torch.empty_like(out)
     loss_acc = torch.zeros((), dtype=torch.float64, device=dev)
     grads = (torch.empty(wl.n_gauss, 2, device=dev), torch.empty(wl.n_gauss, 3, device=dev),
              torch.empty(wl.n_gauss, 3, device=dev), torch.empty(wl.n_gauss, device=dev))
-    from paper_2501_06838_amd import _native as N
-    import ctypes
-    lib = N.lib()
     stream = torch.cuda.current_stream()
-    sp = ctypes.c_void_p(stream.cuda_stream)
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
 
     def step(e=None):
@@ -137,14 +132,11 @@ def main():
         if e: e[0].record(stream)
         plan.render(ws, out)
         if e: e[1].record(stream)
-        N.check(lib.gs_l1_loss_grad(ctypes.c_void_p(out.data_ptr()),
-                                    ctypes.c_void_p(target.data_ptr()), out.numel(),
-                                    ctypes.c_void_p(grad_img.data_ptr()),
-                                    ctypes.c_void_p(loss_acc.data_ptr()), sp), "l1")
         if e: e[2].record(stream)
-        plan.render_backward(ws, grad_img)
+        plan.render_backward_l1(ws, out, target)   # L1 gradient formed per tile
         if e: e[3].record(stream)
         plan.gradients(chol, color, opacity, ws, grads)
+        plan.l1_loss_value(ws, loss_acc)
 
     for _ in range(args.warmup):
         step()
@@ -170,7 +162,7 @@ def main():
     fwd_tflops = n_support * FLOPEQ_FWD / (fwd_ms * 1e-3) / 1e12
     bwd_tflops = n_support * FLOPEQ_BWD / (bwd_ms * 1e-3) / 1e12
     roofline = {
-        "bound": "alu", "kernel": "k_render_bwd", "achieved": round(bwd_tflops, 3),
+        "bound": "alu", "kernel": "k_render_bwd (fused L1 gradient)", "achieved": round(bwd_tflops, 3),
         "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
         "frac": round(bwd_tflops / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": None,
         "per_launch_flopeq": n_support * FLOPEQ_BWD, "avg_launch_us": round(bwd_ms * 1e3, 2),

@@ -84,7 +84,10 @@ typedef struct {
 } gs_config;
 
 /* flags */
-#define GS_FLAG_PERSISTENT 0x1 /* render with persistent work-queue kernels  */
+#define GS_FLAG_PERSISTENT 0x1   /* render with persistent work-queue kernels */
+#define GS_FLAG_ATOMIC_GRADS 0x2 /* backward: one FP32 global atomic per (tile,
+                                    Gaussian, sum) instead of per-pair partial
+                                    sums reduced in a fixed order (default)    */
 
 /* ABI version of the loaded library (GS_ABI_VERSION). */
 int32_t gs_abi_version(void);
@@ -233,6 +236,34 @@ gs_status gs_tile_lists(const gs_config* cfg, const gs_image* images, int32_t n_
                         int64_t n_gauss, const void* workspace, size_t ws_bytes,
                         int32_t* ranges_host, int32_t* gids_host, int64_t max_pairs,
                         int64_t* n_tiles_out, int64_t* n_pairs_out, void* stream);
+
+/* ---- graph capture (HIP graphs) ---------------------------------------- */
+
+/* Opaque executable graph of one whole pass over a fixed batch layout and
+ * fixed device pointers. */
+typedef struct gs_graph_s* gs_graph;
+
+/* Captures, on a private stream, gs_raster_forward followed (when target is
+ * not NULL) by gs_raster_backward_l1 with the same arguments, and
+ * instantiates the result: replaying it runs the whole training step (or
+ * forward pass) with one launch.  Kernel arguments, including the image
+ * table, are baked in; the pointed-to device data is read at replay time, so
+ * the caller may update the Gaussians in place between replays.  The pair
+ * capacity must hold for every replay (check gs_diagnostics).  Arguments as
+ * for gs_raster_forward / gs_raster_backward_l1.  No memset nodes are used.
+ * The graph owns host resources only; destroy it with gs_graph_destroy. */
+gs_status gs_graph_create(const gs_config* cfg, const gs_image* images, int32_t n_img,
+                          const float* mean, const float* chol, const float* color,
+                          const float* opacity, const float* radius, int64_t n_gauss,
+                          void* workspace, size_t ws_bytes, float* out, const float* target,
+                          float* grad_mean, float* grad_chol, float* grad_color,
+                          float* grad_opacity, double* loss, gs_graph* graph);
+
+/* Enqueues one replay on stream. */
+gs_status gs_graph_launch(gs_graph graph, void* stream);
+
+/* Releases the graph (NULL is a no-op). */
+gs_status gs_graph_destroy(gs_graph graph);
 
 #ifdef __cplusplus
 }

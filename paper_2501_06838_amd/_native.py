@@ -20,13 +20,15 @@ GS_E_UNSUPPORTED = -4
 GS_E_WORKSPACE = -5
 
 GS_FLAG_PERSISTENT = 0x1
+GS_FLAG_ATOMIC_GRADS = 0x2
 
 EXPORTED = (
     "gs_abi_version", "gs_status_string", "gs_output_size", "gs_workspace_size",
     "gs_raster_forward", "gs_raster_backward", "gs_l1_loss_grad", "gs_diagnostics",
     "gs_count_pairs", "gs_tile_lists", "gs_raster_bin", "gs_raster_render",
     "gs_raster_render_backward", "gs_raster_gradients", "gs_raster_render_backward_l1",
-    "gs_l1_loss_value", "gs_raster_backward_l1",
+    "gs_l1_loss_value", "gs_raster_backward_l1", "gs_graph_create", "gs_graph_launch",
+    "gs_graph_destroy",
 )
 
 
@@ -108,6 +110,14 @@ def lib():
         L.gs_raster_backward_l1.argtypes = [_cfgp, _imgp, _i32, _vp, _vp, _vp, _i64, _vp, _sz,
                                             _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
         L.gs_raster_backward_l1.restype = _i32
+        L.gs_graph_create.argtypes = [_cfgp, _imgp, _i32, _vp, _vp, _vp, _vp, _vp, _i64, _vp,
+                                      _sz, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                      ctypes.POINTER(_vp)]
+        L.gs_graph_create.restype = _i32
+        L.gs_graph_launch.argtypes = [_vp, _vp]
+        L.gs_graph_launch.restype = _i32
+        L.gs_graph_destroy.argtypes = [_vp]
+        L.gs_graph_destroy.restype = _i32
         if L.gs_abi_version() != 1:
             raise ImportError("libgsraster ABI version mismatch")
         _lib = L

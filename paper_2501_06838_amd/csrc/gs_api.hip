@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <new>
 #include <vector>
 
 #include "gs_internal.h"
@@ -90,7 +91,7 @@ gs_status make_layout(const gs_config* cfg, const gs_image* images, int32_t n_im
     l.off_imgs = off; off = align_up(off + sizeof(ImgDev) * (size_t)n_img);
     l.off_recs = off; off = align_up(off + sizeof(GRec) * (size_t)n_gauss);
     l.off_counts = off; off = align_up(off + sizeof(int32_t) * (size_t)n_gauss);
-    l.off_offsets = off;
+    l.off_offsets = off; off = align_up(off + sizeof(int32_t) * (size_t)n_gauss);
     l.off_blocksums = off; off = align_up(off + sizeof(BlockSums) * (size_t)l.nblk_g);
     l.off_ranges = off; off = align_up(off + sizeof(int2) * (size_t)tiles);
     l.off_moments = off; off = align_up(off + sizeof(float) * 8 * (size_t)n_gauss);
@@ -100,7 +101,11 @@ gs_status make_layout(const gs_config* cfg, const gs_image* images, int32_t n_im
     l.off_keys1 = off; off = align_up(off + sizeof(uint32_t) * (size_t)cap);
     l.off_vals1 = off; off = align_up(off + sizeof(uint32_t) * (size_t)cap);
     l.off_hist = off; off = align_up(off + sizeof(int32_t) * ((size_t)kRadix * l.nblk_sort + kRadix));
+    l.off_pairs = off; off = align_up(off + sizeof(PairRec) * (size_t)cap);
+    l.off_inv = off; off = align_up(off + sizeof(uint32_t) * (size_t)cap);
+    l.off_partials = off; off = align_up(off + sizeof(float) * 8 * (size_t)cap);
     l.total = off;
+    l.host_imgs = table->data();
     *L = l;
     return GS_OK;
 }
@@ -347,6 +352,81 @@ gs_status gs_count_pairs(const gs_config* cfg, const gs_image* images, int32_t n
     GS_TRY(dev(hipStreamSynchronize(st)));
     *n_pairs = h.n_pairs;
     return GS_OK;
+}
+
+struct gs_graph_s {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+gs_status gs_graph_create(const gs_config* cfg, const gs_image* images, int32_t n_img,
+                          const float* mean, const float* chol, const float* color,
+                          const float* opacity, const float* radius, int64_t n_gauss,
+                          void* workspace, size_t ws_bytes, float* out, const float* target,
+                          float* grad_mean, float* grad_chol, float* grad_color,
+                          float* grad_opacity, double* loss, gs_graph* graph_out) {
+    if (!graph_out) return GS_E_INVALID;
+    *graph_out = nullptr;
+    // validate everything before capturing (a failed call inside a capture
+    // would leave the capture half-built)
+    Layout L;
+    std::vector<ImgDev> table;
+    GS_TRY(make_layout(cfg, images, n_img, n_gauss, &L, &table));
+    GS_TRY(check_gauss_ptrs(n_gauss, mean, chol, color, opacity));
+    if (!out) return GS_E_INVALID;
+    if (target && n_gauss > 0 && (!grad_mean || !grad_chol || !grad_color || !grad_opacity))
+        return GS_E_INVALID;
+    if (!workspace || ws_bytes < L.total) return GS_E_WORKSPACE;
+
+    hipStream_t cs;
+    GS_TRY(dev(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)));
+    gs_status st = GS_OK;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        hipStreamDestroy(cs);
+        return GS_E_DEVICE;
+    }
+    st = gs_raster_forward(cfg, images, n_img, mean, chol, color, opacity, radius, n_gauss,
+                           workspace, ws_bytes, out, cs);
+    if (st == GS_OK && target)
+        st = gs_raster_backward_l1(cfg, images, n_img, chol, color, opacity, n_gauss, workspace,
+                                   ws_bytes, out, target, grad_mean, grad_chol, grad_color,
+                                   grad_opacity, loss, cs);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(cs, &g);
+    hipStreamDestroy(cs);
+    if (st != GS_OK || ec != hipSuccess || !g) {
+        if (g) hipGraphDestroy(g);
+        return st != GS_OK ? st : GS_E_DEVICE;
+    }
+    hipGraphExec_t ex = nullptr;
+    if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+        hipGraphDestroy(g);
+        return GS_E_DEVICE;
+    }
+    gs_graph h = new (std::nothrow) gs_graph_s;
+    if (!h) {
+        hipGraphExecDestroy(ex);
+        hipGraphDestroy(g);
+        return GS_E_DEVICE;
+    }
+    h->graph = g;
+    h->exec = ex;
+    *graph_out = h;
+    return GS_OK;
+}
+
+gs_status gs_graph_launch(gs_graph graph, void* stream) {
+    if (!graph || !graph->exec) return GS_E_INVALID;
+    return dev(hipGraphLaunch(graph->exec, static_cast<hipStream_t>(stream)));
+}
+
+gs_status gs_graph_destroy(gs_graph graph) {
+    if (!graph) return GS_OK;
+    hipError_t e1 = hipSuccess, e2 = hipSuccess;
+    if (graph->exec) e1 = hipGraphExecDestroy(graph->exec);
+    if (graph->graph) e2 = hipGraphDestroy(graph->graph);
+    delete graph;
+    return (e1 == hipSuccess && e2 == hipSuccess) ? GS_OK : GS_E_DEVICE;
 }
 
 gs_status gs_tile_lists(const gs_config* cfg, const gs_image* images, int32_t n_img,

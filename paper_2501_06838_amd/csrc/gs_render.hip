@@ -23,7 +23,8 @@ namespace gs {
 
 namespace {
 
-__device__ __forceinline__ int tile_image(const ImgDev* imgs, int n_img, int64_t tile) {
+template <typename Table>
+__device__ __forceinline__ int tile_image(const Table& imgs, int n_img, int64_t tile) {
     int lo = 0, hi = n_img - 1, ans = 0;
     while (lo <= hi) {
         const int mid = (lo + hi) >> 1;
@@ -51,18 +52,25 @@ struct TileShape {
     static constexpr int kBatch = kThreads;
 };
 
+// Gaussians staged per forward round: the per-block lists hold a 48-byte
+// record per (8x8 block, Gaussian), NB * kFwdBatch of them in LDS.
 template <int T>
+struct FwdShape {
+    static constexpr int kBatch = T == 8 ? 64 : (T == 16 ? 128 : 32);
+};
+
+template <int T, typename Table>
 __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_fwd(
-    const ImgDev* __restrict__ imgs, int n_img, const GRec* __restrict__ recs,
-    const uint32_t* __restrict__ gids, const int2* __restrict__ ranges,
-    float* __restrict__ out) {
+    Table imgs, int n_img, const PairRec* __restrict__ pairs,
+    const int2* __restrict__ ranges, float* __restrict__ out) {
     using S = TileShape<T>;
-    constexpr int NB = S::kBlocks, B = S::kBatch;
-    __shared__ float4 sp0[B];          // {x-origin minus kx, y-origin minus ky, fx, fy}
-    __shared__ float4 sp1[B];          // {a, e, g, A0}
-    __shared__ float2 sp2[B];          // {A1, A2}
-    __shared__ uint64_t smask[NB][B];  // compacted lane masks per 8x8 block
-    __shared__ uint16_t slist[NB][B];  // compacted staged indices per block
+    constexpr int NB = S::kBlocks, B = FwdShape<T>::kBatch;
+    // per 8x8 block j, compacted in ascending Gaussian order:
+    //   l0 = {X origin of the block minus kx, same for Y, fx, fy}
+    //   l1 = {a, e, g, A0},  l2 = {A1, A2, lane mask lo, lane mask hi}
+    __shared__ float4 l0[NB][B];
+    __shared__ float4 l1[NB][B];
+    __shared__ float4 l2[NB][B];
     __shared__ int scount[NB];
     __shared__ int wcount[S::kWaves][NB];
 
@@ -74,28 +82,21 @@ __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_fwd(
     const int px0 = (int)(lt % im.tiles_x) * T, py0 = (int)(lt / im.tiles_x) * T;
     const int2 rg = ranges[tile];
 
+    const float lxf = (float)(lane & 7), lyf = (float)(lane >> 3);
     float acc[S::kBlocksPerWave][3];
-    float dxf[S::kBlocksPerWave], dyf[S::kBlocksPerWave];
 #pragma unroll
-    for (int m = 0; m < S::kBlocksPerWave; ++m) {
-        const int j = wave + S::kWaves * m;
-        dxf[m] = (float)((j % S::kBlocksX) * 8 + (lane & 7));
-        dyf[m] = (float)((j / S::kBlocksX) * 8 + (lane >> 3));
-        acc[m][0] = acc[m][1] = acc[m][2] = 0.f;
-    }
+    for (int m = 0; m < S::kBlocksPerWave; ++m) acc[m][0] = acc[m][1] = acc[m][2] = 0.f;
 
     for (int base = rg.x; base < rg.y; base += B) {
         const int nb = min(B, rg.y - base);
+        PairRec r;
         uint64_t my_mask[NB];
 #pragma unroll
         for (int j = 0; j < NB; ++j) my_mask[j] = 0;
         if (t < nb) {
-            const GRec r = recs[gids[base + t]];
-            const int lx0 = max(r.x0 - px0, 0), lx1 = min(r.x1 - px0, T - 1);
-            const int ly0 = max(r.y0 - py0, 0), ly1 = min(r.y1 - py0, T - 1);
-            sp0[t] = make_float4((float)(px0 - r.kx), (float)(py0 - r.ky), r.fx, r.fy);
-            sp1[t] = make_float4(r.a, r.e, r.g, r.A[0]);
-            sp2[t] = make_float2(r.A[1], r.A[2]);
+            r = pairs[base + t];
+            const int lx0 = r.box & 255, lx1 = (r.box >> 8) & 255;
+            const int ly0 = (r.box >> 16) & 255, ly1 = r.box >> 24;
 #pragma unroll
             for (int j = 0; j < NB; ++j) {
                 const int bx = (j % S::kBlocksX) * 8, by = (j / S::kBlocksX) * 8;
@@ -120,8 +121,11 @@ __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_fwd(
             if (my_mask[j] != 0) {
                 int pos = __popcll(bal & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
                 for (int w = 0; w < wave; ++w) pos += wcount[w][j];
-                slist[j][pos] = (uint16_t)t;
-                smask[j][pos] = my_mask[j];
+                const int bx = (j % S::kBlocksX) * 8, by = (j / S::kBlocksX) * 8;
+                l0[j][pos] = make_float4(r.kxr + (float)bx, r.kyr + (float)by, r.fx, r.fy);
+                l1[j][pos] = make_float4(r.a, r.e, r.g, r.A[0]);
+                l2[j][pos] = make_float4(r.A[1], r.A[2], __uint_as_float((uint32_t)my_mask[j]),
+                                         __uint_as_float((uint32_t)(my_mask[j] >> 32)));
             }
         }
         if (t < NB) {
@@ -135,24 +139,25 @@ __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_fwd(
         for (int m = 0; m < S::kBlocksPerWave; ++m) {
             const int j = wave + S::kWaves * m;
             const int cnt = scount[j];
+            if (cnt == 0) continue;
+            // records are read one iteration ahead (fixed stride, no indirection)
+            float4 a0 = l0[j][0], a1 = l1[j][0], a2 = l2[j][0];
             for (int q = 0; q < cnt; ++q) {
-                const int k = __builtin_amdgcn_readfirstlane(slist[j][q]);
-                const uint64_t mk = smask[j][q];
-                const uint32_t mlo = __builtin_amdgcn_readfirstlane((uint32_t)mk);
-                const uint32_t mhi = __builtin_amdgcn_readfirstlane((uint32_t)(mk >> 32));
+                const float4 c0 = a0, c1 = a1, c2 = a2;
+                const int qn = q + 1 < cnt ? q + 1 : q;
+                a0 = l0[j][qn]; a1 = l1[j][qn]; a2 = l2[j][qn];
+                const uint32_t mlo = __builtin_amdgcn_readfirstlane(__float_as_uint(c2.z));
+                const uint32_t mhi = __builtin_amdgcn_readfirstlane(__float_as_uint(c2.w));
                 const uint64_t mask = ((uint64_t)mhi << 32) | mlo;
-                const float4 p0 = sp0[k];
-                const float4 p1 = sp1[k];
-                const float2 p2 = sp2[k];
-                const float X = (p0.x + dxf[m]) - p0.z;
-                const float Y = (p0.y + dyf[m]) - p0.w;
-                const float z1 = p1.x * X;
-                const float z2 = p1.y * Y - p1.z * X;
+                const float X = (c0.x + lxf) - c0.z;
+                const float Y = (c0.y + lyf) - c0.w;
+                const float z1 = c1.x * X;
+                const float z2 = c1.y * Y - c1.z * X;
                 float w = fast_exp2(-(z1 * z1 + z2 * z2));
                 w = __builtin_amdgcn_inverse_ballot_w64(mask) ? w : 0.f;
-                acc[m][0] += p1.w * w;
-                acc[m][1] += p2.x * w;
-                acc[m][2] += p2.y * w;
+                acc[m][0] += c1.w * w;
+                acc[m][1] += c2.x * w;
+                acc[m][2] += c2.y * w;
             }
         }
         __syncthreads();
@@ -162,7 +167,9 @@ __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_fwd(
     float* o = out + im.out_offset;
 #pragma unroll
     for (int m = 0; m < S::kBlocksPerWave; ++m) {
-        const int x = px0 + (int)dxf[m], y = py0 + (int)dyf[m];
+        const int j = wave + S::kWaves * m;
+        const int x = px0 + (j % S::kBlocksX) * 8 + (lane & 7);
+        const int y = py0 + (j / S::kBlocksX) * 8 + (lane >> 3);
         if (x < im.out_w && y < im.out_h) {
             const int64_t p = (int64_t)y * im.out_w + x;
             o[p] = acc[m][0];
@@ -175,12 +182,12 @@ __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_fwd(
 // kL1: the upstream gradient is the L1 loss's, sign(out - target) / numel,
 // formed here from the rendered image and the target (it is never stored),
 // and the tile's share of sum |out - target| goes to tile_loss[tile].
-template <int T, bool kL1>
+template <int T, bool kL1, typename Table>
 __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_bwd(
-    const ImgDev* __restrict__ imgs, int n_img, const GRec* __restrict__ recs,
-    const uint32_t* __restrict__ gids, const int2* __restrict__ ranges,
-    const float* __restrict__ grad_out, const float* __restrict__ target, float inv_numel,
-    double* __restrict__ tile_loss, float* __restrict__ moments) {
+    Table imgs, int n_img, const PairRec* __restrict__ pairs,
+    const int2* __restrict__ ranges, const float* __restrict__ grad_out,
+    const float* __restrict__ target, float inv_numel, double* __restrict__ tile_loss,
+    float* __restrict__ moments, float4* __restrict__ partials, int atomic_grads) {
     using S = TileShape<T>;
     constexpr int NT = S::kThreads, B = S::kBatch;
     __shared__ float4 gt[T * T];     // upstream gradient of the tile, {g0, g1, g2, 0}
@@ -242,14 +249,14 @@ __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_bwd(
         uint32_t my_gid = 0;
         int area = 0;
         if (t < nb) {
-            my_gid = gids[base + t];
-            const GRec r = recs[my_gid];
-            const int lx0 = max(r.x0 - px0, 0), lx1 = min(r.x1 - px0, T - 1);
-            const int ly0 = max(r.y0 - py0, 0), ly1 = min(r.y1 - py0, T - 1);
+            const PairRec r = pairs[base + t];
+            my_gid = r.gid;
+            const int lx0 = r.box & 255, lx1 = (r.box >> 8) & 255;
+            const int ly0 = (r.box >> 16) & 255, ly1 = r.box >> 24;
             const int w = lx1 - lx0 + 1, h = ly1 - ly0 + 1;
-            area = (r.pad == 0) ? w * h : 0;  // dead Gaussians get nothing
-            const float X0 = (float)(px0 + lx0 - r.kx) - r.fx;
-            const float Y0 = (float)(py0 + ly0 - r.ky) - r.fy;
+            area = w * h;  // a dead Gaussian has zero amplitudes; its gradients are discarded
+            const float X0 = (r.kxr + (float)lx0) - r.fx;
+            const float Y0 = (r.kyr + (float)ly0) - r.fy;
             sq0[t] = make_float4(X0, Y0, r.a, r.e);
             sq1[t] = make_float4(r.g, r.A[0], r.A[1], r.A[2]);
             sq2[t] = make_int4(ly0 * T + lx0, w, area, 0);
@@ -284,22 +291,25 @@ __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_bwd(
         float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f, m5 = 0.f, m6 = 0.f, m7 = 0.f;
         if (j0 < j1) {
             // staged entry holding flat pair j0: last k with pfx[k] <= j0
+            // (every entry has a positive area, so it is unique)
             int lo = 0, hi = nb - 1, k = 0;
             while (lo <= hi) {
                 const int mid = (lo + hi) >> 1;
                 if (pfx[mid] <= j0) { k = mid; lo = mid + 1; } else { hi = mid - 1; }
             }
-            // skip empty entries (area 0) sharing the prefix (bounded by nb)
-            while (k < nb - 1 && sq2[k].z == 0) ++k;
             float4 q0 = sq0[k], q1 = sq1[k];
             int4 q2 = sq2[k];
+            // parameters of the next entry, loaded ahead of the switch
+            const int kn = k + 1 < nb ? k + 1 : k;
+            float4 n0 = sq0[kn], n1 = sq1[kn];
+            int4 n2 = sq2[kn];
             int r = j0 - pfx[k];
             int ry = r / q2.y, rx = r - ry * q2.y;
             int pix = q2.x + ry * T + rx;
             float X = q0.x + (float)rx, Y = q0.y + (float)ry;
             int left = q2.z - r;  // pairs of this Gaussian still to visit
+            float4 G = gt[pix];
             for (int j = j0; j < j1; ++j) {
-                const float4 G = gt[pix];
                 const float z1 = q0.z * X;
                 const float z2 = q0.w * Y - q1.x * X;
                 const float w = fast_exp2(-(z1 * z1 + z2 * z2));
@@ -330,12 +340,15 @@ __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_bwd(
                     atomicAdd(&acc[4][k], m4); atomicAdd(&acc[5][k], m5);
                     atomicAdd(&acc[6][k], m6); atomicAdd(&acc[7][k], m7);
                     m0 = m1 = m2 = m3 = m4 = m5 = m6 = m7 = 0.f;
-                    do { ++k; } while (k < nb - 1 && sq2[k].z == 0);
-                    q0 = sq0[k]; q1 = sq1[k]; q2 = sq2[k];
+                    ++k;
+                    q0 = n0; q1 = n1; q2 = n2;
+                    const int k2 = k + 1 < nb ? k + 1 : k;
+                    n0 = sq0[k2]; n1 = sq1[k2]; n2 = sq2[k2];
                     rx = 0; ry = 0; pix = q2.x;
                     X = q0.x; Y = q0.y;
                     left = q2.z;
                 }
+                G = gt[min(pix, T * T - 1)];  // next pair's gradient (clamped past the last)
             }
             key = k;
         }
@@ -365,12 +378,21 @@ __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_bwd(
             }
         }
         __syncthreads();
-        if (t < nb && area > 0) {
-            float* dst = moments + (int64_t)my_gid * 8;
+        if (t < nb) {
+            if (atomic_grads) {
+                // one FP32 global atomic per (tile, Gaussian, sum)
+                float* dst = moments + (int64_t)my_gid * 8;
 #pragma unroll
-            for (int m = 0; m < 8; ++m) {
-                const float v = acc[m][t];
-                if (v != 0.f) atomicAdd(dst + m, v);
+                for (int m = 0; m < 8; ++m) {
+                    const float v = acc[m][t];
+                    if (v != 0.f) atomicAdd(dst + m, v);
+                }
+            } else {
+                // the (tile, Gaussian) sums, coalesced in sorted pair order;
+                // the gradient kernel adds each Gaussian's pairs in a fixed order
+                float4* dst = partials + 2 * (int64_t)(base + t);
+                dst[0] = make_float4(acc[0][t], acc[1][t], acc[2][t], acc[3][t]);
+                dst[1] = make_float4(acc[4][t], acc[5][t], acc[6][t], acc[7][t]);
             }
         }
         __syncthreads();
@@ -390,21 +412,35 @@ __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_bwd(
 __global__ __launch_bounds__(kBlockG) void k_finalize(
     const GRec* __restrict__ recs, int64_t n_gauss, const float* __restrict__ chol,
     const float* __restrict__ color, const float* __restrict__ opacity,
-    float* __restrict__ moments, float* __restrict__ grad_mean,
-    float* __restrict__ grad_chol, float* __restrict__ grad_color,
-    float* __restrict__ grad_opacity) {
+    float* __restrict__ moments, const int32_t* __restrict__ counts,
+    const int32_t* __restrict__ offsets, const uint32_t* __restrict__ inv,
+    const float4* __restrict__ partials, const WsHeader* __restrict__ hdr, int64_t cap,
+    int atomic_grads, float* __restrict__ grad_mean, float* __restrict__ grad_chol,
+    float* __restrict__ grad_color, float* __restrict__ grad_opacity) {
     const int64_t i = (int64_t)blockIdx.x * kBlockG + threadIdx.x;
     if (i >= n_gauss) return;
     const GRec r = recs[i];
     double gm0 = 0, gm1 = 0, gl0 = 0, gl1 = 0, gl2 = 0, gc0 = 0, gc1 = 0, gc2 = 0, ga = 0;
     float m[8];
-    {
+    if (atomic_grads) {
         float4* mp = reinterpret_cast<float4*>(moments + i * 8);
         const float4 u = mp[0], v = mp[1];
         m[0] = u.x; m[1] = u.y; m[2] = u.z; m[3] = u.w;
         m[4] = v.x; m[5] = v.y; m[6] = v.z; m[7] = v.w;
         mp[0] = make_float4(0.f, 0.f, 0.f, 0.f);  // ready for the next backward
         mp[1] = make_float4(0.f, 0.f, 0.f, 0.f);
+    } else {
+        // this Gaussian's pairs, in emission (tile row-major) order
+        for (int k = 0; k < 8; ++k) m[k] = 0.f;
+        const int64_t P = hdr->n_pairs < cap ? hdr->n_pairs : cap;
+        const int64_t e0 = offsets[i], e1 = e0 + counts[i];
+        for (int64_t e = e0; e < e1 && e < cap; ++e) {
+            const uint32_t p = inv[e];
+            if (p >= P) continue;
+            const float4 u = partials[2 * (int64_t)p], v = partials[2 * (int64_t)p + 1];
+            m[0] += u.x; m[1] += u.y; m[2] += u.z; m[3] += u.w;
+            m[4] += v.x; m[5] += v.y; m[6] += v.z; m[7] += v.w;
+        }
     }
     if (r.x0 <= r.x1 && r.pad == 0) {
         const double l11 = chol[3 * i], l21 = chol[3 * i + 1], l22 = chol[3 * i + 2];
@@ -489,21 +525,59 @@ hipError_t launch_sum_loss(const Layout& L, const Ws& w, int64_t numel, double* 
     return hipGetLastError();
 }
 
-hipError_t launch_render_fwd(const Layout& L, const Ws& w, float* out, hipStream_t st) {
-    const uint32_t* gids = (L.n_passes & 1) ? w.vals[1] : w.vals[0];
+template <typename Table>
+static hipError_t launch_fwd_t(const Layout& L, const Ws& w, const Table& tab, float* out,
+                               hipStream_t st) {
     const dim3 grid((unsigned)L.n_tiles);
     switch (L.tile) {
         case 8:
-            hipLaunchKernelGGL(k_render_fwd<8>, grid, dim3(TileShape<8>::kThreads), 0, st,
-                               w.imgs, L.n_img, w.recs, gids, w.ranges, out);
+            hipLaunchKernelGGL((k_render_fwd<8, Table>), grid, dim3(TileShape<8>::kThreads), 0,
+                               st, tab, L.n_img, w.pairs, w.ranges, out);
             break;
         case 16:
-            hipLaunchKernelGGL(k_render_fwd<16>, grid, dim3(TileShape<16>::kThreads), 0, st,
-                               w.imgs, L.n_img, w.recs, gids, w.ranges, out);
+            hipLaunchKernelGGL((k_render_fwd<16, Table>), grid, dim3(TileShape<16>::kThreads), 0,
+                               st, tab, L.n_img, w.pairs, w.ranges, out);
             break;
         case 32:
-            hipLaunchKernelGGL(k_render_fwd<32>, grid, dim3(TileShape<32>::kThreads), 0, st,
-                               w.imgs, L.n_img, w.recs, gids, w.ranges, out);
+            hipLaunchKernelGGL((k_render_fwd<32, Table>), grid, dim3(TileShape<32>::kThreads), 0,
+                               st, tab, L.n_img, w.pairs, w.ranges, out);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_render_fwd(const Layout& L, const Ws& w, float* out, hipStream_t st) {
+    if (L.n_img <= kSetupChunk && L.host_imgs) {
+        ArgTable tab;
+        for (int k = 0; k < kSetupChunk; ++k) tab.c.img[k] = k < L.n_img ? L.host_imgs[k] : ImgDev{};
+        return launch_fwd_t(L, w, tab, out, st);
+    }
+    return launch_fwd_t(L, w, MemTable{w.imgs}, out, st);
+}
+
+template <bool kL1, typename Table>
+static hipError_t launch_bwd_t(const Layout& L, const Ws& w, const Table& tab,
+                               const float* grad_out, const float* target, float inv_numel,
+                               hipStream_t st) {
+    const dim3 grid((unsigned)L.n_tiles);
+    const int atomic = (L.flags & GS_FLAG_ATOMIC_GRADS) ? 1 : 0;
+    switch (L.tile) {
+        case 8:
+            hipLaunchKernelGGL((k_render_bwd<8, kL1, Table>), grid, dim3(TileShape<8>::kThreads),
+                               0, st, tab, L.n_img, w.pairs, w.ranges, grad_out, target,
+                               inv_numel, w.tile_loss, w.moments, w.partials, atomic);
+            break;
+        case 16:
+            hipLaunchKernelGGL((k_render_bwd<16, kL1, Table>), grid,
+                               dim3(TileShape<16>::kThreads), 0, st, tab, L.n_img, w.pairs,
+                               w.ranges, grad_out, target, inv_numel, w.tile_loss, w.moments, w.partials, atomic);
+            break;
+        case 32:
+            hipLaunchKernelGGL((k_render_bwd<32, kL1, Table>), grid,
+                               dim3(TileShape<32>::kThreads), 0, st, tab, L.n_img, w.pairs,
+                               w.ranges, grad_out, target, inv_numel, w.tile_loss, w.moments, w.partials, atomic);
             break;
         default:
             return hipErrorInvalidValue;
@@ -512,40 +586,24 @@ hipError_t launch_render_fwd(const Layout& L, const Ws& w, float* out, hipStream
 }
 
 template <bool kL1>
-static hipError_t launch_bwd_t(const Layout& L, const Ws& w, const float* grad_out,
-                               const float* target, float inv_numel, hipStream_t st) {
-    const uint32_t* gids = (L.n_passes & 1) ? w.vals[1] : w.vals[0];
-    const dim3 grid((unsigned)L.n_tiles);
-    switch (L.tile) {
-        case 8:
-            hipLaunchKernelGGL((k_render_bwd<8, kL1>), grid, dim3(TileShape<8>::kThreads), 0, st,
-                               w.imgs, L.n_img, w.recs, gids, w.ranges, grad_out, target,
-                               inv_numel, w.tile_loss, w.moments);
-            break;
-        case 16:
-            hipLaunchKernelGGL((k_render_bwd<16, kL1>), grid, dim3(TileShape<16>::kThreads), 0, st,
-                               w.imgs, L.n_img, w.recs, gids, w.ranges, grad_out, target,
-                               inv_numel, w.tile_loss, w.moments);
-            break;
-        case 32:
-            hipLaunchKernelGGL((k_render_bwd<32, kL1>), grid, dim3(TileShape<32>::kThreads), 0, st,
-                               w.imgs, L.n_img, w.recs, gids, w.ranges, grad_out, target,
-                               inv_numel, w.tile_loss, w.moments);
-            break;
-        default:
-            return hipErrorInvalidValue;
+static hipError_t launch_bwd_any(const Layout& L, const Ws& w, const float* grad_out,
+                                 const float* target, float inv_numel, hipStream_t st) {
+    if (L.n_img <= kSetupChunk && L.host_imgs) {
+        ArgTable tab;
+        for (int k = 0; k < kSetupChunk; ++k) tab.c.img[k] = k < L.n_img ? L.host_imgs[k] : ImgDev{};
+        return launch_bwd_t<kL1>(L, w, tab, grad_out, target, inv_numel, st);
     }
-    return hipGetLastError();
+    return launch_bwd_t<kL1>(L, w, MemTable{w.imgs}, grad_out, target, inv_numel, st);
 }
 
 hipError_t launch_render_bwd(const Layout& L, const Ws& w, const float* grad_out,
                              hipStream_t st) {
-    return launch_bwd_t<false>(L, w, grad_out, nullptr, 0.f, st);
+    return launch_bwd_any<false>(L, w, grad_out, nullptr, 0.f, st);
 }
 
 hipError_t launch_render_bwd_l1(const Layout& L, const Ws& w, const float* out,
                                 const float* target, int64_t numel, hipStream_t st) {
-    return launch_bwd_t<true>(L, w, out, target, (float)(1.0 / (double)numel), st);
+    return launch_bwd_any<true>(L, w, out, target, (float)(1.0 / (double)numel), st);
 }
 
 hipError_t launch_finalize(const Layout& L, const Ws& w, const float* chol,
@@ -554,8 +612,10 @@ hipError_t launch_finalize(const Layout& L, const Ws& w, const float* chol,
                            hipStream_t st) {
     if (L.n_gauss == 0) return hipSuccess;
     hipLaunchKernelGGL(k_finalize, dim3(blocks_for(L.n_gauss, kBlockG)), dim3(kBlockG), 0, st,
-                       w.recs, L.n_gauss, chol, color, opacity, w.moments, grad_mean,
-                       grad_chol, grad_color, grad_opacity);
+                       w.recs, L.n_gauss, chol, color, opacity, w.moments, w.counts, w.offsets,
+                       w.inv, w.partials, w.hdr, L.cap,
+                       (L.flags & GS_FLAG_ATOMIC_GRADS) ? 1 : 0, grad_mean, grad_chol,
+                       grad_color, grad_opacity);
     return hipGetLastError();
 }
 

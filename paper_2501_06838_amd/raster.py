@@ -23,7 +23,7 @@ import torch
 
 from . import _native as N
 
-__all__ = ["RasterPlan", "GSRasterize", "rasterize", "l1_loss_grad"]
+__all__ = ["RasterPlan", "GSRasterize", "StepGraph", "rasterize", "l1_loss_grad"]
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -270,6 +270,44 @@ class RasterPlan:
                                       ctypes.byref(nt), ctypes.byref(npairs),
                                       _stream(stream)), "tile lists")
         return ranges, gids[:npairs.value]
+
+
+class StepGraph:
+    """A captured HIP graph of one forward (+ fused L1 backward) pass over a
+    plan's batch with fixed buffers; ``launch()`` replays it on the current
+    stream.  Update the Gaussian tensors in place between replays."""
+
+    def __init__(self, plan: "RasterPlan", mean, chol, color, opacity, workspace, out,
+                 target=None, grads=None, loss=None, radius=None, capacity=None):
+        self.plan = plan
+        # keep every buffer alive as long as the graph
+        self.buffers = (mean, chol, color, opacity, workspace, out, target, grads, loss, radius)
+        cfg = plan.config(capacity)
+        gm = gc = gcol = gop = None
+        if grads is not None:
+            gm, gc, gcol, gop = grads
+        h = ctypes.c_void_p()
+        N.check(N.lib().gs_graph_create(ctypes.byref(cfg), plan._arr, len(plan.images),
+                                        _ptr(mean), _ptr(chol), _ptr(color), _ptr(opacity),
+                                        _ptr(radius), plan.n_gauss, _ptr(workspace),
+                                        workspace.numel(), _ptr(out), _ptr(target), _ptr(gm),
+                                        _ptr(gc), _ptr(gcol), _ptr(gop), _ptr(loss),
+                                        ctypes.byref(h)), "graph create")
+        self._h = h
+
+    def launch(self, stream=None):
+        N.check(N.lib().gs_graph_launch(self._h, _stream(stream)), "graph launch")
+
+    def close(self):
+        if self._h:
+            N.lib().gs_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class GSRasterize(torch.autograd.Function):

@@ -217,13 +217,14 @@ def test_l1_loss_kernel():
     np.testing.assert_array_equal(g.cpu().numpy(), np.float32(ref_g[0]))
 
 
-@pytest.mark.parametrize("tile", [16, 8, 32])
-def test_backward_parity_config1(tile):
+@pytest.mark.parametrize("tile,flags", [(16, 0), (8, 0), (32, 0), (16, 2)])
+def test_backward_parity_config1(tile, flags):
     """Config-1 batch with the L1 loss: gradients of every Gaussian property
-    against the FP64 oracle (same upstream gradient on both sides)."""
+    against the FP64 oracle (same upstream gradient on both sides).  flags=2
+    is the global-atomic reduction of the per-tile sums."""
     wl = synth.config1(n_images=16 if tile == 16 else 3)
-    say("backward", tile, wl.n_gauss)
-    plan, ws, out = render(wl, tile)
+    say("backward", tile, flags, wl.n_gauss)
+    plan, ws, out = render(wl, tile, plan=plan_for(wl, tile, flags=flags))
     ref_imgs = _oracle_images(wl)
     _, grads = O.l1_loss_and_grad(ref_imgs, wl.target[:len(wl.images)])
     G = plan.pack([torch.from_numpy(np.float32(g)) for g in grads]).cuda()
@@ -310,3 +311,69 @@ def test_autograd_matches_direct():
     assert_grad_close(c.grad.cpu().numpy(), rc, name="chol")
     assert_grad_close(col.grad.cpu().numpy(), rcol, name="color")
     assert_grad_close(op.grad.cpu().numpy(), rop, name="opacity")
+
+
+@pytest.mark.parametrize("tile", [16, 32])
+def test_backward_fused_l1(tile):
+    """Backward fused with the L1 loss: the sign decision is taken on the
+    GPU's FP32 image on both sides; gradients and the loss value against the
+    oracle."""
+    wl = synth.config1(n_images=4)
+    say("fused l1", tile)
+    plan, ws, out = render(wl, tile)
+    target = plan.pack([torch.from_numpy(t) for t in wl.target]).cuda()
+    m, c, col, op = to_dev(wl)
+    loss = torch.zeros((), dtype=torch.float64, device="cuda")
+    gm, gc, gcol, gop = plan.backward_l1(c, col, op, ws, out, target, loss=loss)
+    torch.cuda.synchronize()
+    imgs = [x.cpu().numpy() for x in plan.split(out)]
+    ref_loss, G = O.l1_loss_and_grad(imgs, wl.target[:len(wl.images)])
+    assert abs(loss.item() - ref_loss) <= 1e-12 * ref_loss
+    rm, rc, rcol, rop = O.backward_batch(wl, G)
+    assert_grad_close(gm.cpu().numpy(), rm, name="mean")
+    assert_grad_close(gc.cpu().numpy(), rc, name="chol")
+    assert_grad_close(gcol.cpu().numpy(), rcol, name="color")
+    assert_grad_close(gop.cpu().numpy(), rop, name="opacity")
+    # a second backward of the same forward gives the same gradients (up to
+    # the order of the FP32 atomic adds)
+    gm2 = plan.backward_l1(c, col, op, ws, out, target)[0]
+    assert torch.allclose(gm2, gm, rtol=1e-5, atol=1e-6 * gm.abs().max().item())
+
+
+def test_graph_replay_matches_eager():
+    """A captured training step replays to the eager results: forward image
+    bitwise, gradients within the backward tolerance, over several replays
+    with eager work and synchronisations in between, and after updating the
+    Gaussians in place."""
+    import paper_2501_06838_amd as P
+    wl = synth.config1(n_images=3)
+    plan = plan_for(wl, 16)
+    m, c, col, op = to_dev(wl)
+    plan.ensure_capacity(m, c, headroom=1.5)
+    dev = "cuda"
+    target = plan.pack([torch.from_numpy(t) for t in wl.target]).cuda()
+
+    def bufs():
+        return (plan.new_workspace(), plan.new_output(),
+                tuple(torch.empty(s, device=dev) for s in [(wl.n_gauss, 2), (wl.n_gauss, 3),
+                                                            (wl.n_gauss, 3), (wl.n_gauss,)]),
+                torch.zeros((), dtype=torch.float64, device=dev))
+    ws_g, out_g, gr_g, loss_g = bufs()
+    say("graph capture")
+    graph = P.StepGraph(plan, m, c, col, op, ws_g, out_g, target, gr_g, loss_g)
+    for rep in range(3):
+        if rep == 2:  # in-place update between replays
+            with torch.no_grad():
+                m.add_(0.01)
+                col.mul_(0.9)
+        graph.launch()
+        torch.cuda.synchronize()
+        ws_e, out_e, gr_e, loss_e = bufs()
+        plan.forward(m, c, col, op, ws_e, out_e)
+        plan.backward_l1(c, col, op, ws_e, out_e, target, grads=gr_e, loss=loss_e)
+        torch.cuda.synchronize()
+        assert torch.equal(out_g, out_e), rep
+        assert abs(loss_g.item() - loss_e.item()) <= 1e-12 * loss_e.item()
+        for a, b in zip(gr_g, gr_e):
+            assert torch.allclose(a, b, rtol=1e-5, atol=1e-6 * b.abs().max().item())
+    graph.close()
