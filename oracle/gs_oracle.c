@@ -324,3 +324,40 @@ void or_pixel_values(int32_t H, int32_t W, double s, int64_t n,
         }
     }
 }
+
+/* Support-radius labels of one image for the learned pruning: for each
+ * Gaussian, the largest Mahalanobis distance d (LR units, d^2 = the Eq. 2
+ * quadratic form) over the HR pixels of its exact support box whose own
+ * contribution alpha * max_c(c_c) * f (Eq. 1, 2) is at least tau; 0 if no
+ * pixel qualifies or the Gaussian has no support.  R [n] is overwritten. */
+void or_radius_labels(int32_t H, int32_t W, double s, int64_t n,
+                      const double* mean, const double* chol, const double* color,
+                      const double* opacity, double tau, double* R)
+{
+    int32_t oh, ow;
+    for (int64_t i = 0; i < n; ++i) R[i] = 0.0;
+    if (or_output_size(H, W, s, &oh, &ow) != 0) return;
+    for (int64_t i = 0; i < n; ++i) {
+        const double mx = mean[2 * i], my = mean[2 * i + 1];
+        const double l11 = chol[3 * i], l21 = chol[3 * i + 1], l22 = chol[3 * i + 2];
+        int32_t r[4];
+        if (!or_support_rect(s, ow, oh, mx, my, l11, l21, l22, 3.0, r)) continue;
+        double cmax = color[3 * i];
+        if (color[3 * i + 1] > cmax) cmax = color[3 * i + 1];
+        if (color[3 * i + 2] > cmax) cmax = color[3 * i + 2];
+        double sx, sy, rho;
+        chol_to_eq2(l11, l21, l22, &sx, &sy, &rho);
+        const double D = 1.0 - rho * rho;
+        double best = 0.0;
+        for (int32_t y = r[2]; y <= r[3]; ++y) {
+            for (int32_t x = r[0]; x <= r[1]; ++x) {
+                const double dx = (double)x / s - mx, dy = (double)y / s - my;
+                const double q = (dx * dx / (sx * sx) - 2.0 * rho * dx * dy / (sx * sy) +
+                                  dy * dy / (sy * sy)) / D;
+                const double f = exp(-0.5 * q) / (2.0 * OR_PI * sx * sy * sqrt(D));
+                if (opacity[i] * cmax * f >= tau && q > best * best) best = sqrt(q);
+            }
+        }
+        R[i] = best;
+    }
+}

@@ -66,6 +66,9 @@ def lib():
                                       ctypes.c_int64, _D, _D, _D, _D, _D, ctypes.c_int64,
                                       _I32, _I32, _D]
         L.or_pixel_values.restype = None
+        L.or_radius_labels.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                       ctypes.c_int64, _D, _D, _D, _D, ctypes.c_double, _D]
+        L.or_radius_labels.restype = None
         _lib = L
     return _lib
 
@@ -140,6 +143,24 @@ def pixel_values(H, W, s, mean, chol, color, opacity, xs, ys, radius=None):
     out = np.zeros((3, xs.size), dtype=np.float64)
     lib().or_pixel_values(H, W, float(s), mean.shape[0], _p(mean), _p(chol), _p(color),
                           _p(opacity), _p(rad), xs.size, _p(xs, _I32), _p(ys, _I32), _p(out))
+    return out
+
+
+def radius_labels(H, W, s, mean, chol, color, opacity, tau):
+    """Per-Gaussian support-radius labels of one image (see gs_oracle.c)."""
+    mean, chol, color, opacity = _d(mean), _d(chol), _d(color), _d(opacity)
+    R = np.zeros(mean.shape[0])
+    lib().or_radius_labels(H, W, float(s), mean.shape[0], _p(mean), _p(chol), _p(color),
+                           _p(opacity), float(tau), _p(R))
+    return R
+
+
+def radius_labels_batch(wl, tau):
+    out = np.zeros(wl.n_gauss)
+    for k, im in enumerate(wl.images):
+        sl = wl.image_slice(k)
+        out[sl] = radius_labels(im.lr_h, im.lr_w, im.scale, wl.mean[sl], wl.chol[sl],
+                                wl.color[sl], wl.opacity[sl], tau)
     return out
 
 
