@@ -237,6 +237,69 @@ gs_status gs_tile_lists(const gs_config* cfg, const gs_image* images, int32_t n_
                         int32_t* ranges_host, int32_t* gids_host, int64_t max_pairs,
                         int64_t* n_tiles_out, int64_t* n_pairs_out, void* stream);
 
+/* ---- learned support radius (pruned rasterization) ----------------------
+ *
+ * A small MLP predicts, per Gaussian and scale, the support half-width R (in
+ * standard deviations) beyond which the Gaussian's own contribution
+ * alpha max(c) f (Eq. 1, 2) stays below a threshold tau; the pruned render
+ * passes R as `radius` to gs_raster_forward, so fewer (tile, Gaussian) pairs
+ * are binned and evaluated.  The exact 3-sigma box remains the fallback.
+ * Network: features [log s, log sigma_x, log sigma_y, rho, alpha, c_r, c_g,
+ * c_b] (Sec. 3.1's properties minus the position, plus the scale),
+ * standardised; 8 -> 64 -> 64 -> 1 with ReLU; BF16 matrix-core products with
+ * FP32 accumulation.  Parameters: FP32 master copy, GS_MLP_PARAMS floats in
+ * the order W1 [64][8], b1 [64], W2 [64][64], b2 [64], W3 [1][64], b3 [1]. */
+#define GS_MLP_PARAMS 4801
+
+typedef struct {
+    float mu[8], sd[8];      /* training mean / standard deviation per feature */
+    float fmin[8], fmax[8];  /* training range of the standardised features   */
+    float margin;            /* added to the prediction (calibrated)          */
+    float reserved[3];
+} gs_mlp_norm;
+
+/* Features of every Gaussian of the batch (device feats [n_gauss][8]),
+ * standardised with norm (host) or raw when norm is NULL. */
+gs_status gs_mlp_features(const gs_image* images, int32_t n_img, const float* chol,
+                          const float* color, const float* opacity, int64_t n_gauss,
+                          const gs_mlp_norm* norm, float* feats, void* stream);
+
+/* MLP forward on n standardised feature rows (device).  norm NULL: out[n] is
+ * the raw prediction; otherwise out[n] is the support half-width for the
+ * pruned path: min(max(prediction + margin, 0), 3), or 3 (the exact box) when
+ * a feature lies outside [fmin, fmax] or the prediction is not finite. */
+gs_status gs_mlp_forward(const float* params, const float* feats, int64_t n,
+                         const gs_mlp_norm* norm, float* out, void* stream);
+
+/* Device workspace bytes of gs_mlp_grad for n rows. */
+gs_status gs_mlp_workspace_size(int64_t n, size_t* bytes);
+
+/* Gradient of the mean pinball (quantile) loss against labels (device [n]),
+ * or, when labels is NULL, of sum_i dout_i * prediction_i for a given
+ * upstream gradient dout (device [n]).  grad: device [GS_MLP_PARAMS],
+ * overwritten (sums over the batch in a fixed order).  loss_sum (device
+ * double, may be NULL) is incremented by the mean pinball loss. */
+gs_status gs_mlp_grad(const float* params, const float* feats, const float* labels,
+                      const float* dout, int64_t n, float quantile, void* workspace,
+                      size_t ws_bytes, float* grad, double* loss_sum, void* stream);
+
+/* One Adam step (Kingma & Ba: beta1 0.9, beta2 0.999, eps 1e-8) on the FP32
+ * master parameters; m, v: device [GS_MLP_PARAMS]; step counts from 1. */
+gs_status gs_mlp_adam(float* params, float* m, float* v, const float* grad, int32_t step,
+                      float lr, void* stream);
+
+/* Training labels from the exact rasterizer: per Gaussian, the largest
+ * Mahalanobis distance over the HR pixels of its 3-sigma box whose own
+ * contribution alpha max(c) f is at least tau (0 if none).  Uses the
+ * workspace of a gs_raster_forward with radius NULL; radius: device [n_gauss]. */
+gs_status gs_radius_stats(const gs_config* cfg, const gs_image* images, int32_t n_img,
+                          int64_t n_gauss, const void* workspace, size_t ws_bytes, float tau,
+                          float* radius, void* stream);
+
+/* sum (a_i - b_i)^2 over n elements, ADDED to *sum (device double): the
+ * squared error behind the PSNR of a pruned render against the exact one. */
+gs_status gs_sq_error(const float* a, const float* b, int64_t n, double* sum, void* stream);
+
 /* ---- graph capture (HIP graphs) ---------------------------------------- */
 
 /* Opaque executable graph of one whole pass over a fixed batch layout and

@@ -28,7 +28,8 @@ EXPORTED = (
     "gs_count_pairs", "gs_tile_lists", "gs_raster_bin", "gs_raster_render",
     "gs_raster_render_backward", "gs_raster_gradients", "gs_raster_render_backward_l1",
     "gs_l1_loss_value", "gs_raster_backward_l1", "gs_graph_create", "gs_graph_launch",
-    "gs_graph_destroy",
+    "gs_graph_destroy", "gs_mlp_features", "gs_mlp_forward", "gs_mlp_workspace_size",
+    "gs_mlp_grad", "gs_mlp_adam", "gs_radius_stats", "gs_sq_error",
 )
 
 

@@ -354,6 +354,96 @@ gs_status gs_count_pairs(const gs_config* cfg, const gs_image* images, int32_t n
     return GS_OK;
 }
 
+gs_status gs_mlp_features(const gs_image* images, int32_t n_img, const float* chol,
+                          const float* color, const float* opacity, int64_t n_gauss,
+                          const gs_mlp_norm* norm, float* feats, void* stream) {
+    if (n_gauss > 0 && (!chol || !color || !opacity || !feats)) return GS_E_INVALID;
+    gs_mlp_norm nm{};
+    if (norm) {
+        nm = *norm;
+        for (int k = 0; k < 8; ++k)
+            if (!(nm.sd[k] > 0.f) || !std::isfinite(nm.mu[k])) return GS_E_INVALID;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // one launch per chunk of images (the chunk's table travels by value)
+    for (int first = 0; first < n_img; first += kSetupChunk) {
+        const int count = std::min(kSetupChunk, n_img - first);
+        std::vector<gs_image> sub(images + first, images + first + count);
+        const int64_t g0 = sub.front().g_begin;
+        const int64_t g1 = sub.back().g_begin + sub.back().g_count;
+        for (auto& im : sub) { im.g_begin -= g0; im.out_offset = 0; }
+        // out_offset is irrelevant here; make the blocks disjoint for validation
+        int64_t off = 0;
+        for (auto& im : sub) {
+            int32_t oh, ow;
+            GS_TRY(size_of(im.lr_h, im.lr_w, im.scale, &oh, &ow));
+            im.out_offset = off;
+            off += 3LL * oh * ow;
+        }
+        Layout L;
+        std::vector<ImgDev> table;
+        GS_TRY(make_layout(nullptr, sub.data(), count, g1 - g0, &L, &table));
+        Ws w{};
+        GS_TRY(dev(launch_mlp_features(L, w, chol + 3 * g0, color + 3 * g0, opacity + g0, nm,
+                                       norm ? 1 : 0, feats + 8 * g0, st)));
+    }
+    return GS_OK;
+}
+
+gs_status gs_mlp_forward(const float* params, const float* feats, int64_t n,
+                         const gs_mlp_norm* norm, float* out, void* stream) {
+    if (n < 0) return GS_E_INVALID;
+    if (n > 0 && (!params || !feats || !out)) return GS_E_INVALID;
+    gs_mlp_norm nm{};
+    if (norm) nm = *norm;
+    return dev(launch_mlp_forward(params, feats, n, nm, norm ? 1 : 0, out,
+                                  static_cast<hipStream_t>(stream)));
+}
+
+gs_status gs_mlp_workspace_size(int64_t n, size_t* bytes) {
+    if (!bytes || n < 0) return GS_E_INVALID;
+    *bytes = sizeof(float) * (size_t)kMlpParams * (size_t)mlp_grad_waves(n);
+    return GS_OK;
+}
+
+gs_status gs_mlp_grad(const float* params, const float* feats, const float* labels,
+                      const float* dout, int64_t n, float quantile, void* workspace,
+                      size_t ws_bytes, float* grad, double* loss_sum, void* stream) {
+    if (n < 1 || !params || !feats || !grad || (!labels && !dout)) return GS_E_INVALID;
+    if (labels && !(quantile > 0.f && quantile < 1.f)) return GS_E_INVALID;
+    size_t need = 0;
+    GS_TRY(gs_mlp_workspace_size(n, &need));
+    if (!workspace || ws_bytes < need) return GS_E_WORKSPACE;
+    return dev(launch_mlp_grad(params, feats, labels, dout, n, quantile,
+                               static_cast<float*>(workspace), grad, labels ? loss_sum : nullptr,
+                               static_cast<hipStream_t>(stream)));
+}
+
+gs_status gs_mlp_adam(float* params, float* m, float* v, const float* grad, int32_t step,
+                      float lr, void* stream) {
+    if (!params || !m || !v || !grad || step < 1 || !(lr > 0.f)) return GS_E_INVALID;
+    return dev(launch_adam(params, m, v, grad, step, lr, 0.9f, 0.999f, 1e-8f,
+                           static_cast<hipStream_t>(stream)));
+}
+
+gs_status gs_radius_stats(const gs_config* cfg, const gs_image* images, int32_t n_img,
+                          int64_t n_gauss, const void* workspace, size_t ws_bytes, float tau,
+                          float* radius, void* stream) {
+    Layout L;
+    std::vector<ImgDev> table;
+    GS_TRY(make_layout(cfg, images, n_img, n_gauss, &L, &table));
+    if (n_gauss > 0 && !radius) return GS_E_INVALID;
+    if (!(tau > 0.f)) return GS_E_INVALID;
+    if (!workspace || ws_bytes < L.total) return GS_E_WORKSPACE;
+    return dev(launch_radius_stats(L, bind(L, const_cast<void*>(workspace)), tau, radius,
+                                   static_cast<hipStream_t>(stream)));
+}
+
+gs_status gs_sq_error(const float* a, const float* b, int64_t n, double* sum, void* stream) {
+    if (n < 0 || (n > 0 && (!a || !b || !sum))) return GS_E_INVALID;
+    return dev(launch_sq_error(a, b, n, sum, static_cast<hipStream_t>(stream)));
+}
+
 struct gs_graph_s {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;

@@ -10,6 +10,7 @@
 
 namespace gs {
 
+constexpr int kMlpParams = 4801;        // W1 64x8, b1 64, W2 64x64, b2 64, W3 1x64, b3 1
 constexpr int kSetupChunk = 32;        // images per table chunk (kernel argument)
 constexpr int kFoldScanBlocks = 2048;  // up to this many Gaussian blocks the
                                        // emission kernel scans the block sums itself
@@ -192,5 +193,24 @@ hipError_t launch_finalize(const Layout& L, const Ws& w, const float* chol,
                            hipStream_t st);
 hipError_t launch_l1(const float* img, const float* target, int64_t numel, float* grad,
                      double* loss_sum, hipStream_t st);
+
+// ---- launchers (gs_surrogate.hip) ----------------------------------------
+int64_t mlp_grad_waves(int64_t n);
+hipError_t launch_mlp_features(const Layout& L, const Ws& w, const float* chol,
+                               const float* color, const float* opacity,
+                               const gs_mlp_norm& norm, int standardise, float* X,
+                               hipStream_t st);
+hipError_t launch_mlp_forward(const float* params, const float* X, int64_t n,
+                              const gs_mlp_norm& norm, int radius_mode, float* out,
+                              hipStream_t st);
+hipError_t launch_mlp_grad(const float* params, const float* X, const float* labels,
+                           const float* dout, int64_t n, float q, float* partials,
+                           float* grad, double* loss_sum, hipStream_t st);
+hipError_t launch_adam(float* p, float* m, float* v, const float* grad, int t, float lr,
+                       float b1, float b2, float eps, hipStream_t st);
+hipError_t launch_radius_stats(const Layout& L, const Ws& w, float tau, float* R,
+                               hipStream_t st);
+hipError_t launch_sq_error(const float* a, const float* b, int64_t n, double* sum,
+                           hipStream_t st);
 
 }  // namespace gs

@@ -1,0 +1,125 @@
+"""GPU parity of the learned-radius kernels against the surrogate oracle.
+
+The MLP's hidden activations are rounded to BF16 on both sides at the same
+points, but each side forms the value it rounds in its own precision (FP32
+accumulation on the matrix cores, FP64 in the oracle), so a value lying
+within an FP32 rounding of a BF16 midpoint can round to neighbouring BF16
+values.  The bars therefore hold almost everywhere tightly and everywhere
+loosely (stated per test).
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import oracle as O
+from oracle import surrogate as S
+from tests._gpu import plan_for, render, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _params(seed):
+    p = S.init_params(seed).astype(np.float64)
+    rng = np.random.default_rng(seed + 100)
+    d = S.unpack(p)
+    d["b1"] = rng.normal(0, 0.3, 64)
+    d["b2"] = rng.normal(0, 0.3, 64)
+    d["b3"] = rng.normal(0, 0.3, 1)
+    return S.pack(d).astype(np.float32)
+
+
+def test_mlp_forward_parity():
+    from paper_2501_06838_amd.surrogate import RadiusMLP
+    params = _params(1)
+    X = np.random.default_rng(2).normal(size=(1000, 8)).astype(np.float32)
+    say("mlp forward")
+    net = RadiusMLP(params)
+    got = net.predict(torch.from_numpy(X).cuda()).cpu().numpy().astype(np.float64)
+    ref, _ = S.mlp_forward(params, X)
+    scale = np.abs(ref).max()
+    err = np.abs(got - ref)
+    assert (err <= 1e-4 * scale).mean() >= 0.99
+    assert err.max() <= 2e-2 * scale
+
+
+@pytest.mark.parametrize("n", [1, 37, 1000, 20000])
+def test_mlp_gradient_parity(n):
+    from paper_2501_06838_amd.surrogate import RadiusMLP
+    params = _params(3)
+    rng = np.random.default_rng(4)
+    X = rng.normal(size=(n, 8)).astype(np.float32)
+    dout = (rng.normal(size=n) / n).astype(np.float32)
+    say("mlp grad", n)
+    net = RadiusMLP(params)
+    g = net.gradient(torch.from_numpy(X).cuda(), dout=torch.from_numpy(dout).cuda())
+    g = g.cpu().numpy().astype(np.float64)
+    _, cache = S.mlp_forward(params, X)
+    ref = S.mlp_backward(cache, np.float64(dout))
+    for name, sl in (("W1", slice(0, 512)), ("b1", slice(512, 576)), ("W2", slice(576, 4672)),
+                     ("b2", slice(4672, 4736)), ("W3", slice(4736, 4800)), ("b3", slice(4800, 4801))):
+        a, b = g[sl], ref[sl]
+        scale = np.abs(b).max()
+        assert np.abs(a - b).max() <= 2e-2 * scale + 1e-12, name
+        assert np.abs(a - b).mean() <= 2e-3 * scale + 1e-12, name
+
+
+def test_mlp_pinball_gradient_and_adam():
+    from paper_2501_06838_amd.surrogate import RadiusMLP
+    params = _params(5)
+    rng = np.random.default_rng(6)
+    X = rng.normal(size=(4096, 8)).astype(np.float32)
+    lab = rng.uniform(0, 3, 4096).astype(np.float32)
+    say("mlp pinball + adam")
+    net = RadiusMLP(params)
+    loss = torch.zeros((), dtype=torch.float64, device="cuda")
+    net.step(torch.from_numpy(X).cuda(), torch.from_numpy(lab).cuda(), lr=1e-3, quantile=0.9,
+             loss=loss)
+    pred, cache = S.mlp_forward(params, X)
+    ref_loss, dpred = S.pinball(pred, lab, 0.9)
+    assert abs(loss.item() - ref_loss) <= 1e-3 * abs(ref_loss)
+    ref_g = S.mlp_backward(cache, dpred)
+    g = net.grad.cpu().numpy().astype(np.float64)
+    assert np.abs(g - ref_g).max() <= 2e-2 * np.abs(ref_g).max()
+    # Adam on the same gradient (the GPU's) gives the oracle's update
+    p1, _, _ = S.adam(params, g, np.zeros(4801), np.zeros(4801), 1, 1e-3)
+    np.testing.assert_allclose(net.params.cpu().numpy(), p1, rtol=1e-5, atol=1e-7)
+
+
+def test_features_parity():
+    from paper_2501_06838_amd.surrogate import features, make_norm
+    wl = synth.config3(n_images=40)   # two chunks of the by-value image table
+    plan = plan_for(wl, 16)
+    m, c, col, op = to_dev(wl)
+    scale = np.concatenate([np.full(im.g_count, im.scale) for im in wl.images])
+    F = S.features(scale, wl.chol, wl.color, wl.opacity)
+    mu, sd = F.mean(0), F.std(0)
+    say("features")
+    got = features(plan, c, col, op, make_norm(mu, sd)).cpu().numpy()
+    ref = (F - mu) / sd
+    assert np.abs(got - ref).max() < 1e-5 * max(1.0, np.abs(ref).max())
+
+
+def test_radius_labels_bracket_oracle():
+    """GPU labels decide 'contribution >= tau' in FP32: each must lie between
+    the oracle's labels at tau (1 + 1e-4) and tau (1 - 1e-4)."""
+    from paper_2501_06838_amd.surrogate import radius_labels
+    wl = synth.tiny(H=24, W=20, s=5.3, seed=8, sigma=(0.8, 0.5), extra_frac=0.25)
+    tau = 2e-3
+    say("radius stats")
+    plan, ws, _ = render(wl, 16)
+    got = radius_labels(plan, ws, tau).cpu().numpy().astype(np.float64)
+    lo = O.radius_labels_batch(wl, tau * (1 + 1e-4))
+    hi = O.radius_labels_batch(wl, tau * (1 - 1e-4))
+    assert (got >= lo * (1 - 1e-5) - 1e-6).all() and (got <= hi * (1 + 1e-5) + 1e-6).all()
+    assert (got > 0).mean() > 0.5
+
+
+def test_sq_error_kernel():
+    from paper_2501_06838_amd.surrogate import sq_error
+    rng = np.random.default_rng(9)
+    a, b = rng.normal(size=100001).astype(np.float32), rng.normal(size=100001).astype(np.float32)
+    say("sq error")
+    got = sq_error(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda())
+    ref = float(((np.float64(a) - np.float64(b)) ** 2).sum())
+    assert abs(got - ref) <= 1e-12 * ref
