@@ -85,6 +85,95 @@ def cpu_baseline(wl, seconds: float):
     }
 
 
+def pruned_comparison(args, G, synth, torch, np):
+    """Exact vs surrogate-pruned fwd+bwd on a wide-sigma DIV2K-sized workload:
+    train the radius network on labels the exact rasterizer measures on 10k
+    seeded images, then time both steps (each captured as one graph) and
+    report the PSNR of the pruned render against the exact one."""
+    from paper_2501_06838_amd.surrogate import features, psnr
+    from paper_2501_06838_amd.surrogate_train import train_radius_mlp
+    dev = torch.device("cuda:0")
+    tau = 4e-3
+    log("surrogate: labels from the exact rasterizer on 10k images, training")
+    net, info = train_radius_mlp(lambda k: synth.surrogate_training_batch(11, k), 600, 25, tau,
+                                 steps=600, lr=3e-3, quantile=0.9, coverage=0.999)
+    log(f"surrogate trained: margin {info['margin']:.3f}, loss {info['losses'][-1]:.4f}")
+    wl = synth.by_name(args.pruned_workload)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    mean, chol, color, opacity = t(wl.mean), t(wl.chol), t(wl.color), t(wl.opacity)
+    imgs = [(im.lr_h, im.lr_w, im.scale, im.g_begin, im.g_count) for im in wl.images]
+    target = None
+    results = {}
+    feats = torch.empty(wl.n_gauss, 8, device=dev)
+    radius = torch.empty(wl.n_gauss, device=dev)
+    # closed-form control radius sqrt(2 ln(alpha max(c) K / tau)), K = 1/(2 pi l11 l22)
+    K = 1.0 / (2 * np.pi * np.float64(wl.chol[:, 0]) * np.float64(wl.chol[:, 2]))
+    arg = np.float64(wl.opacity) * np.float64(wl.color).max(1) * K / tau
+    rcf = t(np.minimum(np.sqrt(2 * np.log(np.maximum(arg, 1.0))), 3.0).astype(np.float32))
+    for mode in ("exact", "pruned", "closed_form"):
+        plan = G.RasterPlan(imgs, wl.n_gauss, tile=args.tile)
+        if target is None:
+            target = plan.pack([t(x) for x in wl.target])
+        rad = None
+        if mode == "pruned":
+            features(plan, chol, color, opacity, net.norm, out=feats)
+            net.radius(feats, out=radius)
+            rad = radius
+        elif mode == "closed_form":
+            rad = rcf
+        plan.ensure_capacity(mean, chol, rad, headroom=1.05)
+        ws, out = plan.new_workspace(dev), plan.new_output(dev)
+        grads = (torch.empty(wl.n_gauss, 2, device=dev), torch.empty(wl.n_gauss, 3, device=dev),
+                 torch.empty(wl.n_gauss, 3, device=dev), torch.empty(wl.n_gauss, device=dev))
+
+        def step():
+            if mode == "pruned":  # the radius is predicted inside the step
+                features(plan, chol, color, opacity, net.norm, out=feats)
+                net.radius(feats, out=radius)
+            plan.forward(mean, chol, color, opacity, ws, out, rad)
+            plan.render_backward_l1(ws, out, target)
+            plan.gradients(chol, color, opacity, ws, grads)
+
+        step()
+        torch.cuda.synchronize()
+        npairs, overflow, _, nsup = plan.diagnostics(ws, support=True)
+        if overflow:
+            raise SystemExit("pair capacity overflow (pruned comparison)")
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            step()
+        for _ in range(3):
+            g.replay()
+        torch.cuda.synchronize()
+        n = max(5, args.steps // 5)
+        t0 = time.perf_counter()
+        for _ in range(n):
+            g.replay()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / n
+        results[mode] = {"ms_per_step": round(ms, 4),
+                         "mp_s": round(plan.out_numel / 3 / (ms * 1e-3) / 1e6, 2),
+                         "tile_pairs": npairs, "support_pairs": nsup, "image": out.clone()}
+        if mode != "exact":
+            results[mode]["psnr_db"] = round(psnr(out, results["exact"]["image"]), 2)
+        if mode == "pruned":
+            results[mode]["share_at_full_radius"] = round(float((radius >= 3.0).float().mean()), 4)
+        del g
+    for r in results.values():
+        r.pop("image")
+    return {
+        "workload": f"{args.pruned_workload}: {WORKLOADS[args.pruned_workload]}",
+        "tau": tau, "exact": results["exact"], "pruned": results["pruned"],
+        "speedup": round(results["exact"]["ms_per_step"] / results["pruned"]["ms_per_step"], 3),
+        "closed_form_control": results["closed_form"],
+        "surrogate": {k: info[k] for k in ("train_rows", "calib_rows", "margin", "steps",
+                                            "seconds_data", "seconds_train", "quantile",
+                                            "coverage")},
+        "launch": "each step (the pruned one including feature + MLP radius kernels) "
+                  "captured as one HIP graph",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +183,8 @@ def main():
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-pruned", action="store_true")
+    ap.add_argument("--pruned-workload", default="config2a", choices=["config2a", "config2b"])
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -187,6 +278,11 @@ def main():
                                    "frac": round(fwd_tflops / PEAK_FP32_VECTOR_TFLOPS, 4),
                                    "avg_launch_us": round(fwd_ms * 1e3, 2)}},
     }
+    pruned = None
+    if not args.no_pruned:
+        pruned = pruned_comparison(args, G, synth, torch, np)
+        log(f"pruned: {pruned['pruned']['mp_s']} vs exact {pruned['exact']['mp_s']} MP/s "
+            f"({pruned['speedup']}x) at {pruned['pruned']['psnr_db']} dB")
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline")
@@ -201,7 +297,7 @@ def main():
                    "hr_pixels": hr_px, "gaussians": wl.n_gauss, "tile_pairs": npairs,
                    "support_pairs": n_support,
                    "launch": "whole step captured in one HIP graph, replayed"},
-        "roofline": roofline, "cpu_baseline": cpu,
+        "roofline": roofline, "cpu_baseline": cpu, "surrogate_pruned": pruned,
     }
     print(json.dumps(rec), flush=True)
 

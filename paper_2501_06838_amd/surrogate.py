@@ -68,10 +68,11 @@ def make_norm(mu, sd, fmin=None, fmax=None, margin=0.0) -> gs_mlp_norm:
 
 
 def features(plan: RasterPlan, chol, color, opacity, norm: Optional[gs_mlp_norm] = None,
-             stream=None) -> torch.Tensor:
+             stream=None, out=None) -> torch.Tensor:
     """[n, 8] features (standardised when norm is given)."""
     L = _bind()
-    out = torch.empty(plan.n_gauss, 8, dtype=torch.float32, device=chol.device)
+    if out is None:
+        out = torch.empty(plan.n_gauss, 8, dtype=torch.float32, device=chol.device)
     N.check(L.gs_mlp_features(plan._arr, len(plan.images), _ptr(chol), _ptr(color),
                               _ptr(opacity), plan.n_gauss,
                               None if norm is None else ctypes.byref(norm), _ptr(out),
@@ -127,12 +128,13 @@ class RadiusMLP:
                                  _stream(stream)), "mlp forward")
         return out
 
-    def radius(self, feats, stream=None) -> torch.Tensor:
+    def radius(self, feats, stream=None, out=None) -> torch.Tensor:
         """Support half-width for the pruned path (needs self.norm)."""
         L = _bind()
         if self.norm is None:
             raise RuntimeError("calibrate the network first")
-        out = torch.empty(feats.shape[0], dtype=torch.float32, device=feats.device)
+        if out is None:
+            out = torch.empty(feats.shape[0], dtype=torch.float32, device=feats.device)
         N.check(L.gs_mlp_forward(_ptr(self.params), _ptr(feats), feats.shape[0],
                                  ctypes.byref(self.norm), _ptr(out), _stream(stream)),
                 "mlp radius")

@@ -201,3 +201,24 @@ def concat(workloads: List[Workload], name="concat") -> Workload:
                     np.concatenate([w.chol for w in workloads]),
                     np.concatenate([w.color for w in workloads]),
                     np.concatenate([w.opacity for w in workloads]), tg)
+
+
+def surrogate_training_batch(seed: int, k: int, n_images: int = 16, lr_side: int = 24):
+    """Training batch k for the learned support radius: n_images LR
+    lr_side x lr_side images, one Gaussian per LR pixel plus 25% extra, with
+    the per-axis log-std of config 2 (even k) or of configs 0/1/3 (odd k),
+    and scales U[1.4, 12.6] (slightly wider than the workloads' [1.5, 12]).
+
+    Returns (images, mean, chol, color, opacity), images as
+    (lr_h, lr_w, scale, g_begin, g_count)."""
+    rng = np.random.default_rng([seed, k, 7])
+    sig = (0.8, 0.5) if k % 2 == 0 else (0.6, 0.3)
+    parts, images, begin = [], [], 0
+    for j in range(n_images):
+        s = float(rng.uniform(1.4, 12.6))
+        g = draw_image_gaussians(np.random.default_rng([seed, k, j]), lr_side, lr_side,
+                                 sig[0], sig[1], 0.25)
+        parts.append(g)
+        images.append((lr_side, lr_side, s, begin, g[0].shape[0]))
+        begin += g[0].shape[0]
+    return (images,) + tuple(np.concatenate([p[i] for p in parts]) for i in range(4))

@@ -123,3 +123,31 @@ def test_sq_error_kernel():
     got = sq_error(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda())
     ref = float(((np.float64(a) - np.float64(b)) ** 2).sum())
     assert abs(got - ref) <= 1e-12 * ref
+
+
+def test_trained_radius_gain_at_50db():
+    """Trained on labels the exact rasterizer measures, the pruned render of
+    a wide-sigma image stays >= 50 dB from the exact render while binning and
+    evaluating fewer pairs; its image equals the oracle's render with the
+    same radii (1e-5)."""
+    import paper_2501_06838_amd as P
+    from paper_2501_06838_amd.surrogate import features, psnr
+    from paper_2501_06838_amd.surrogate_train import train_radius_mlp
+    say("surrogate training")
+    net, info = train_radius_mlp(lambda k: synth.surrogate_training_batch(11, k), 40, 8, 4e-3,
+                                 steps=500, lr=3e-3)
+    assert info["losses"][-1] < 0.1 * info["losses"][0]
+    wl = synth._build("wide", [(96, 96, 4.0)], (0.8, 0.5), 0.0, seed=5)
+    plan, ws, exact = render(wl, 16)
+    m, c, col, op = to_dev(wl)
+    R = net.radius(features(plan, c, col, op, net.norm))
+    plan2 = plan_for(wl, 16)
+    plan2, ws2, pruned = render(wl, 16, radius=R.cpu().numpy(), plan=plan2)
+    p_ex, _, _, s_ex = plan.diagnostics(ws, support=True)
+    p_pr, _, _, s_pr = plan2.diagnostics(ws2, support=True)
+    db = psnr(pruned, exact)
+    assert db >= 50.0, db
+    assert s_pr < 0.9 * s_ex and p_pr < p_ex
+    ref = O.forward_batch(wl, radius=R.cpu().numpy())
+    from tests._gpu import assert_forward_close
+    assert_forward_close(plan2.split(pruned)[0].cpu().numpy(), ref[0])
