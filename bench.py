@@ -39,6 +39,33 @@ PEAK_HBM_GBS = 8000.0
 FLOPEQ_FWD = 32.0
 FLOPEQ_BWD = 48.0
 
+# HBM traffic of one k_render_bwd launch (fused L1) on config1 at tile 16, from
+# two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch,
+# averaged over the dispatches), each scaled by what the same counter reads for
+# a plain 256 MiB device copy: FETCH_SIZE reads 131,084 KiB (factor 2.0),
+# WRITE_SIZE 262,144 KiB (factor 1.0).  Valid only while the render sources
+# hash to `sources`; otherwise reported as null.
+TRAFFIC = {"workload": "config1", "tile": 16, "sources": "f9ed41f8edf2007b",
+           "fetch_kib": 38085.5, "write_kib": 6604.7, "fetch_factor": 2.0, "write_factor": 1.0}
+TRAFFIC_SOURCES = ("paper_2501_06838_amd/csrc/gs_render.hip", "paper_2501_06838_amd/csrc/gs_internal.h")
+
+
+def render_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_bytes(workload, tile):
+    T = TRAFFIC
+    if workload != T["workload"] or tile != T["tile"] or render_sources_hash() != T["sources"]:
+        return None
+    return round(T["fetch_kib"] * 1024 * T["fetch_factor"] + T["write_kib"] * 1024 * T["write_factor"])
+
+
 WORKLOADS = {
     "config1": "16 x 64x64 LR (4,096 Gaussians each) -> 237x237 at s=3.7, fwd+bwd, L1 loss",
     "config0": "48x48 LR (2,304 Gaussians) -> 192x192 at s=4, fwd+bwd, L1 loss",
@@ -185,6 +212,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pruned", action="store_true")
     ap.add_argument("--pruned-workload", default="config2a", choices=["config2a", "config2b"])
+    ap.add_argument("--calibration-copy", type=int, default=0, metavar="MIB",
+                    help="finish with 5 plain device-to-device copies of MIB MiB (a known "
+                         "byte count for scaling hardware traffic counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -272,7 +302,8 @@ def main():
     roofline = {
         "bound": "alu", "kernel": "k_render_bwd (fused L1 gradient)", "achieved": round(bwd_tflops, 3),
         "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-        "frac": round(bwd_tflops / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": None,
+        "frac": round(bwd_tflops / PEAK_FP32_VECTOR_TFLOPS, 4),
+        "traffic": traffic_bytes(args.workload, args.tile),
         "per_launch_flopeq": n_support * FLOPEQ_BWD, "avg_launch_us": round(bwd_ms * 1e3, 2),
         "other": {"k_render_fwd": {"achieved": round(fwd_tflops, 3),
                                    "frac": round(fwd_tflops / PEAK_FP32_VECTOR_TFLOPS, 4),
@@ -300,6 +331,14 @@ def main():
         "roofline": roofline, "cpu_baseline": cpu, "surrogate_pruned": pruned,
     }
     print(json.dumps(rec), flush=True)
+    if args.calibration_copy > 0:
+        n = args.calibration_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: 5 x {args.calibration_copy} MiB")
 
 
 if __name__ == "__main__":
