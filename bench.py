@@ -112,6 +112,61 @@ def cpu_baseline(wl, seconds: float):
     }
 
 
+def batched_uneven(args, G, synth, torch, np):
+    """The serving-style batch: 64 uneven images rendered fwd+bwd in one
+    captured step, with the launch configuration (tile, LDS batch,
+    persistent longest-first kernels) picked by the autotuner; the default
+    launch (tile 16, one workgroup per tile) is timed beside it."""
+    from paper_2501_06838_amd.autotune import tune
+    dev = torch.device("cuda:0")
+    log("batched: config3 (64 uneven images)")
+    wl = synth.config3(with_target=True)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    mean, chol, color, opacity = t(wl.mean), t(wl.chol), t(wl.color), t(wl.opacity)
+    imgs = [(im.lr_h, im.lr_w, im.scale, im.g_begin, im.g_count) for im in wl.images]
+    plan0 = G.RasterPlan(imgs, wl.n_gauss, tile=16)
+    target = plan0.pack([t(x) for x in wl.target])
+    wl.target = None
+    t0 = time.perf_counter()
+    res = tune(imgs, mean, chol, color, opacity, target, reps=3, warmup=1)
+    t_tune = time.perf_counter() - t0
+    best = res["config"]
+    log(f"batched: autotuner picked {best} in {t_tune:.1f} s")
+    hr_px = plan0.out_numel // 3
+    out = {"workload": "config3: " + WORKLOADS["config3"], "images": len(imgs),
+           "hr_pixels": hr_px, "gaussians": int(mean.shape[0]),
+           "autotune": {"config": best, "seconds": round(t_tune, 2),
+                        "timings_ms": [[c["config"]["tile"], c["config"]["lds_batch"],
+                                        c["config"]["flags"], c["ms"]] for c in res["timings"]]}}
+    for name, cfg in (("tuned", best), ("default_launch", {"tile": 16, "lds_batch": 0,
+                                                           "flags": 0})):
+        plan = G.RasterPlan(imgs, int(mean.shape[0]), **cfg)
+        pairs = plan.ensure_capacity(mean, chol)
+        ws, img = plan.new_workspace(dev), plan.new_output(dev)
+        n = int(mean.shape[0])
+        grads = (torch.empty(n, 2, device=dev), torch.empty(n, 3, device=dev),
+                 torch.empty(n, 3, device=dev), torch.empty(n, device=dev))
+        loss = torch.zeros((), dtype=torch.float64, device=dev)
+        graph = G.StepGraph(plan, mean, chol, color, opacity, ws, img, target, grads, loss)
+        for _ in range(3):
+            graph.launch()
+        torch.cuda.synchronize()
+        steps = max(5, args.steps // 5)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            graph.launch()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        if plan.diagnostics(ws)[1]:
+            raise SystemExit("pair capacity overflow (batched)")
+        graph.close()
+        out[name] = {"ms_per_step": round(ms, 4), "mp_s": round(hr_px / (ms * 1e-3) / 1e6, 2),
+                     "tile_pairs": pairs, "steps": steps, "config": cfg}
+        del ws, img, grads
+    out["launch"] = "each step captured as one HIP graph, replayed"
+    return out
+
+
 def pruned_comparison(args, G, synth, torch, np):
     """Exact vs surrogate-pruned fwd+bwd on a wide-sigma DIV2K-sized workload:
     train the radius network on labels the exact rasterizer measures on 10k
@@ -211,6 +266,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pruned", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--pruned-workload", default="config2a", choices=["config2a", "config2b"])
     ap.add_argument("--calibration-copy", type=int, default=0, metavar="MIB",
                     help="finish with 5 plain device-to-device copies of MIB MiB (a known "
@@ -314,6 +370,11 @@ def main():
         pruned = pruned_comparison(args, G, synth, torch, np)
         log(f"pruned: {pruned['pruned']['mp_s']} vs exact {pruned['exact']['mp_s']} MP/s "
             f"({pruned['speedup']}x) at {pruned['pruned']['psnr_db']} dB")
+    batched = None
+    if not args.no_batched:
+        batched = batched_uneven(args, G, synth, torch, np)
+        log(f"batched: tuned {batched['tuned']['mp_s']} MP/s, default launch "
+            f"{batched['default_launch']['mp_s']} MP/s")
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline")
@@ -329,6 +390,7 @@ def main():
                    "support_pairs": n_support,
                    "launch": "whole step captured in one HIP graph, replayed"},
         "roofline": roofline, "cpu_baseline": cpu, "surrogate_pruned": pruned,
+        "batched_uneven": batched,
     }
     print(json.dumps(rec), flush=True)
     if args.calibration_copy > 0:

@@ -75,16 +75,23 @@ typedef struct {
 /* Launch configuration.  Zero fields take defaults. */
 typedef struct {
     int32_t tile;          /* square HR tile side: 8, 16 (default) or 32     */
-    int32_t lds_batch;     /* Gaussians staged in LDS per round: 64, 128 or
-                              256 (default 256; at most the tile's threads)  */
-    int32_t flags;         /* GS_FLAG_*                                      */
+    int32_t lds_batch;     /* Gaussians the forward stages in LDS per round:
+                              tile 8: 32 or 64 (default 64); tile 16: 64,
+                              128 (default) or 256; tile 32: 32 (default) or
+                              64.  The image does not depend on it.          */
+    int32_t flags;         /* GS_FLAG_* (other bits: GS_E_INVALID)           */
     int32_t reserved;
     int64_t pair_capacity; /* max (tile, Gaussian) pairs the workspace holds;
                               0 = n_gauss * 16 (use gs_count_pairs to size)  */
 } gs_config;
 
 /* flags */
-#define GS_FLAG_PERSISTENT 0x1   /* render with persistent work-queue kernels */
+#define GS_FLAG_PERSISTENT 0x1   /* tile kernels run persistent: a grid of as
+                                    many workgroups as fit on the device takes
+                                    tiles from a device work counter, longest
+                                    list first (the binning builds that order).
+                                    Results are bitwise those of the default
+                                    one-workgroup-per-tile launch.            */
 #define GS_FLAG_ATOMIC_GRADS 0x2 /* backward: one FP32 global atomic per (tile,
                                     Gaussian, sum) instead of per-pair partial
                                     sums reduced in a fixed order (default)    */
@@ -146,9 +153,12 @@ gs_status gs_raster_render(const gs_config* cfg, const gs_image* images, int32_t
  * (device, same layout as out).  Uses the workspace left by the forward of
  * the same inputs.  Writes (overwrites) dL/d(mean) [n][2], dL/d(chol) [n][3],
  * dL/d(color) [n][3] and dL/d(opacity) [n] (all device).  The support box is
- * held fixed (its derivative is zero almost everywhere).  Per-tile partial
- * sums are reduced in LDS before FP32 global atomics, so the result is not
- * bitwise deterministic. */
+ * held fixed (its derivative is zero almost everywhere).  Each tile reduces
+ * its (tile, Gaussian) sums in registers and LDS and stores them per pair;
+ * the gradient stage adds a Gaussian's pairs in a fixed order, so the result
+ * is bitwise deterministic (with GS_FLAG_ATOMIC_GRADS the tiles add into
+ * per-Gaussian FP32 accumulators with global atomics instead: not bitwise
+ * deterministic). */
 gs_status gs_raster_backward(const gs_config* cfg, const gs_image* images, int32_t n_img,
                              const float* mean, const float* chol, const float* color,
                              const float* opacity, const float* radius, int64_t n_gauss,
@@ -157,9 +167,10 @@ gs_status gs_raster_backward(const gs_config* cfg, const gs_image* images, int32
                              float* grad_opacity, void* stream);
 
 /* First stage of gs_raster_backward: the per-tile backward render (one
- * kernel).  Accumulates, per Gaussian, the eight sums the gradients are made
- * of into the workspace (they start at zero after a forward and after every
- * gs_raster_gradients).  grad_out: device, layout of out. */
+ * kernel).  Stores, per (tile, Gaussian) pair, the eight sums the gradients
+ * are made of in the workspace (with GS_FLAG_ATOMIC_GRADS: adds them into
+ * per-Gaussian accumulators, which start at zero after a forward and after
+ * every gs_raster_gradients).  grad_out: device, layout of out. */
 gs_status gs_raster_render_backward(const gs_config* cfg, const gs_image* images,
                                     int32_t n_img, int64_t n_gauss, void* workspace,
                                     size_t ws_bytes, const float* grad_out, void* stream);
@@ -236,6 +247,19 @@ gs_status gs_tile_lists(const gs_config* cfg, const gs_image* images, int32_t n_
                         int64_t n_gauss, const void* workspace, size_t ws_bytes,
                         int32_t* ranges_host, int32_t* gids_host, int64_t max_pairs,
                         int64_t* n_tiles_out, int64_t* n_pairs_out, void* stream);
+
+/* Synchronising.  The work order of the persistent tile kernels written by
+ * the last gs_raster_bin / gs_raster_forward in this workspace with
+ * GS_FLAG_PERSISTENT: order_host [n_tiles] receives every tile id once,
+ * longest list first (longest-processing-time order of a batch of uneven
+ * images; lists of equal length bucket keep ascending tile id), and *ordered
+ * is 1 when that order is complete (0 after a binning without the flag, in
+ * which case the persistent kernels take tiles in id order).  order_host may
+ * be NULL; max_tiles is its length (GS_E_INVALID if below n_tiles). */
+gs_status gs_tile_order(const gs_config* cfg, const gs_image* images, int32_t n_img,
+                        int64_t n_gauss, const void* workspace, size_t ws_bytes,
+                        uint32_t* order_host, int64_t max_tiles, int32_t* ordered,
+                        void* stream);
 
 /* ---- learned support radius (pruned rasterization) ----------------------
  *

@@ -29,7 +29,7 @@ EXPORTED = (
     "gs_raster_render_backward", "gs_raster_gradients", "gs_raster_render_backward_l1",
     "gs_l1_loss_value", "gs_raster_backward_l1", "gs_graph_create", "gs_graph_launch",
     "gs_graph_destroy", "gs_mlp_features", "gs_mlp_forward", "gs_mlp_workspace_size",
-    "gs_mlp_grad", "gs_mlp_adam", "gs_radius_stats", "gs_sq_error",
+    "gs_mlp_grad", "gs_mlp_adam", "gs_radius_stats", "gs_sq_error", "gs_tile_order",
 )
 
 
@@ -93,6 +93,9 @@ def lib():
         L.gs_tile_lists.argtypes = [_cfgp, _imgp, _i32, _i64, _vp, _sz, _vp, _vp, _i64,
                                     ctypes.POINTER(_i64), ctypes.POINTER(_i64), _vp]
         L.gs_tile_lists.restype = _i32
+        L.gs_tile_order.argtypes = [_cfgp, _imgp, _i32, _i64, _vp, _sz, _vp, _i64,
+                                    ctypes.POINTER(_i32), _vp]
+        L.gs_tile_order.restype = _i32
         L.gs_raster_bin.argtypes = [_cfgp, _imgp, _i32, _vp, _vp, _vp, _vp, _vp, _i64, _vp,
                                     _sz, _vp]
         L.gs_raster_bin.restype = _i32

@@ -36,10 +36,17 @@ gs_status make_layout(const gs_config* cfg, const gs_image* images, int32_t n_im
     Layout l;
     l.tile = (cfg && cfg->tile) ? cfg->tile : 16;
     if (l.tile != 8 && l.tile != 16 && l.tile != 32) return GS_E_UNSUPPORTED;
-    const int threads = l.tile * l.tile >= 256 ? 256 : l.tile * l.tile;
-    l.lds_batch = (cfg && cfg->lds_batch) ? cfg->lds_batch : threads;
-    if (l.lds_batch != threads) return GS_E_UNSUPPORTED;
+    // forward LDS batch: per tile size, the staged Gaussians per round whose
+    // per-block record lists fit the LDS next to a useful occupancy
+    const int dflt = l.tile == 8 ? 64 : (l.tile == 16 ? 128 : 32);
+    l.lds_batch = (cfg && cfg->lds_batch) ? cfg->lds_batch : dflt;
+    const bool ok_batch = (l.tile == 8 && (l.lds_batch == 32 || l.lds_batch == 64)) ||
+                          (l.tile == 16 && (l.lds_batch == 64 || l.lds_batch == 128 ||
+                                            l.lds_batch == 256)) ||
+                          (l.tile == 32 && (l.lds_batch == 32 || l.lds_batch == 64));
+    if (!ok_batch) return GS_E_UNSUPPORTED;
     l.flags = cfg ? cfg->flags : 0;
+    if (l.flags & ~(GS_FLAG_PERSISTENT | GS_FLAG_ATOMIC_GRADS)) return GS_E_INVALID;
     l.n_img = n_img;
     l.n_gauss = n_gauss;
 
@@ -83,6 +90,7 @@ gs_status make_layout(const gs_config* cfg, const gs_image* images, int32_t n_im
     l.n_passes = (bits + kRadixBits - 1) / kRadixBits;
     l.nblk_g = (int32_t)std::max<int64_t>(1, (n_gauss + kBlockG - 1) / kBlockG);
     l.nblk_sort = (int32_t)std::max<int64_t>(1, (cap + kSortTile - 1) / kSortTile);
+    l.nblk_order = (int32_t)std::max<int64_t>(1, (tiles + kSortTile - 1) / kSortTile);
 
     // Capacity-independent sections first, so a small workspace can run the
     // counting kernels of a larger layout.
@@ -96,6 +104,9 @@ gs_status make_layout(const gs_config* cfg, const gs_image* images, int32_t n_im
     l.off_ranges = off; off = align_up(off + sizeof(int2) * (size_t)tiles);
     l.off_moments = off; off = align_up(off + sizeof(float) * 8 * (size_t)n_gauss);
     l.off_tile_loss = off; off = align_up(off + sizeof(double) * (size_t)tiles);
+    l.off_order = off; off = align_up(off + sizeof(uint32_t) * (size_t)tiles);
+    l.off_order_hist = off;
+    off = align_up(off + sizeof(int32_t) * ((size_t)kRadix * l.nblk_order + kRadix));
     l.off_keys0 = off; off = align_up(off + sizeof(uint32_t) * (size_t)cap);
     l.off_vals0 = off; off = align_up(off + sizeof(uint32_t) * (size_t)cap);
     l.off_keys1 = off; off = align_up(off + sizeof(uint32_t) * (size_t)cap);
@@ -142,6 +153,7 @@ gs_status run_binning(const Layout& L, const Ws& w, const std::vector<ImgDev>& t
     GS_TRY(dev(launch_emit(L, w, st)));
     GS_TRY(dev(launch_sort(L, w, st)));
     GS_TRY(dev(launch_ranges(L, w, st)));
+    if (L.flags & GS_FLAG_PERSISTENT) GS_TRY(dev(launch_order(L, w, st)));
     return GS_OK;
 }
 
@@ -472,7 +484,7 @@ gs_status gs_graph_create(const gs_config* cfg, const gs_image* images, int32_t 
     GS_TRY(dev(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)));
     gs_status st = GS_OK;
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-        hipStreamDestroy(cs);
+        (void)hipStreamDestroy(cs);
         return GS_E_DEVICE;
     }
     st = gs_raster_forward(cfg, images, n_img, mean, chol, color, opacity, radius, n_gauss,
@@ -483,20 +495,20 @@ gs_status gs_graph_create(const gs_config* cfg, const gs_image* images, int32_t 
                                    grad_opacity, loss, cs);
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(cs, &g);
-    hipStreamDestroy(cs);
+    (void)hipStreamDestroy(cs);
     if (st != GS_OK || ec != hipSuccess || !g) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return st != GS_OK ? st : GS_E_DEVICE;
     }
     hipGraphExec_t ex = nullptr;
     if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
-        hipGraphDestroy(g);
+        (void)hipGraphDestroy(g);
         return GS_E_DEVICE;
     }
     gs_graph h = new (std::nothrow) gs_graph_s;
     if (!h) {
-        hipGraphExecDestroy(ex);
-        hipGraphDestroy(g);
+        (void)hipGraphExecDestroy(ex);
+        (void)hipGraphDestroy(g);
         return GS_E_DEVICE;
     }
     h->graph = g;
@@ -544,6 +556,27 @@ gs_status gs_tile_lists(const gs_config* cfg, const gs_image* images, int32_t n_
                                   hipMemcpyDeviceToHost, st)));
     }
     return dev(hipStreamSynchronize(st));
+}
+
+gs_status gs_tile_order(const gs_config* cfg, const gs_image* images, int32_t n_img,
+                        int64_t n_gauss, const void* workspace, size_t ws_bytes,
+                        uint32_t* order_host, int64_t max_tiles, int32_t* ordered,
+                        void* stream) {
+    Layout L;
+    std::vector<ImgDev> table;
+    GS_TRY(make_layout(cfg, images, n_img, n_gauss, &L, &table));
+    if (!workspace || ws_bytes < L.total) return GS_E_WORKSPACE;
+    if (order_host && max_tiles < L.n_tiles) return GS_E_INVALID;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const char* b = static_cast<const char*>(workspace);
+    WsHeader h;
+    GS_TRY(dev(hipMemcpyAsync(&h, b + L.off_header, sizeof h, hipMemcpyDeviceToHost, st)));
+    if (order_host)
+        GS_TRY(dev(hipMemcpyAsync(order_host, b + L.off_order, sizeof(uint32_t) * L.n_tiles,
+                                  hipMemcpyDeviceToHost, st)));
+    GS_TRY(dev(hipStreamSynchronize(st)));
+    if (ordered) *ordered = h.ordered;
+    return GS_OK;
 }
 
 }  // extern "C"

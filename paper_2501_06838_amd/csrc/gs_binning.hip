@@ -224,6 +224,8 @@ __global__ __launch_bounds__(kBlockG) void k_scan_blocks(BlockSums* __restrict__
         hdr->overflow = carry > cap ? 1 : 0;
         hdr->n_support = a;
         hdr->n_invalid = b;
+        for (int k = 0; k < 4; ++k) hdr->work[k] = 0;
+        hdr->ordered = 0;
     }
 }
 
@@ -263,6 +265,9 @@ __global__ __launch_bounds__(kBlockG) void k_emit(
             hdr->overflow = total > cap ? 1 : 0;
             hdr->n_support = sa;
             hdr->n_invalid = sb;
+            for (int k = 0; k < 4; ++k) hdr->work[k] = 0;
+            hdr->ordered = 0;
+        hdr->ordered = 0;
         }
     } else {
         base = bs[blockIdx.x].pairs;  // scanned by k_scan_blocks
@@ -293,21 +298,77 @@ __device__ __forceinline__ int64_t pairs_in_use(const WsHeader* hdr, int64_t cap
     return p < cap ? p : cap;
 }
 
-// Per sort block: histogram of the digit at `shift`.  hist is digit-major:
+// Sort sources.  PairDigits: the (tile, Gaussian) pairs, keyed by the 8-bit
+// digit of the tile id at `shift`.  TileDigits: the tiles themselves, keyed
+// by the bucket of their list length, longest first (the longest-processing-
+// time order the persistent tile kernels take their work in).
+struct PairDigits {
+    const uint32_t* keys;
+    const uint32_t* vals;
+    const WsHeader* hdr;
+    int64_t cap;
+    int shift;
+    __device__ __forceinline__ int64_t count() const { return pairs_in_use(hdr, cap); }
+    __device__ __forceinline__ int digit(int64_t i) const {
+        return (int)((keys[i] >> shift) & (kRadix - 1));
+    }
+    __device__ __forceinline__ void load(int64_t i, int* d, uint32_t* a, uint32_t* b) const {
+        *a = keys[i];
+        *b = vals[i];
+        *d = (int)((*a >> shift) & (kRadix - 1));
+    }
+};
+struct PairSink {
+    uint32_t* keys;
+    uint32_t* vals;
+    __device__ __forceinline__ void store(int64_t pos, uint32_t a, uint32_t b) const {
+        keys[pos] = a;
+        vals[pos] = b;
+    }
+};
+
+// List length -> digit: lengths 0..127 one bucket each, then buckets 16 wide,
+// everything from 2160 on in the last; digit 255 - bucket puts long lists first.
+__device__ __forceinline__ int length_digit(int len) {
+    const int b = len < 128 ? len : min(255, 128 + ((len - 128) >> 4));
+    return (kRadix - 1) - b;
+}
+struct TileDigits {
+    const int2* ranges;
+    int64_t n_tiles;
+    __device__ __forceinline__ int64_t count() const { return n_tiles; }
+    __device__ __forceinline__ int digit(int64_t i) const {
+        const int2 r = ranges[i];
+        return length_digit(r.y - r.x);
+    }
+    __device__ __forceinline__ void load(int64_t i, int* d, uint32_t* a, uint32_t* b) const {
+        *d = digit(i);
+        *a = (uint32_t)i;
+        *b = 0;
+    }
+};
+struct OrderSink {
+    uint32_t* order;
+    __device__ __forceinline__ void store(int64_t pos, uint32_t a, uint32_t) const {
+        order[pos] = a;
+    }
+};
+
+// Per sort block: histogram of the digits.  hist is digit-major:
 // hist[d * nblk + b].
-__global__ __launch_bounds__(kSortThreads) void k_sort_hist(
-    const uint32_t* __restrict__ keys, const WsHeader* __restrict__ hdr, int64_t cap,
-    int shift, int nblk, int32_t* __restrict__ hist) {
+template <typename Src>
+__global__ __launch_bounds__(kSortThreads) void k_sort_hist(Src src, int nblk,
+                                                            int32_t* __restrict__ hist) {
     __shared__ int32_t cnt[kRadix];
     const int t = threadIdx.x;
     cnt[t] = 0;
     __syncthreads();
-    const int64_t P = pairs_in_use(hdr, cap);
+    const int64_t P = src.count();
     const int64_t start = (int64_t)blockIdx.x * kSortTile;
 #pragma unroll
     for (int k = 0; k < kSortItems; ++k) {
         const int64_t idx = start + (int64_t)k * kSortThreads + t;
-        if (idx < P) atomicAdd(&cnt[(keys[idx] >> shift) & (kRadix - 1)], 1);
+        if (idx < P) atomicAdd(&cnt[src.digit(idx)], 1);
     }
     __syncthreads();
     hist[(int64_t)t * nblk + blockIdx.x] = cnt[t];
@@ -335,20 +396,19 @@ __global__ __launch_bounds__(kBlockG) void k_sort_rowscan(int32_t* __restrict__ 
     if (threadIdx.x == 0) totals[blockIdx.x] = (int32_t)carry;
 }
 
-// Stable scatter of one sort block.  Keys are ranked 256 at a time in index
+// Stable scatter of one sort block.  Items are ranked 256 at a time in index
 // order: within a wave by matching the digit bit by bit with ballots, across
 // the block's four waves through LDS counts.
+template <typename Src, typename Dst>
 __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
-    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
-    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
-    const int32_t* __restrict__ hist, const int32_t* __restrict__ totals,
-    const WsHeader* __restrict__ hdr, int64_t cap, int shift, int nblk) {
+    Src src, Dst dst, const int32_t* __restrict__ hist, const int32_t* __restrict__ totals,
+    int nblk) {
     constexpr int kWaves = kSortThreads / 64;
     __shared__ int32_t base[kRadix];
     __shared__ int32_t wcnt[kWaves][kRadix];
     __shared__ int64_t tmp[kBlockG / 64];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int64_t P = pairs_in_use(hdr, cap);
+    const int64_t P = src.count();
     const int64_t start = (int64_t)blockIdx.x * kSortTile;
     if (start >= P) return;  // uniform per block
 
@@ -365,15 +425,15 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
     for (int round = 0; round < kSortItems; ++round) {
         const int64_t idx = start + (int64_t)round * kSortThreads + t;
         const bool valid = idx < P;
-        uint32_t key = 0, val = 0;
-        if (valid) { key = keys_in[idx]; val = vals_in[idx]; }
-        const int d = (key >> shift) & (kRadix - 1);
+        uint32_t a = 0, b = 0;
+        int d = 0;
+        if (valid) src.load(idx, &d, &a, &b);
         uint64_t peers = __ballot(valid);
 #pragma unroll
-        for (int b = 0; b < kRadixBits; ++b) {
-            const bool bit = (d >> b) & 1;
-            const uint64_t bal = __ballot(bit);
-            peers &= bit ? bal : ~bal;
+        for (int bit = 0; bit < kRadixBits; ++bit) {
+            const bool on = (d >> bit) & 1;
+            const uint64_t bal = __ballot(on);
+            peers &= on ? bal : ~bal;
         }
         const int rank = __popcll(peers & lt_mask);
         if (valid && rank == 0) wcnt[wave][d] = __popcll(peers);
@@ -381,8 +441,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
         if (valid) {
             int pos = base[d] + rank;
             for (int k = 0; k < wave; ++k) pos += wcnt[k][d];
-            keys_out[pos] = key;
-            vals_out[pos] = val;
+            dst.store(pos, a, b);
         }
         __syncthreads();
         int add = 0;
@@ -391,6 +450,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
         __syncthreads();
     }
 }
+
+__global__ void k_mark_ordered(WsHeader* __restrict__ hdr) { hdr->ordered = 1; }
 
 // One thread per sorted pair: tile range boundaries, and the pair's render
 // record (the Gaussian's record located in its tile).
@@ -493,15 +554,30 @@ hipError_t launch_sort(const Layout& L, const Ws& w, hipStream_t st) {
     int32_t* totals = w.hist + (int64_t)kRadix * L.nblk_sort;
     for (int pass = 0; pass < L.n_passes; ++pass) {
         const int src = pass & 1, dst = src ^ 1;
-        const int shift = pass * kRadixBits;
-        hipLaunchKernelGGL(k_sort_hist, dim3(L.nblk_sort), dim3(kSortThreads), 0, st,
-                           w.keys[src], w.hdr, L.cap, shift, L.nblk_sort, w.hist);
+        const PairDigits in{w.keys[src], w.vals[src], w.hdr, L.cap, pass * kRadixBits};
+        const PairSink out{w.keys[dst], w.vals[dst]};
+        hipLaunchKernelGGL(k_sort_hist<PairDigits>, dim3(L.nblk_sort), dim3(kSortThreads), 0, st,
+                           in, L.nblk_sort, w.hist);
         hipLaunchKernelGGL(k_sort_rowscan, dim3(kRadix), dim3(kBlockG), 0, st, w.hist,
                            L.nblk_sort, totals);
-        hipLaunchKernelGGL(k_sort_scatter, dim3(L.nblk_sort), dim3(kSortThreads), 0, st,
-                           w.keys[src], w.vals[src], w.keys[dst], w.vals[dst], w.hist,
-                           totals, w.hdr, L.cap, shift, L.nblk_sort);
+        hipLaunchKernelGGL((k_sort_scatter<PairDigits, PairSink>), dim3(L.nblk_sort),
+                           dim3(kSortThreads), 0, st, in, out, w.hist, totals, L.nblk_sort);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_order(const Layout& L, const Ws& w, hipStream_t st) {
+    if (L.n_tiles == 0) return hipSuccess;
+    int32_t* totals = w.order_hist + (int64_t)kRadix * L.nblk_order;
+    const TileDigits in{w.ranges, L.n_tiles};
+    hipLaunchKernelGGL(k_sort_hist<TileDigits>, dim3(L.nblk_order), dim3(kSortThreads), 0, st, in,
+                       L.nblk_order, w.order_hist);
+    hipLaunchKernelGGL(k_sort_rowscan, dim3(kRadix), dim3(kBlockG), 0, st, w.order_hist,
+                       L.nblk_order, totals);
+    hipLaunchKernelGGL((k_sort_scatter<TileDigits, OrderSink>), dim3(L.nblk_order),
+                       dim3(kSortThreads), 0, st, in, OrderSink{w.order}, w.order_hist, totals,
+                       L.nblk_order);
+    hipLaunchKernelGGL(k_mark_ordered, dim3(1), dim3(1), 0, st, w.hdr);
     return hipGetLastError();
 }
 

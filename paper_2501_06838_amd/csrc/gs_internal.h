@@ -82,8 +82,11 @@ struct WsHeader {
     int64_t n_invalid;    // Gaussians without support because of bad values
     int64_t n_support;    // in-support (pixel, Gaussian) pairs: sum of box areas
     int32_t overflow;     // n_pairs > capacity
-    int32_t pad0;
-    uint32_t work[4];     // persistent-kernel work counters
+    int32_t ordered;      // 1 once the tile order of this binning is complete
+    // persistent tile kernels: work[0] / work[1] next work item of the
+    // forward / backward, work[2] / work[3] their workgroups that have run
+    // out of work (the last one resets both, ready for the next launch)
+    uint32_t work[4];
 };
 
 // Host-side workspace layout for one batch shape.
@@ -98,6 +101,8 @@ struct Layout {
     int32_t nblk_g = 0;       // blocks of per-Gaussian kernels
     int32_t nblk_sort = 0;    // blocks of the sort at full capacity
     int32_t n_passes = 0;     // radix passes over the tile-id bits
+    int32_t nblk_order = 0;   // blocks of the tile-order sort
+    size_t off_order = 0, off_order_hist = 0;
     size_t off_header = 0, off_imgs = 0, off_recs = 0, off_counts = 0, off_offsets = 0,
            off_blocksums = 0, off_keys0 = 0, off_vals0 = 0, off_keys1 = 0, off_vals1 = 0,
            off_hist = 0, off_ranges = 0, off_moments = 0, off_tile_loss = 0, off_pairs = 0,
@@ -125,6 +130,8 @@ struct Ws {
     PairRec* pairs;
     uint32_t* inv;       // emission index -> sorted position
     float4* partials;    // per sorted pair: 8 backward sums (2 x float4)
+    uint32_t* order;     // tiles, longest list first (persistent kernels)
+    int32_t* order_hist; // histograms of the tile-order sort
 };
 
 inline Ws bind(const Layout& L, void* base) {
@@ -147,6 +154,8 @@ inline Ws bind(const Layout& L, void* base) {
     w.pairs = reinterpret_cast<PairRec*>(b + L.off_pairs);
     w.inv = reinterpret_cast<uint32_t*>(b + L.off_inv);
     w.partials = reinterpret_cast<float4*>(b + L.off_partials);
+    w.order = reinterpret_cast<uint32_t*>(b + L.off_order);
+    w.order_hist = reinterpret_cast<int32_t*>(b + L.off_order_hist);
     return w;
 }
 
@@ -178,6 +187,8 @@ hipError_t launch_support(const Layout& L, const Ws& w, const ImgDev* host_imgs,
 hipError_t launch_emit(const Layout& L, const Ws& w, hipStream_t st);
 hipError_t launch_sort(const Layout& L, const Ws& w, hipStream_t st);
 hipError_t launch_ranges(const Layout& L, const Ws& w, hipStream_t st);
+// Tile work order for the persistent kernels: longest list first.
+hipError_t launch_order(const Layout& L, const Ws& w, hipStream_t st);
 
 // ---- launchers (gs_render.hip) -------------------------------------------
 hipError_t launch_render_fwd(const Layout& L, const Ws& w, float* out, hipStream_t st);

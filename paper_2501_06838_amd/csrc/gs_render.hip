@@ -17,6 +17,8 @@
 // flushes them into the round's LDS accumulators when it leaves a Gaussian,
 // and the workgroup issues one FP32 global atomic per (tile, Gaussian,
 // moment).  The finalize kernel turns moments into parameter gradients.
+#include <algorithm>
+
 #include "gs_internal.h"
 
 namespace gs {
@@ -52,30 +54,54 @@ struct TileShape {
     static constexpr int kBatch = kThreads;
 };
 
-// Gaussians staged per forward round: the per-block lists hold a 48-byte
-// record per (8x8 block, Gaussian), NB * kFwdBatch of them in LDS.
+// Gaussians staged per forward round (lds_batch): the per-block lists hold a
+// 48-byte record per (8x8 block, Gaussian), NB * B of them in LDS.
 template <int T>
 struct FwdShape {
-    static constexpr int kBatch = T == 8 ? 64 : (T == 16 ? 128 : 32);
+    static constexpr int kDefaultBatch = T == 8 ? 64 : (T == 16 ? 128 : 32);
 };
 
-template <int T, typename Table>
-__global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_fwd(
-    Table imgs, int n_img, const PairRec* __restrict__ pairs,
-    const int2* __restrict__ ranges, float* __restrict__ out) {
-    using S = TileShape<T>;
-    constexpr int NB = S::kBlocks, B = FwdShape<T>::kBatch;
+template <int T, int B>
+struct FwdLds {
+    static constexpr int NB = TileShape<T>::kBlocks;
     // per 8x8 block j, compacted in ascending Gaussian order:
     //   l0 = {X origin of the block minus kx, same for Y, fx, fy}
     //   l1 = {a, e, g, A0},  l2 = {A1, A2, lane mask lo, lane mask hi}
-    __shared__ float4 l0[NB][B];
-    __shared__ float4 l1[NB][B];
-    __shared__ float4 l2[NB][B];
-    __shared__ int scount[NB];
-    __shared__ int wcount[S::kWaves][NB];
+    float4 l0[NB][B];
+    float4 l1[NB][B];
+    float4 l2[NB][B];
+    int scount[NB];
+    int wcount[TileShape<T>::kWaves][NB];
+};
 
+// Persistent tile kernels: the workgroup's first item is its own index, the
+// following ones come from a device counter; items index the longest-first
+// tile order.  Returns the next item (uniform over the workgroup).
+__device__ __forceinline__ int64_t next_item(uint32_t* counter, uint32_t* s_item) {
+    __syncthreads();  // every thread has read the previous item
+    if (threadIdx.x == 0) *s_item = gridDim.x + atomicAdd(counter, 1u);
+    __syncthreads();
+    return (int64_t)*s_item;
+}
+
+// Workgroup out of work: the last one to leave resets the counters.
+__device__ __forceinline__ void leave(uint32_t* counter, uint32_t* exited) {
+    if (threadIdx.x == 0) {
+        if (atomicAdd(exited, 1u) == gridDim.x - 1) {
+            atomicExch(counter, 0u);
+            atomicExch(exited, 0u);
+        }
+    }
+}
+
+template <int T, int B, typename Table>
+__device__ __forceinline__ void fwd_tile(FwdLds<T, B>& sm, const Table& imgs, int n_img,
+                                         const PairRec* __restrict__ pairs,
+                                         const int2* __restrict__ ranges,
+                                         float* __restrict__ out, int64_t tile) {
+    using S = TileShape<T>;
+    constexpr int NB = S::kBlocks;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int64_t tile = blockIdx.x;
     const int k_img = tile_image(imgs, n_img, tile);
     const ImgDev im = imgs[k_img];
     const int64_t lt = tile - im.tile_base;
@@ -112,7 +138,7 @@ __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_fwd(
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
             const uint64_t bal = __ballot(my_mask[j] != 0);
-            if (lane == 0) wcount[wave][j] = __popcll(bal);
+            if (lane == 0) sm.wcount[wave][j] = __popcll(bal);
         }
         __syncthreads();
 #pragma unroll
@@ -120,32 +146,32 @@ __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_fwd(
             const uint64_t bal = __ballot(my_mask[j] != 0);
             if (my_mask[j] != 0) {
                 int pos = __popcll(bal & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
-                for (int w = 0; w < wave; ++w) pos += wcount[w][j];
+                for (int w = 0; w < wave; ++w) pos += sm.wcount[w][j];
                 const int bx = (j % S::kBlocksX) * 8, by = (j / S::kBlocksX) * 8;
-                l0[j][pos] = make_float4(r.kxr + (float)bx, r.kyr + (float)by, r.fx, r.fy);
-                l1[j][pos] = make_float4(r.a, r.e, r.g, r.A[0]);
-                l2[j][pos] = make_float4(r.A[1], r.A[2], __uint_as_float((uint32_t)my_mask[j]),
-                                         __uint_as_float((uint32_t)(my_mask[j] >> 32)));
+                sm.l0[j][pos] = make_float4(r.kxr + (float)bx, r.kyr + (float)by, r.fx, r.fy);
+                sm.l1[j][pos] = make_float4(r.a, r.e, r.g, r.A[0]);
+                sm.l2[j][pos] = make_float4(r.A[1], r.A[2], __uint_as_float((uint32_t)my_mask[j]),
+                                            __uint_as_float((uint32_t)(my_mask[j] >> 32)));
             }
         }
         if (t < NB) {
             int c = 0;
-            for (int w = 0; w < S::kWaves; ++w) c += wcount[w][t];
-            scount[t] = c;
+            for (int w = 0; w < S::kWaves; ++w) c += sm.wcount[w][t];
+            sm.scount[t] = c;
         }
         __syncthreads();
 
 #pragma unroll
         for (int m = 0; m < S::kBlocksPerWave; ++m) {
             const int j = wave + S::kWaves * m;
-            const int cnt = scount[j];
+            const int cnt = sm.scount[j];
             if (cnt == 0) continue;
             // records are read one iteration ahead (fixed stride, no indirection)
-            float4 a0 = l0[j][0], a1 = l1[j][0], a2 = l2[j][0];
+            float4 a0 = sm.l0[j][0], a1 = sm.l1[j][0], a2 = sm.l2[j][0];
             for (int q = 0; q < cnt; ++q) {
                 const float4 c0 = a0, c1 = a1, c2 = a2;
                 const int qn = q + 1 < cnt ? q + 1 : q;
-                a0 = l0[j][qn]; a1 = l1[j][qn]; a2 = l2[j][qn];
+                a0 = sm.l0[j][qn]; a1 = sm.l1[j][qn]; a2 = sm.l2[j][qn];
                 const uint32_t mlo = __builtin_amdgcn_readfirstlane(__float_as_uint(c2.z));
                 const uint32_t mhi = __builtin_amdgcn_readfirstlane(__float_as_uint(c2.w));
                 const uint64_t mask = ((uint64_t)mhi << 32) | mlo;
@@ -179,27 +205,63 @@ __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_fwd(
     }
 }
 
+// One tile per workgroup (grid of n_tiles), or, with `persistent`, a grid
+// sized to the resident workgroups that walks the longest-first tile order.
+template <int T, int B, typename Table>
+__global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_fwd(
+    Table imgs, int n_img, const PairRec* __restrict__ pairs,
+    const int2* __restrict__ ranges, float* __restrict__ out,
+    const uint32_t* __restrict__ order, WsHeader* __restrict__ hdr, int64_t n_tiles,
+    int persistent) {
+    __shared__ FwdLds<T, B> sm;
+    __shared__ uint32_t s_item;
+    if (!persistent) {
+        fwd_tile<T, B>(sm, imgs, n_img, pairs, ranges, out, (int64_t)blockIdx.x);
+        return;
+    }
+    // without a tile order from the matching binning, items are tiles
+    const bool ordered = hdr->ordered != 0;
+    for (int64_t item = blockIdx.x; item < n_tiles; item = next_item(&hdr->work[0], &s_item)) {
+        const int64_t tile = ordered ? (int64_t)order[item] : item;
+        if (tile < n_tiles) fwd_tile<T, B>(sm, imgs, n_img, pairs, ranges, out, tile);
+    }
+    leave(&hdr->work[0], &hdr->work[2]);
+}
+
 // kL1: the upstream gradient is the L1 loss's, sign(out - target) / numel,
 // formed here from the rendered image and the target (it is never stored),
 // and the tile's share of sum |out - target| goes to tile_loss[tile].
+template <int T>
+struct BwdLds {
+    static constexpr int NT = TileShape<T>::kThreads, B = TileShape<T>::kBatch;
+    float4 gt[T * T];     // upstream gradient of the tile, {g0, g1, g2, 0}
+    float4 sq0[B];        // {X at box start, Y at box start, a, e}
+    float4 sq1[B];        // {g, A0, A1, A2}
+    int4 sq2[B];          // {first pixel index, box width, area, -}
+    int pfx[B + 1];
+    float acc[8][B];      // moment-major: lanes flushing different Gaussians hit different banks
+    int64_t tmp[NT / 64];
+    double lpart[NT / 64];
+};
+
 template <int T, bool kL1, typename Table>
-__global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_bwd(
-    Table imgs, int n_img, const PairRec* __restrict__ pairs,
+__device__ __forceinline__ void bwd_tile(
+    BwdLds<T>& sm, const Table& imgs, int n_img, const PairRec* __restrict__ pairs,
     const int2* __restrict__ ranges, const float* __restrict__ grad_out,
     const float* __restrict__ target, float inv_numel, double* __restrict__ tile_loss,
-    float* __restrict__ moments, float4* __restrict__ partials, int atomic_grads) {
+    float* __restrict__ moments, float4* __restrict__ partials, int atomic_grads,
+    int64_t tile) {
     using S = TileShape<T>;
     constexpr int NT = S::kThreads, B = S::kBatch;
-    __shared__ float4 gt[T * T];     // upstream gradient of the tile, {g0, g1, g2, 0}
-    __shared__ float4 sq0[B];        // {X at box start, Y at box start, a, e}
-    __shared__ float4 sq1[B];        // {g, A0, A1, A2}
-    __shared__ int4 sq2[B];          // {first pixel index, box width, area, -}
-    __shared__ int pfx[B + 1];
-    __shared__ float acc[8][B];      // moment-major: lanes flushing different Gaussians hit different banks
-    __shared__ int64_t tmp[NT / 64];
+    float4* gt = sm.gt;
+    float4* sq0 = sm.sq0;
+    float4* sq1 = sm.sq1;
+    int4* sq2 = sm.sq2;
+    int* pfx = sm.pfx;
+    auto& acc = sm.acc;
+    int64_t* tmp = sm.tmp;
 
     const int t = threadIdx.x;
-    const int64_t tile = blockIdx.x;
     const int k_img = tile_image(imgs, n_img, tile);
     const ImgDev im = imgs[k_img];
     const int64_t lt = tile - im.tile_base;
@@ -233,12 +295,11 @@ __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_bwd(
     }
     if (kL1) {
         for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o, 64);
-        __shared__ double lpart[NT / 64];
-        if ((t & 63) == 0) lpart[t >> 6] = lsum;
+        if ((t & 63) == 0) sm.lpart[t >> 6] = lsum;
         __syncthreads();
         if (t == 0) {
             double sum = 0.0;
-            for (int k = 0; k < NT / 64; ++k) sum += lpart[k];
+            for (int k = 0; k < NT / 64; ++k) sum += sm.lpart[k];
             tile_loss[tile] = sum;
         }
         if (rg.y <= rg.x) return;  // uniform
@@ -399,6 +460,31 @@ __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_bwd(
     }
 }
 
+template <int T, bool kL1, typename Table>
+__global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_bwd(
+    Table imgs, int n_img, const PairRec* __restrict__ pairs,
+    const int2* __restrict__ ranges, const float* __restrict__ grad_out,
+    const float* __restrict__ target, float inv_numel, double* __restrict__ tile_loss,
+    float* __restrict__ moments, float4* __restrict__ partials, int atomic_grads,
+    const uint32_t* __restrict__ order, WsHeader* __restrict__ hdr, int64_t n_tiles,
+    int persistent) {
+    __shared__ BwdLds<T> sm;
+    __shared__ uint32_t s_item;
+    if (!persistent) {
+        bwd_tile<T, kL1>(sm, imgs, n_img, pairs, ranges, grad_out, target, inv_numel, tile_loss,
+                         moments, partials, atomic_grads, (int64_t)blockIdx.x);
+        return;
+    }
+    const bool ordered = hdr->ordered != 0;
+    for (int64_t item = blockIdx.x; item < n_tiles; item = next_item(&hdr->work[1], &s_item)) {
+        const int64_t tile = ordered ? (int64_t)order[item] : item;
+        if (tile < n_tiles)
+            bwd_tile<T, kL1>(sm, imgs, n_img, pairs, ranges, grad_out, target, inv_numel,
+                             tile_loss, moments, partials, atomic_grads, tile);
+    }
+    leave(&hdr->work[1], &hdr->work[3]);
+}
+
 // Moments -> gradients, per Gaussian, in FP64.  With K = 1/(2 pi l11 l22),
 // w = exp(-(z1^2 + z2^2)/2), z1 = (x/s - mu_x)/l11,
 // z2 = ((y/s - mu_y) - l21 z1)/l22, H = sum_c A_c dL/dI_c:
@@ -525,30 +611,61 @@ hipError_t launch_sum_loss(const Layout& L, const Ws& w, int64_t numel, double* 
     return hipGetLastError();
 }
 
-template <typename Table>
-static hipError_t launch_fwd_t(const Layout& L, const Ws& w, const Table& tab, float* out,
-                               hipStream_t st) {
-    const dim3 grid((unsigned)L.n_tiles);
-    switch (L.tile) {
-        case 8:
-            hipLaunchKernelGGL((k_render_fwd<8, Table>), grid, dim3(TileShape<8>::kThreads), 0,
-                               st, tab, L.n_img, w.pairs, w.ranges, out);
-            break;
-        case 16:
-            hipLaunchKernelGGL((k_render_fwd<16, Table>), grid, dim3(TileShape<16>::kThreads), 0,
-                               st, tab, L.n_img, w.pairs, w.ranges, out);
-            break;
-        case 32:
-            hipLaunchKernelGGL((k_render_fwd<32, Table>), grid, dim3(TileShape<32>::kThreads), 0,
-                               st, tab, L.n_img, w.pairs, w.ranges, out);
-            break;
-        default:
-            return hipErrorInvalidValue;
-    }
+// Grid of a tile kernel: one workgroup per tile, or, persistent, as many as
+// fit on the device at once (never more than the tiles).
+static hipError_t tile_grid(const Layout& L, const void* kernel, int threads, unsigned* grid) {
+    *grid = (unsigned)L.n_tiles;
+    if (!(L.flags & GS_FLAG_PERSISTENT)) return hipSuccess;
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0);
+    if (e != hipSuccess) return e;
+    const int64_t resident = (int64_t)std::max(cus, 1) * std::max(per_cu, 1);
+    *grid = (unsigned)std::min<int64_t>(L.n_tiles, resident);
+    return hipSuccess;
+}
+
+template <int T, int B, typename Table>
+static hipError_t launch_fwd_tb(const Layout& L, const Ws& w, const Table& tab, float* out,
+                                hipStream_t st) {
+    const auto kernel = k_render_fwd<T, B, Table>;
+    unsigned grid = 0;
+    const hipError_t e = tile_grid(L, reinterpret_cast<const void*>(kernel),
+                                   TileShape<T>::kThreads, &grid);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(TileShape<T>::kThreads), 0, st, tab, L.n_img,
+                       w.pairs, w.ranges, out, w.order, w.hdr, L.n_tiles,
+                       (L.flags & GS_FLAG_PERSISTENT) ? 1 : 0);
     return hipGetLastError();
 }
 
+template <typename Table>
+static hipError_t launch_fwd_t(const Layout& L, const Ws& w, const Table& tab, float* out,
+                               hipStream_t st) {
+    const int b = L.lds_batch;
+    switch (L.tile) {
+        case 8:
+            if (b == 32) return launch_fwd_tb<8, 32>(L, w, tab, out, st);
+            if (b == 64) return launch_fwd_tb<8, 64>(L, w, tab, out, st);
+            break;
+        case 16:
+            if (b == 64) return launch_fwd_tb<16, 64>(L, w, tab, out, st);
+            if (b == 128) return launch_fwd_tb<16, 128>(L, w, tab, out, st);
+            if (b == 256) return launch_fwd_tb<16, 256>(L, w, tab, out, st);
+            break;
+        case 32:
+            if (b == 32) return launch_fwd_tb<32, 32>(L, w, tab, out, st);
+            if (b == 64) return launch_fwd_tb<32, 64>(L, w, tab, out, st);
+            break;
+        default:
+            break;
+    }
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_render_fwd(const Layout& L, const Ws& w, float* out, hipStream_t st) {
+    if (L.n_tiles == 0) return hipSuccess;
     if (L.n_img <= kSetupChunk && L.host_imgs) {
         ArgTable tab;
         for (int k = 0; k < kSetupChunk; ++k) tab.c.img[k] = k < L.n_img ? L.host_imgs[k] : ImgDev{};
@@ -557,37 +674,38 @@ hipError_t launch_render_fwd(const Layout& L, const Ws& w, float* out, hipStream
     return launch_fwd_t(L, w, MemTable{w.imgs}, out, st);
 }
 
+template <int T, bool kL1, typename Table>
+static hipError_t launch_bwd_tt(const Layout& L, const Ws& w, const Table& tab,
+                                const float* grad_out, const float* target, float inv_numel,
+                                hipStream_t st) {
+    const auto kernel = k_render_bwd<T, kL1, Table>;
+    unsigned grid = 0;
+    const hipError_t e = tile_grid(L, reinterpret_cast<const void*>(kernel),
+                                   TileShape<T>::kThreads, &grid);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(TileShape<T>::kThreads), 0, st, tab, L.n_img,
+                       w.pairs, w.ranges, grad_out, target, inv_numel, w.tile_loss, w.moments,
+                       w.partials, (L.flags & GS_FLAG_ATOMIC_GRADS) ? 1 : 0, w.order, w.hdr,
+                       L.n_tiles, (L.flags & GS_FLAG_PERSISTENT) ? 1 : 0);
+    return hipGetLastError();
+}
+
 template <bool kL1, typename Table>
 static hipError_t launch_bwd_t(const Layout& L, const Ws& w, const Table& tab,
                                const float* grad_out, const float* target, float inv_numel,
                                hipStream_t st) {
-    const dim3 grid((unsigned)L.n_tiles);
-    const int atomic = (L.flags & GS_FLAG_ATOMIC_GRADS) ? 1 : 0;
     switch (L.tile) {
-        case 8:
-            hipLaunchKernelGGL((k_render_bwd<8, kL1, Table>), grid, dim3(TileShape<8>::kThreads),
-                               0, st, tab, L.n_img, w.pairs, w.ranges, grad_out, target,
-                               inv_numel, w.tile_loss, w.moments, w.partials, atomic);
-            break;
-        case 16:
-            hipLaunchKernelGGL((k_render_bwd<16, kL1, Table>), grid,
-                               dim3(TileShape<16>::kThreads), 0, st, tab, L.n_img, w.pairs,
-                               w.ranges, grad_out, target, inv_numel, w.tile_loss, w.moments, w.partials, atomic);
-            break;
-        case 32:
-            hipLaunchKernelGGL((k_render_bwd<32, kL1, Table>), grid,
-                               dim3(TileShape<32>::kThreads), 0, st, tab, L.n_img, w.pairs,
-                               w.ranges, grad_out, target, inv_numel, w.tile_loss, w.moments, w.partials, atomic);
-            break;
-        default:
-            return hipErrorInvalidValue;
+        case 8: return launch_bwd_tt<8, kL1>(L, w, tab, grad_out, target, inv_numel, st);
+        case 16: return launch_bwd_tt<16, kL1>(L, w, tab, grad_out, target, inv_numel, st);
+        case 32: return launch_bwd_tt<32, kL1>(L, w, tab, grad_out, target, inv_numel, st);
+        default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 template <bool kL1>
 static hipError_t launch_bwd_any(const Layout& L, const Ws& w, const float* grad_out,
                                  const float* target, float inv_numel, hipStream_t st) {
+    if (L.n_tiles == 0) return hipSuccess;
     if (L.n_img <= kSetupChunk && L.host_imgs) {
         ArgTable tab;
         for (int k = 0; k < kSetupChunk; ++k) tab.c.img[k] = k < L.n_img ? L.host_imgs[k] : ImgDev{};

@@ -272,6 +272,19 @@ class RasterPlan:
         return ranges, gids[:npairs.value]
 
 
+    def tile_order(self, workspace, stream=None, capacity=None):
+        """(order [n_tiles] uint32, ordered flag) of the persistent kernels."""
+        import numpy as np
+        cfg = self.config(capacity)
+        order = np.zeros(self.n_tiles, dtype=np.uint32)
+        flag = ctypes.c_int32()
+        N.check(N.lib().gs_tile_order(ctypes.byref(cfg), self._arr, len(self.images),
+                                      self.n_gauss, _ptr(workspace), workspace.numel(),
+                                      order.ctypes.data_as(ctypes.c_void_p), order.size,
+                                      ctypes.byref(flag), _stream(stream)), "tile order")
+        return order, flag.value
+
+
 class StepGraph:
     """A captured HIP graph of one forward (+ fused L1 backward) pass over a
     plan's batch with fixed buffers; ``launch()`` replays it on the current

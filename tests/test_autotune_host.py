@@ -1,0 +1,58 @@
+"""Launch-configuration space and autotuner cache (host only, no device calls)."""
+import ctypes
+import json
+
+import pytest
+
+
+def _ws(tile, batch, flags=0):
+    from paper_2501_06838_amd import _native as N
+    arr = (N.gs_image * 2)(N.gs_image(40, 30, 3.3, 0, 1200, 0),
+                           N.gs_image(17, 90, 11.5, 1200, 1530, 3 * 132 * 99))
+    cfg = N.gs_config(tile, batch, flags, 0, 0)
+    b = ctypes.c_size_t()
+    return N.lib().gs_workspace_size(ctypes.byref(cfg), arr, 2, 2730, ctypes.byref(b))
+
+
+def test_every_candidate_is_accepted_and_others_are_not():
+    from paper_2501_06838_amd import _native as N
+    from paper_2501_06838_amd.autotune import TILE_BATCHES, candidates
+    for c in candidates():
+        assert _ws(c["tile"], c["lds_batch"], c["flags"]) == N.GS_OK, c
+    assert len(candidates()) == 2 * len(TILE_BATCHES)
+    for tile in (8, 16, 32):
+        for batch in (16, 32, 48, 64, 128, 256, 512):
+            ok = (tile, batch) in TILE_BATCHES
+            assert (_ws(tile, batch) == N.GS_OK) == ok, (tile, batch)
+        assert _ws(tile, 0) == N.GS_OK   # default batch
+    assert _ws(16, 0, 0x4) == N.GS_E_INVALID  # unknown flag bit
+
+
+def test_layout_key_depends_on_layout_and_device():
+    from paper_2501_06838_amd.autotune import layout_key
+    a = [(64, 64, 3.7, 0, 4096)] * 3
+    assert layout_key(a, "gfx950") == layout_key([tuple(x) for x in a], "gfx950")
+    assert layout_key(a, "gfx950") != layout_key(a, "other")
+    b = [(64, 64, 3.7000001, 0, 4096)] * 3
+    assert layout_key(a, "gfx950") != layout_key(b, "gfx950")
+    c = [(64, 64, 3.7, 0, 4096)] * 2
+    assert layout_key(a, "gfx950") != layout_key(c, "gfx950")
+    # the packing offset does not matter, the counts do
+    d = [(64, 64, 3.7, 7, 4096)] * 3
+    assert layout_key(a, "gfx950") == layout_key(d, "gfx950")
+
+
+def test_cache_round_trip_and_rejects_bad_entries(tmp_path):
+    from paper_2501_06838_amd.autotune import TuneCache
+    p = tmp_path / "sub" / "tune.json"
+    c = TuneCache(str(p))
+    assert c.get("k") is None
+    c.put("k", {"config": {"tile": 16, "lds_batch": 128, "flags": 1}, "ms": 1.5})
+    c2 = TuneCache(str(p))
+    assert c2.get("k")["config"] == {"tile": 16, "lds_batch": 128, "flags": 1}
+    c2.put("bad", {"config": {"tile": 12, "lds_batch": 128, "flags": 0}, "ms": 1.0})
+    assert TuneCache(str(p)).get("bad") is None
+    p.write_text("not json")
+    assert TuneCache(str(p)).get("k") is None
+    p.write_text(json.dumps([1, 2]))
+    assert TuneCache(str(p)).entries == {}
