@@ -242,6 +242,8 @@ struct BwdLds {
     float acc[8][B];      // moment-major: lanes flushing different Gaussians hit different banks
     int64_t tmp[NT / 64];
     double lpart[NT / 64];
+    float bnd[NT / 64][8];  // per wave: sums of the segment holding lane 0
+    int bkey[NT / 64];      // its Gaussian (-1: none)
 };
 
 template <int T, bool kL1, typename Table>
@@ -416,8 +418,14 @@ __device__ __forceinline__ void bwd_tile(
         // Chunk ends: lanes sharing a last Gaussian are contiguous in the wave
         // (keys ascend with the lane), so a segmented suffix sum leaves each
         // segment's total in its first lane, which alone adds it to LDS.
+        // Order of the adds: a Gaussian's pairs are contiguous over the lanes,
+        // so it receives at most one mid-chunk flush and at most one segment
+        // that does not hold its wave's lane 0; those two adds onto zero
+        // commute exactly.  A segment holding lane 0 (it may continue the
+        // previous wave's Gaussian) is kept aside and added after the barrier
+        // in wave order, so the sums are bitwise reproducible.
         {
-            const int lane = t & 63;
+            const int lane = t & 63, wave = t >> 6;
 #pragma unroll
             for (int o = 1; o < 64; o <<= 1) {
                 const int kk = __shfl_down(key, o, 64);
@@ -431,11 +439,23 @@ __device__ __forceinline__ void bwd_tile(
                 }
             }
             const int kprev = __shfl_up(key, 1, 64);
-            if (j0 < j1 && (lane == 0 || kprev != key)) {
+            if (lane == 0) {
+                sm.bkey[wave] = j0 < j1 ? key : -1;
+                sm.bnd[wave][0] = m0; sm.bnd[wave][1] = m1; sm.bnd[wave][2] = m2;
+                sm.bnd[wave][3] = m3; sm.bnd[wave][4] = m4; sm.bnd[wave][5] = m5;
+                sm.bnd[wave][6] = m6; sm.bnd[wave][7] = m7;
+            } else if (j0 < j1 && kprev != key) {
                 atomicAdd(&acc[0][key], m0); atomicAdd(&acc[1][key], m1);
                 atomicAdd(&acc[2][key], m2); atomicAdd(&acc[3][key], m3);
                 atomicAdd(&acc[4][key], m4); atomicAdd(&acc[5][key], m5);
                 atomicAdd(&acc[6][key], m6); atomicAdd(&acc[7][key], m7);
+            }
+        }
+        __syncthreads();
+        if (t < 8) {
+            for (int w = 0; w < NT / 64; ++w) {
+                const int k = sm.bkey[w];
+                if (k >= 0) acc[t][k] += sm.bnd[w][t];
             }
         }
         __syncthreads();
