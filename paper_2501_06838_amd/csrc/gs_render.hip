@@ -10,13 +10,13 @@
 // Planar stores of the finished tile are coalesced along rows.
 //
 // Backward: one workgroup per tile.  The tile's upstream gradient is staged
-// in LDS; the (Gaussian, pixel) pairs of each round are flattened (box area
-// prefix sums in LDS) and split into equal contiguous chunks, one per lane,
-// so every lane does the same number of pair evaluations whatever the box
-// sizes.  A lane accumulates the eight per-Gaussian moments in registers,
-// flushes them into the round's LDS accumulators when it leaves a Gaussian,
-// and the workgroup issues one FP32 global atomic per (tile, Gaussian,
-// moment).  The finalize kernel turns moments into parameter gradients.
+// in LDS and the listed Gaussians are compacted per 8x8 block as in the
+// forward; a wave puts one Gaussian of a block's list on each lane and walks
+// the block's pixels with all lanes together, so every lane accumulates the
+// eight per-Gaussian sums of its own Gaussian in registers.  The tile's sums
+// per (tile, Gaussian) are stored once, in sorted pair order (or added into
+// per-Gaussian accumulators with global atomics); the finalize kernel turns
+// them into parameter gradients.
 #include <algorithm>
 
 #include "gs_internal.h"
@@ -231,21 +231,38 @@ __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_fwd(
 // kL1: the upstream gradient is the L1 loss's, sign(out - target) / numel,
 // formed here from the rendered image and the target (it is never stored),
 // and the tile's share of sum |out - target| goes to tile_loss[tile].
+// Backward: Gaussians staged per round.
 template <int T>
-struct BwdLds {
-    static constexpr int NT = TileShape<T>::kThreads, B = TileShape<T>::kBatch;
-    float4 gt[T * T];     // upstream gradient of the tile, {g0, g1, g2, 0}
-    float4 sq0[B];        // {X at box start, Y at box start, a, e}
-    float4 sq1[B];        // {g, A0, A1, A2}
-    int4 sq2[B];          // {first pixel index, box width, area, -}
-    int pfx[B + 1];
-    float acc[8][B];      // moment-major: lanes flushing different Gaussians hit different banks
-    int64_t tmp[NT / 64];
-    double lpart[NT / 64];
-    float bnd[NT / 64][8];  // per wave: sums of the segment holding lane 0
-    int bkey[NT / 64];      // its Gaussian (-1: none)
+struct BwdShape {
+    static constexpr int kBatch = T == 8 ? 64 : (T == 16 ? 128 : 32);
 };
 
+template <int T>
+struct BwdLds {
+    static constexpr int NB = TileShape<T>::kBlocks, NW = TileShape<T>::kWaves,
+                         B = BwdShape<T>::kBatch;
+    float4 gt[T * T];       // upstream gradient of the tile, {g0, g1, g2, 0}
+    float4 r0[B];           // staged Gaussian: {kxr, kyr, fx, fy}
+    float4 r1[B];           // {a, e, g, A0}
+    float2 r2[B];           // {A1, A2}
+    uint2 bm[NB][B];        // per 8x8 block, compacted: pixel mask of the box
+    short lst[NB][B];       // per 8x8 block, compacted: staged index
+    int bcount[NB];
+    int wcount[NW][NB];
+    float4 acc[NB][B][2];   // per (block, staged Gaussian): the eight sums
+    double lpart[NW];
+};
+
+// One tile of the backward.  Per round, B listed Gaussians are staged and,
+// per 8x8 block, compacted into the list of those whose box touches it (with
+// the box's 64-bit pixel mask), as in the forward.  A wave then takes a
+// block and puts one Gaussian of its list on each lane; all lanes walk the
+// block's pixels together (the union of their boxes), so the pixel, its
+// upstream gradient and the loop are uniform over the wave, and each lane
+// accumulates its own Gaussian's eight sums in registers: no cross-lane
+// reduction, no atomics, no divergence.  Along a row z1 and z2 advance by
+// constant steps.  Each (block, Gaussian) writes its sums once; the tile's
+// sums per Gaussian add the blocks in ascending order (bitwise reproducible).
 template <int T, bool kL1, typename Table>
 __device__ __forceinline__ void bwd_tile(
     BwdLds<T>& sm, const Table& imgs, int n_img, const PairRec* __restrict__ pairs,
@@ -254,16 +271,8 @@ __device__ __forceinline__ void bwd_tile(
     float* __restrict__ moments, float4* __restrict__ partials, int atomic_grads,
     int64_t tile) {
     using S = TileShape<T>;
-    constexpr int NT = S::kThreads, B = S::kBatch;
-    float4* gt = sm.gt;
-    float4* sq0 = sm.sq0;
-    float4* sq1 = sm.sq1;
-    int4* sq2 = sm.sq2;
-    int* pfx = sm.pfx;
-    auto& acc = sm.acc;
-    int64_t* tmp = sm.tmp;
-
-    const int t = threadIdx.x;
+    constexpr int NT = S::kThreads, NB = S::kBlocks, NW = S::kWaves, B = BwdShape<T>::kBatch;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int k_img = tile_image(imgs, n_img, tile);
     const ImgDev im = imgs[k_img];
     const int64_t lt = tile - im.tile_base;
@@ -293,187 +302,160 @@ __device__ __forceinline__ void bwd_tile(
                 v = make_float4(g[q], g[plane + q], g[2 * plane + q], 0.f);
             }
         }
-        gt[p] = v;
+        sm.gt[p] = v;
     }
     if (kL1) {
         for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o, 64);
-        if ((t & 63) == 0) sm.lpart[t >> 6] = lsum;
+        if (lane == 0) sm.lpart[wave] = lsum;
         __syncthreads();
         if (t == 0) {
             double sum = 0.0;
-            for (int k = 0; k < NT / 64; ++k) sum += sm.lpart[k];
+            for (int k = 0; k < NW; ++k) sum += sm.lpart[k];
             tile_loss[tile] = sum;
         }
         if (rg.y <= rg.x) return;  // uniform
+    } else {
+        __syncthreads();
     }
 
     for (int base = rg.x; base < rg.y; base += B) {
         const int nb = min(B, rg.y - base);
-        uint32_t my_gid = 0;
-        int area = 0;
+        uint64_t my_mask[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) my_mask[j] = 0;
+        uint32_t my_gid = 0, touch = 0;
         if (t < nb) {
             const PairRec r = pairs[base + t];
             my_gid = r.gid;
+            sm.r0[t] = make_float4(r.kxr, r.kyr, r.fx, r.fy);
+            sm.r1[t] = make_float4(r.a, r.e, r.g, r.A[0]);
+            sm.r2[t] = make_float2(r.A[1], r.A[2]);
             const int lx0 = r.box & 255, lx1 = (r.box >> 8) & 255;
             const int ly0 = (r.box >> 16) & 255, ly1 = r.box >> 24;
-            const int w = lx1 - lx0 + 1, h = ly1 - ly0 + 1;
-            area = w * h;  // a dead Gaussian has zero amplitudes; its gradients are discarded
-            const float X0 = (r.kxr + (float)lx0) - r.fx;
-            const float Y0 = (r.kyr + (float)ly0) - r.fy;
-            sq0[t] = make_float4(X0, Y0, r.a, r.e);
-            sq1[t] = make_float4(r.g, r.A[0], r.A[1], r.A[2]);
-            sq2[t] = make_int4(ly0 * T + lx0, w, area, 0);
-        }
-        // exclusive prefix of box areas (block-wide)
-        {
-            const int lane = t & 63, wave = t >> 6;
-            int v = area;
-            for (int o = 1; o < 64; o <<= 1) {
-                const int u = __shfl_up(v, o, 64);
-                if (lane >= o) v += u;
-            }
-            if (lane == 63) tmp[wave] = v;
-            __syncthreads();
-            int carry = 0;
-            for (int k = 0; k < wave; ++k) carry += (int)tmp[k];
-            pfx[t] = carry + v - area;
-            if (t == NT - 1) pfx[NT] = carry + v;
-        }
 #pragma unroll
-        for (int m = 0; m < 8; ++m) acc[m][t] = 0.f;
+            for (int j = 0; j < NB; ++j) {
+                const int bx = (j % S::kBlocksX) * 8, by = (j / S::kBlocksX) * 8;
+                const int c0 = max(lx0, bx) - bx, c1 = min(lx1, bx + 7) - bx;
+                const int r0 = max(ly0, by) - by, r1 = min(ly1, by + 7) - by;
+                if (c0 <= c1 && r0 <= r1) {
+                    const uint64_t cols = ((1ull << (c1 - c0 + 1)) - 1ull) << c0;
+                    my_mask[j] = (cols * 0x0101010101010101ull) & rows_mask(r0, r1);
+                }
+            }
+        }
+        // per-block lists, in staged order
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const uint64_t bal = __ballot(my_mask[j] != 0);
+            if (lane == 0) sm.wcount[wave][j] = __popcll(bal);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const uint64_t bal = __ballot(my_mask[j] != 0);
+            if (my_mask[j] != 0) {
+                int pos = __popcll(bal & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+                for (int w = 0; w < wave; ++w) pos += sm.wcount[w][j];
+                sm.bm[j][pos] = make_uint2((uint32_t)my_mask[j], (uint32_t)(my_mask[j] >> 32));
+                sm.lst[j][pos] = (short)t;
+                touch |= 1u << j;
+            }
+        }
+        if (t < NB) {
+            int c = 0;
+            for (int w = 0; w < NW; ++w) c += sm.wcount[w][t];
+            sm.bcount[t] = c;
+        }
         __syncthreads();
 
-        const int total = pfx[NT];
-        const int L = (total + NT - 1) / NT;
-        const int j0 = min(t * L, total), j1 = min(j0 + L, total);
-        // Every lane ends with the partial sums of the last Gaussian of its
-        // chunk in m0..m7 (key k); Gaussians finished strictly inside the
-        // chunk are flushed to LDS on the way (at most one lane of a wave
-        // finishes a given Gaussian, so those adds never collide in a wave).
-        int key = 0x7fffffff;  // lanes without pairs: never merged with a Gaussian
-        float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f, m5 = 0.f, m6 = 0.f, m7 = 0.f;
-        if (j0 < j1) {
-            // staged entry holding flat pair j0: last k with pfx[k] <= j0
-            // (every entry has a positive area, so it is unique)
-            int lo = 0, hi = nb - 1, k = 0;
-            while (lo <= hi) {
-                const int mid = (lo + hi) >> 1;
-                if (pfx[mid] <= j0) { k = mid; lo = mid + 1; } else { hi = mid - 1; }
-            }
-            float4 q0 = sq0[k], q1 = sq1[k];
-            int4 q2 = sq2[k];
-            // parameters of the next entry, loaded ahead of the switch
-            const int kn = k + 1 < nb ? k + 1 : k;
-            float4 n0 = sq0[kn], n1 = sq1[kn];
-            int4 n2 = sq2[kn];
-            int r = j0 - pfx[k];
-            int ry = r / q2.y, rx = r - ry * q2.y;
-            int pix = q2.x + ry * T + rx;
-            float X = q0.x + (float)rx, Y = q0.y + (float)ry;
-            int left = q2.z - r;  // pairs of this Gaussian still to visit
-            float4 G = gt[pix];
-            for (int j = j0; j < j1; ++j) {
-                const float z1 = q0.z * X;
-                const float z2 = q0.w * Y - q1.x * X;
-                const float w = fast_exp2(-(z1 * z1 + z2 * z2));
-                m0 += G.x * w;
-                m1 += G.y * w;
-                m2 += G.z * w;
-                const float hw = (q1.y * G.x + q1.z * G.y + q1.w * G.z) * w;
-                const float t1 = hw * z1, t2 = hw * z2;
-                m3 += t1;
-                m4 += t2;
-                m5 += t1 * z1;
-                m6 += t1 * z2;
-                m7 += t2 * z2;
-                // advance within the box (row-major)
-                ++rx;
-                ++pix;
-                X += 1.0f;
-                if (rx == q2.y) {
-                    rx = 0;
-                    ++ry;
-                    pix += T - q2.y;
-                    X = q0.x;
-                    Y += 1.0f;
-                }
-                if (--left == 0 && j + 1 < j1) {
-                    atomicAdd(&acc[0][k], m0); atomicAdd(&acc[1][k], m1);
-                    atomicAdd(&acc[2][k], m2); atomicAdd(&acc[3][k], m3);
-                    atomicAdd(&acc[4][k], m4); atomicAdd(&acc[5][k], m5);
-                    atomicAdd(&acc[6][k], m6); atomicAdd(&acc[7][k], m7);
-                    m0 = m1 = m2 = m3 = m4 = m5 = m6 = m7 = 0.f;
-                    ++k;
-                    q0 = n0; q1 = n1; q2 = n2;
-                    const int k2 = k + 1 < nb ? k + 1 : k;
-                    n0 = sq0[k2]; n1 = sq1[k2]; n2 = sq2[k2];
-                    rx = 0; ry = 0; pix = q2.x;
-                    X = q0.x; Y = q0.y;
-                    left = q2.z;
-                }
-                G = gt[min(pix, T * T - 1)];  // next pair's gradient (clamped past the last)
-            }
-            key = k;
-        }
-        // Chunk ends: lanes sharing a last Gaussian are contiguous in the wave
-        // (keys ascend with the lane), so a segmented suffix sum leaves each
-        // segment's total in its first lane, which alone adds it to LDS.
-        // Order of the adds: a Gaussian's pairs are contiguous over the lanes,
-        // so it receives at most one mid-chunk flush and at most one segment
-        // that does not hold its wave's lane 0; those two adds onto zero
-        // commute exactly.  A segment holding lane 0 (it may continue the
-        // previous wave's Gaussian) is kept aside and added after the barrier
-        // in wave order, so the sums are bitwise reproducible.
-        {
-            const int lane = t & 63, wave = t >> 6;
 #pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const int kk = __shfl_down(key, o, 64);
-                const float v0 = __shfl_down(m0, o, 64), v1 = __shfl_down(m1, o, 64);
-                const float v2 = __shfl_down(m2, o, 64), v3 = __shfl_down(m3, o, 64);
-                const float v4 = __shfl_down(m4, o, 64), v5 = __shfl_down(m5, o, 64);
-                const float v6 = __shfl_down(m6, o, 64), v7 = __shfl_down(m7, o, 64);
-                if (lane + o < 64 && kk == key) {
-                    m0 += v0; m1 += v1; m2 += v2; m3 += v3;
-                    m4 += v4; m5 += v5; m6 += v6; m7 += v7;
+        for (int mb = 0; mb < S::kBlocksPerWave; ++mb) {
+            const int j = wave + NW * mb;
+            const int cnt = sm.bcount[j];
+            const int bx = (j % S::kBlocksX) * 8, by = (j / S::kBlocksX) * 8;
+            for (int p0 = 0; p0 < cnt; p0 += 64) {
+                const int pos = p0 + lane;
+                const bool active = pos < cnt;
+                const int ti = active ? (int)sm.lst[j][pos] : 0;
+                const uint2 mk = active ? sm.bm[j][pos] : make_uint2(0u, 0u);
+                const float4 q0 = sm.r0[ti], q1 = sm.r1[ti];
+                const float2 q2 = sm.r2[ti];
+                // rows and columns the wave's boxes cover in this block
+                uint32_t cm = mk.x | mk.y;
+                cm |= cm >> 16;
+                cm |= cm >> 8;
+                uint32_t rows = 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    rows |= ((mk.x >> (8 * k)) & 255u) ? (1u << k) : 0u;
+                    rows |= ((mk.y >> (8 * k)) & 255u) ? (1u << (k + 4)) : 0u;
                 }
-            }
-            const int kprev = __shfl_up(key, 1, 64);
-            if (lane == 0) {
-                sm.bkey[wave] = j0 < j1 ? key : -1;
-                sm.bnd[wave][0] = m0; sm.bnd[wave][1] = m1; sm.bnd[wave][2] = m2;
-                sm.bnd[wave][3] = m3; sm.bnd[wave][4] = m4; sm.bnd[wave][5] = m5;
-                sm.bnd[wave][6] = m6; sm.bnd[wave][7] = m7;
-            } else if (j0 < j1 && kprev != key) {
-                atomicAdd(&acc[0][key], m0); atomicAdd(&acc[1][key], m1);
-                atomicAdd(&acc[2][key], m2); atomicAdd(&acc[3][key], m3);
-                atomicAdd(&acc[4][key], m4); atomicAdd(&acc[5][key], m5);
-                atomicAdd(&acc[6][key], m6); atomicAdd(&acc[7][key], m7);
-            }
-        }
-        __syncthreads();
-        if (t < 8) {
-            for (int w = 0; w < NT / 64; ++w) {
-                const int k = sm.bkey[w];
-                if (k >= 0) acc[t][k] += sm.bnd[w][t];
+                uint32_t any = (cm & 255u) | (rows << 8);
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) any |= (uint32_t)__shfl_xor((int)any, o, 64);
+                any = __builtin_amdgcn_readfirstlane(any);
+                const int cx0 = __builtin_ctz(any & 255u), cx1 = 31 - __builtin_clz(any & 255u);
+                const int ry0 = __builtin_ctz(any >> 8), ry1 = 31 - __builtin_clz(any >> 8);
+                const float a = q1.x, e = q1.y, gg = q1.z;
+                float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f, m5 = 0.f, m6 = 0.f,
+                      m7 = 0.f;
+                for (int ry = ry0; ry <= ry1; ++ry) {
+                    const uint32_t rowbits = ((ry < 4 ? mk.x : mk.y) >> (8 * (ry & 3))) & 255u;
+                    const float Y = (q0.y + (float)(by + ry)) - q0.w;
+                    const float X0 = (q0.x + (float)(bx + cx0)) - q0.z;
+                    float z1 = a * X0;
+                    float z2 = e * Y - gg * X0;
+                    const float4* grow = &sm.gt[(by + ry) * T + bx];
+#pragma unroll
+                    for (int cx = 0; cx < 8; ++cx) {
+                        if (cx < cx0 || cx > cx1) continue;  // uniform
+                        const float4 G = grow[cx];
+                        float w = fast_exp2(-(z1 * z1 + z2 * z2));
+                        w = (rowbits & (1u << cx)) ? w : 0.f;
+                        m0 += G.x * w;
+                        m1 += G.y * w;
+                        m2 += G.z * w;
+                        const float hw = (q1.w * G.x + q2.x * G.y + q2.y * G.z) * w;
+                        const float t1 = hw * z1, t2 = hw * z2;
+                        m3 += t1;
+                        m4 += t2;
+                        m5 += t1 * z1;
+                        m6 += t1 * z2;
+                        m7 += t2 * z2;
+                        z1 += a;
+                        z2 -= gg;
+                    }
+                }
+                if (active) {
+                    sm.acc[j][ti][0] = make_float4(m0, m1, m2, m3);
+                    sm.acc[j][ti][1] = make_float4(m4, m5, m6, m7);
+                }
             }
         }
         __syncthreads();
         if (t < nb) {
+            float4 u = make_float4(0.f, 0.f, 0.f, 0.f), v = u;
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                if (touch & (1u << j)) {
+                    const float4 a0 = sm.acc[j][t][0], a1 = sm.acc[j][t][1];
+                    u.x += a0.x; u.y += a0.y; u.z += a0.z; u.w += a0.w;
+                    v.x += a1.x; v.y += a1.y; v.z += a1.z; v.w += a1.w;
+                }
+            }
             if (atomic_grads) {
                 // one FP32 global atomic per (tile, Gaussian, sum)
                 float* dst = moments + (int64_t)my_gid * 8;
+                const float vals[8] = {u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
 #pragma unroll
-                for (int m = 0; m < 8; ++m) {
-                    const float v = acc[m][t];
-                    if (v != 0.f) atomicAdd(dst + m, v);
-                }
+                for (int m = 0; m < 8; ++m)
+                    if (vals[m] != 0.f) atomicAdd(dst + m, vals[m]);
             } else {
                 // the (tile, Gaussian) sums, coalesced in sorted pair order;
                 // the gradient kernel adds each Gaussian's pairs in a fixed order
                 float4* dst = partials + 2 * (int64_t)(base + t);
-                dst[0] = make_float4(acc[0][t], acc[1][t], acc[2][t], acc[3][t]);
-                dst[1] = make_float4(acc[4][t], acc[5][t], acc[6][t], acc[7][t]);
+                dst[0] = u;
+                dst[1] = v;
             }
         }
         __syncthreads();
