@@ -368,68 +368,74 @@ __device__ __forceinline__ void bwd_tile(
         }
         __syncthreads();
 
+        // The (block, Gaussian) records of all blocks, block after block, go
+        // 64 to a wave: a pass walks the block-local pixels of the union of
+        // its lanes' boxes, each lane reading the gradient of its own block.
+        int total = 0;
 #pragma unroll
-        for (int mb = 0; mb < S::kBlocksPerWave; ++mb) {
-            const int j = wave + NW * mb;
-            const int cnt = sm.bcount[j];
+        for (int j = 0; j < NB; ++j) total += sm.bcount[j];
+        for (int f0 = wave * 64; f0 < total; f0 += NW * 64) {
+            const int f = f0 + lane;
+            const bool active = f < total;
+            int j = 0, pos = f;
+#pragma unroll
+            for (int k = 0; k + 1 < NB; ++k) {
+                if (j == k && pos >= sm.bcount[k]) { pos -= sm.bcount[k]; j = k + 1; }
+            }
+            if (!active) { j = 0; pos = 0; }
+            const int ti = active ? (int)sm.lst[j][pos] : 0;
+            const uint2 mk = active ? sm.bm[j][pos] : make_uint2(0u, 0u);
             const int bx = (j % S::kBlocksX) * 8, by = (j / S::kBlocksX) * 8;
-            for (int p0 = 0; p0 < cnt; p0 += 64) {
-                const int pos = p0 + lane;
-                const bool active = pos < cnt;
-                const int ti = active ? (int)sm.lst[j][pos] : 0;
-                const uint2 mk = active ? sm.bm[j][pos] : make_uint2(0u, 0u);
-                const float4 q0 = sm.r0[ti], q1 = sm.r1[ti];
-                const float2 q2 = sm.r2[ti];
-                // rows and columns the wave's boxes cover in this block
-                uint32_t cm = mk.x | mk.y;
-                cm |= cm >> 16;
-                cm |= cm >> 8;
-                uint32_t rows = 0;
+            const float4 q0 = sm.r0[ti], q1 = sm.r1[ti];
+            const float2 q2 = sm.r2[ti];
+            // block-local rows and columns the wave's boxes cover
+            uint32_t cm = mk.x | mk.y;
+            cm |= cm >> 16;
+            cm |= cm >> 8;
+            uint32_t rows = 0;
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    rows |= ((mk.x >> (8 * k)) & 255u) ? (1u << k) : 0u;
-                    rows |= ((mk.y >> (8 * k)) & 255u) ? (1u << (k + 4)) : 0u;
-                }
-                uint32_t any = (cm & 255u) | (rows << 8);
+            for (int k = 0; k < 4; ++k) {
+                rows |= ((mk.x >> (8 * k)) & 255u) ? (1u << k) : 0u;
+                rows |= ((mk.y >> (8 * k)) & 255u) ? (1u << (k + 4)) : 0u;
+            }
+            uint32_t any = (cm & 255u) | (rows << 8);
 #pragma unroll
-                for (int o = 1; o < 64; o <<= 1) any |= (uint32_t)__shfl_xor((int)any, o, 64);
-                any = __builtin_amdgcn_readfirstlane(any);
-                const int cx0 = __builtin_ctz(any & 255u), cx1 = 31 - __builtin_clz(any & 255u);
-                const int ry0 = __builtin_ctz(any >> 8), ry1 = 31 - __builtin_clz(any >> 8);
-                const float a = q1.x, e = q1.y, gg = q1.z;
-                float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f, m5 = 0.f, m6 = 0.f,
-                      m7 = 0.f;
-                for (int ry = ry0; ry <= ry1; ++ry) {
-                    const uint32_t rowbits = ((ry < 4 ? mk.x : mk.y) >> (8 * (ry & 3))) & 255u;
-                    const float Y = (q0.y + (float)(by + ry)) - q0.w;
-                    const float X0 = (q0.x + (float)(bx + cx0)) - q0.z;
-                    float z1 = a * X0;
-                    float z2 = e * Y - gg * X0;
-                    const float4* grow = &sm.gt[(by + ry) * T + bx];
+            for (int o = 1; o < 64; o <<= 1) any |= (uint32_t)__shfl_xor((int)any, o, 64);
+            any = __builtin_amdgcn_readfirstlane(any);
+            const int cx0 = __builtin_ctz(any & 255u), cx1 = 31 - __builtin_clz(any & 255u);
+            const int ry0 = __builtin_ctz(any >> 8), ry1 = 31 - __builtin_clz(any >> 8);
+            const float a = q1.x, e = q1.y, gg = q1.z;
+            float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f, m5 = 0.f, m6 = 0.f, m7 = 0.f;
+            for (int ry = ry0; ry <= ry1; ++ry) {
+                const uint32_t rowbits = ((ry < 4 ? mk.x : mk.y) >> (8 * (ry & 3))) & 255u;
+                const float Y = (q0.y + (float)(by + ry)) - q0.w;
+                const float X0 = (q0.x + (float)(bx + cx0)) - q0.z;
+                float z1 = a * X0;
+                float z2 = e * Y - gg * X0;
+                const float4* grow = &sm.gt[(by + ry) * T + bx];
 #pragma unroll
-                    for (int cx = 0; cx < 8; ++cx) {
-                        if (cx < cx0 || cx > cx1) continue;  // uniform
-                        const float4 G = grow[cx];
-                        float w = fast_exp2(-(z1 * z1 + z2 * z2));
-                        w = (rowbits & (1u << cx)) ? w : 0.f;
-                        m0 += G.x * w;
-                        m1 += G.y * w;
-                        m2 += G.z * w;
-                        const float hw = (q1.w * G.x + q2.x * G.y + q2.y * G.z) * w;
-                        const float t1 = hw * z1, t2 = hw * z2;
-                        m3 += t1;
-                        m4 += t2;
-                        m5 += t1 * z1;
-                        m6 += t1 * z2;
-                        m7 += t2 * z2;
-                        z1 += a;
-                        z2 -= gg;
-                    }
+                for (int cx = 0; cx < 8; ++cx) {
+                    if (cx < cx0 || cx > cx1) continue;  // uniform
+                    const float4 G = grow[cx];
+                    float w = fast_exp2(-(z1 * z1 + z2 * z2));
+                    w = (rowbits & (1u << cx)) ? w : 0.f;
+                    m0 += G.x * w;
+                    m1 += G.y * w;
+                    m2 += G.z * w;
+                    const float hw = (q1.w * G.x + q2.x * G.y + q2.y * G.z) * w;
+                    const float t1 = hw * z1, t2 = hw * z2;
+                    m3 += t1;
+                    m4 += t2;
+                    m5 += t1 * z1;
+                    m6 += t1 * z2;
+                    m7 += t2 * z2;
+                    z1 += a;
+                    z2 -= gg;
                 }
-                if (active) {
-                    sm.acc[j][ti][0] = make_float4(m0, m1, m2, m3);
-                    sm.acc[j][ti][1] = make_float4(m4, m5, m6, m7);
-                }
+            }
+            if (active) {
+                sm.acc[j][ti][0] = make_float4(m0, m1, m2, m3);
+                sm.acc[j][ti][1] = make_float4(m4, m5, m6, m7);
             }
         }
         __syncthreads();
