@@ -75,10 +75,11 @@ typedef struct {
 /* Launch configuration.  Zero fields take defaults. */
 typedef struct {
     int32_t tile;          /* square HR tile side: 8, 16 (default) or 32     */
-    int32_t lds_batch;     /* Gaussians the forward stages in LDS per round:
-                              tile 8: 32 or 64 (default 64); tile 16: 64,
-                              128 (default) or 256; tile 32: 32 (default) or
-                              64.  The image does not depend on it.          */
+    int32_t lds_batch;     /* Gaussians the tile kernels stage in LDS per
+                              round: tile 8: 32 or 64 (default 64); tile 16:
+                              64, 128 (default) or 256; tile 32: 32 (default)
+                              or 64.  Neither the image nor the gradients
+                              depend on it.                                  */
     int32_t flags;         /* GS_FLAG_* (other bits: GS_E_INVALID)           */
     int32_t reserved;
     int64_t pair_capacity; /* max (tile, Gaussian) pairs the workspace holds;
@@ -88,7 +89,7 @@ typedef struct {
 /* flags */
 #define GS_FLAG_PERSISTENT 0x1   /* tile kernels run persistent: a grid of as
                                     many workgroups as fit on the device takes
-                                    tiles from a device work counter, longest
+                                    tiles from device work counters, longest
                                     list first (the binning builds that order).
                                     Results are bitwise those of the default
                                     one-workgroup-per-tile launch.            */

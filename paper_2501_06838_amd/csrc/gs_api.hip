@@ -107,6 +107,7 @@ gs_status make_layout(const gs_config* cfg, const gs_image* images, int32_t n_im
     l.off_order = off; off = align_up(off + sizeof(uint32_t) * (size_t)tiles);
     l.off_order_hist = off;
     off = align_up(off + sizeof(int32_t) * ((size_t)kRadix * l.nblk_order + kRadix));
+    l.off_sched = off; off = align_up(off + sizeof(uint32_t) * kSchedWords);
     l.off_keys0 = off; off = align_up(off + sizeof(uint32_t) * (size_t)cap);
     l.off_vals0 = off; off = align_up(off + sizeof(uint32_t) * (size_t)cap);
     l.off_keys1 = off; off = align_up(off + sizeof(uint32_t) * (size_t)cap);

@@ -101,9 +101,12 @@ __global__ __launch_bounds__(kBlockG) void k_support(
     const float* __restrict__ color, const float* __restrict__ opacity,
     const float* __restrict__ radius, GRec* __restrict__ recs, int32_t* __restrict__ counts,
     BlockSums* __restrict__ blocksums, int2* __restrict__ ranges, int64_t n_tiles,
-    float4* __restrict__ moments) {
+    float4* __restrict__ moments, uint32_t* __restrict__ sched) {
     __shared__ int64_t tmp[3][kBlockG / 64];
     const int64_t i = (int64_t)blockIdx.x * kBlockG + threadIdx.x;
+
+    if (blockIdx.x == 0)
+        for (int k = threadIdx.x; k < kSchedWords; k += kBlockG) sched[k] = 0;
 
     if (kArgTable && blockIdx.x == 0 && threadIdx.x < n_img)
         imgs[threadIdx.x] = arg_imgs.img[threadIdx.x];
@@ -224,7 +227,6 @@ __global__ __launch_bounds__(kBlockG) void k_scan_blocks(BlockSums* __restrict__
         hdr->overflow = carry > cap ? 1 : 0;
         hdr->n_support = a;
         hdr->n_invalid = b;
-        for (int k = 0; k < 4; ++k) hdr->work[k] = 0;
         hdr->ordered = 0;
     }
 }
@@ -265,8 +267,7 @@ __global__ __launch_bounds__(kBlockG) void k_emit(
             hdr->overflow = total > cap ? 1 : 0;
             hdr->n_support = sa;
             hdr->n_invalid = sb;
-            for (int k = 0; k < 4; ++k) hdr->work[k] = 0;
-            hdr->ordered = 0;
+                hdr->ordered = 0;
         hdr->ordered = 0;
         }
     } else {
@@ -527,11 +528,11 @@ hipError_t launch_support(const Layout& L, const Ws& w, const ImgDev* host_imgs,
     if (by_value)
         hipLaunchKernelGGL(k_support<true>, dim3(L.nblk_g), dim3(kBlockG), 0, st, chunk, w.imgs,
                            L.n_img, L.n_gauss, L.tile, mean, chol, color, opacity, radius,
-                           w.recs, w.counts, w.blocksums, w.ranges, L.n_tiles, mom);
+                           w.recs, w.counts, w.blocksums, w.ranges, L.n_tiles, mom, w.sched);
     else
         hipLaunchKernelGGL(k_support<false>, dim3(L.nblk_g), dim3(kBlockG), 0, st, chunk, w.imgs,
                            L.n_img, L.n_gauss, L.tile, mean, chol, color, opacity, radius,
-                           w.recs, w.counts, w.blocksums, w.ranges, L.n_tiles, mom);
+                           w.recs, w.counts, w.blocksums, w.ranges, L.n_tiles, mom, w.sched);
     if (count_only || L.nblk_g > kFoldScanBlocks)
         hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kBlockG), 0, st, w.blocksums, L.nblk_g,
                            L.cap, w.hdr);

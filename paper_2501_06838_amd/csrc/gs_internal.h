@@ -19,6 +19,11 @@ constexpr int kSortThreads = 256;      // radix sort workgroup
 constexpr int kSortItems = 4;          // keys per thread per sort block
 constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kRadixBits = 8;
+// Persistent tile kernels: per kernel (forward, backward) kSchedParts work
+// counters and one exit counter, each on a 64-byte line of its own.
+constexpr int kSchedParts = 16;
+constexpr int kSchedStride = 16;  // words
+constexpr int kSchedWords = 2 * (kSchedParts + 1) * kSchedStride;
 constexpr int kRadix = 1 << kRadixBits;
 
 // exp(-q/2) = exp2(-(kc z)^2) with kc = sqrt(log2(e) / 2); the render
@@ -83,10 +88,7 @@ struct WsHeader {
     int64_t n_support;    // in-support (pixel, Gaussian) pairs: sum of box areas
     int32_t overflow;     // n_pairs > capacity
     int32_t ordered;      // 1 once the tile order of this binning is complete
-    // persistent tile kernels: work[0] / work[1] next work item of the
-    // forward / backward, work[2] / work[3] their workgroups that have run
-    // out of work (the last one resets both, ready for the next launch)
-    uint32_t work[4];
+    uint32_t reserved[4];
 };
 
 // Host-side workspace layout for one batch shape.
@@ -102,7 +104,7 @@ struct Layout {
     int32_t nblk_sort = 0;    // blocks of the sort at full capacity
     int32_t n_passes = 0;     // radix passes over the tile-id bits
     int32_t nblk_order = 0;   // blocks of the tile-order sort
-    size_t off_order = 0, off_order_hist = 0;
+    size_t off_order = 0, off_order_hist = 0, off_sched = 0;
     size_t off_header = 0, off_imgs = 0, off_recs = 0, off_counts = 0, off_offsets = 0,
            off_blocksums = 0, off_keys0 = 0, off_vals0 = 0, off_keys1 = 0, off_vals1 = 0,
            off_hist = 0, off_ranges = 0, off_moments = 0, off_tile_loss = 0, off_pairs = 0,
@@ -132,6 +134,7 @@ struct Ws {
     float4* partials;    // per sorted pair: 8 backward sums (2 x float4)
     uint32_t* order;     // tiles, longest list first (persistent kernels)
     int32_t* order_hist; // histograms of the tile-order sort
+    uint32_t* sched;     // persistent-kernel counters (kSchedWords, zeroed by the binning)
 };
 
 inline Ws bind(const Layout& L, void* base) {
@@ -156,6 +159,7 @@ inline Ws bind(const Layout& L, void* base) {
     w.partials = reinterpret_cast<float4*>(b + L.off_partials);
     w.order = reinterpret_cast<uint32_t*>(b + L.off_order);
     w.order_hist = reinterpret_cast<int32_t*>(b + L.off_order_hist);
+    w.sched = reinterpret_cast<uint32_t*>(b + L.off_sched);
     return w;
 }
 

@@ -65,30 +65,53 @@ template <int T, int B>
 struct FwdLds {
     static constexpr int NB = TileShape<T>::kBlocks;
     // per 8x8 block j, compacted in ascending Gaussian order:
-    //   l0 = {X origin of the block minus kx, same for Y, fx, fy}
-    //   l1 = {a, e, g, A0},  l2 = {A1, A2, lane mask lo, lane mask hi}
+    //   l0 = {z1, z2 at the block's first pixel, a, e}
+    //   l1 = {g, A0, A1, A2},  l2 = {lane mask lo, lane mask hi, -, -}
+    // (equal strides: one address register walks all three)
     float4 l0[NB][B];
     float4 l1[NB][B];
-    float4 l2[NB][B];
+    uint4 l2[NB][B];
     int scount[NB];
     int wcount[TileShape<T>::kWaves][NB];
 };
 
-// Persistent tile kernels: the workgroup's first item is its own index, the
-// following ones come from a device counter; items index the longest-first
-// tile order.  Returns the next item (uniform over the workgroup).
-__device__ __forceinline__ int64_t next_item(uint32_t* counter, uint32_t* s_item) {
-    __syncthreads();  // every thread has read the previous item
-    if (threadIdx.x == 0) *s_item = gridDim.x + atomicAdd(counter, 1u);
-    __syncthreads();
-    return (int64_t)*s_item;
-}
-
-// Workgroup out of work: the last one to leave resets the counters.
-__device__ __forceinline__ void leave(uint32_t* counter, uint32_t* exited) {
+// Persistent tile kernels.  The items (the longest-first tile order) are
+// dealt round-robin to K = min(16, grid) partitions, item i to partition
+// i % K, whose workgroups are p, p + K, p + 2K, ...  A workgroup's first item
+// in its partition is fixed by its index; later ones come from the
+// partition's own counter (a line of its own, so the atomics of different
+// partitions do not queue on one address), and the ticket for the item after
+// next is taken while the current one is processed, which hides the atomic's
+// latency.  Every workgroup leaves once its partition is exhausted; the last
+// one to leave resets the counters for the next launch.
+template <typename Body>
+__device__ __forceinline__ void run_persistent(uint32_t* ctrs, int64_t n_items, Body body) {
+    __shared__ uint32_t s_n;
+    const int G = (int)gridDim.x;
+    const int K = G < kSchedParts ? G : kSchedParts;
+    const int p = (int)blockIdx.x % K;
+    const int Gp = (G - p + K - 1) / K;  // workgroups of partition p
+    uint32_t* ctr = ctrs + kSchedStride * p;
+    uint32_t ticket = 0;
+    if (threadIdx.x == 0) ticket = atomicAdd(ctr, 1u);  // for the second item
+    int64_t n = (int64_t)blockIdx.x / K;
+    for (;;) {
+        const int64_t item = (int64_t)p + n * K;
+        if (item >= n_items) break;  // uniform
+        body(item);
+        __syncthreads();  // every thread is done with s_n
+        if (threadIdx.x == 0) {
+            s_n = (uint32_t)Gp + ticket;
+            ticket = atomicAdd(ctr, 1u);
+        }
+        __syncthreads();
+        n = (int64_t)s_n;
+    }
     if (threadIdx.x == 0) {
-        if (atomicAdd(exited, 1u) == gridDim.x - 1) {
-            atomicExch(counter, 0u);
+        __threadfence();  // this workgroup's tickets are taken
+        uint32_t* exited = ctrs + kSchedStride * kSchedParts;
+        if (atomicAdd(exited, 1u) == (uint32_t)G - 1) {
+            for (int k = 0; k < K; ++k) atomicExch(ctrs + kSchedStride * k, 0u);
             atomicExch(exited, 0u);
         }
     }
@@ -148,10 +171,13 @@ __device__ __forceinline__ void fwd_tile(FwdLds<T, B>& sm, const Table& imgs, in
                 int pos = __popcll(bal & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
                 for (int w = 0; w < wave; ++w) pos += sm.wcount[w][j];
                 const int bx = (j % S::kBlocksX) * 8, by = (j / S::kBlocksX) * 8;
-                sm.l0[j][pos] = make_float4(r.kxr + (float)bx, r.kyr + (float)by, r.fx, r.fy);
-                sm.l1[j][pos] = make_float4(r.a, r.e, r.g, r.A[0]);
-                sm.l2[j][pos] = make_float4(r.A[1], r.A[2], __uint_as_float((uint32_t)my_mask[j]),
-                                            __uint_as_float((uint32_t)(my_mask[j] >> 32)));
+                // block origin relative to the HR centre: exact integer part,
+                // one rounding for the fraction
+                const float Xb = (r.kxr + (float)bx) - r.fx;
+                const float Yb = (r.kyr + (float)by) - r.fy;
+                sm.l0[j][pos] = make_float4(r.a * Xb, r.e * Yb - r.g * Xb, r.a, r.e);
+                sm.l1[j][pos] = make_float4(r.g, r.A[0], r.A[1], r.A[2]);
+                sm.l2[j][pos] = make_uint4((uint32_t)my_mask[j], (uint32_t)(my_mask[j] >> 32), 0u, 0u);
             }
         }
         if (t < NB) {
@@ -164,26 +190,25 @@ __device__ __forceinline__ void fwd_tile(FwdLds<T, B>& sm, const Table& imgs, in
 #pragma unroll
         for (int m = 0; m < S::kBlocksPerWave; ++m) {
             const int j = wave + S::kWaves * m;
-            const int cnt = sm.scount[j];
+            const int cnt = __builtin_amdgcn_readfirstlane(sm.scount[j]);  // uniform
             if (cnt == 0) continue;
             // records are read one iteration ahead (fixed stride, no indirection)
-            float4 a0 = sm.l0[j][0], a1 = sm.l1[j][0], a2 = sm.l2[j][0];
+#pragma unroll 2
             for (int q = 0; q < cnt; ++q) {
-                const float4 c0 = a0, c1 = a1, c2 = a2;
-                const int qn = q + 1 < cnt ? q + 1 : q;
-                a0 = sm.l0[j][qn]; a1 = sm.l1[j][qn]; a2 = sm.l2[j][qn];
-                const uint32_t mlo = __builtin_amdgcn_readfirstlane(__float_as_uint(c2.z));
-                const uint32_t mhi = __builtin_amdgcn_readfirstlane(__float_as_uint(c2.w));
+                const float4 c0 = sm.l0[j][q], c1 = sm.l1[j][q];
+                const uint2 c2 = make_uint2(sm.l2[j][q].x, sm.l2[j][q].y);
+                const uint32_t mlo = __builtin_amdgcn_readfirstlane(c2.x);
+                const uint32_t mhi = __builtin_amdgcn_readfirstlane(c2.y);
                 const uint64_t mask = ((uint64_t)mhi << 32) | mlo;
-                const float X = (c0.x + lxf) - c0.z;
-                const float Y = (c0.y + lyf) - c0.w;
-                const float z1 = c1.x * X;
-                const float z2 = c1.y * Y - c1.z * X;
+                // z at this lane's pixel: the block's first pixel plus the
+                // in-block offset (dx, dy)
+                const float z1 = __builtin_fmaf(c0.z, lxf, c0.x);
+                const float z2 = __builtin_fmaf(c0.w, lyf, __builtin_fmaf(-c1.x, lxf, c0.y));
                 float w = fast_exp2(-(z1 * z1 + z2 * z2));
                 w = __builtin_amdgcn_inverse_ballot_w64(mask) ? w : 0.f;
-                acc[m][0] += c1.w * w;
-                acc[m][1] += c2.x * w;
-                acc[m][2] += c2.y * w;
+                acc[m][0] += c1.y * w;
+                acc[m][1] += c1.z * w;
+                acc[m][2] += c1.w * w;
             }
         }
         __syncthreads();
@@ -211,36 +236,27 @@ template <int T, int B, typename Table>
 __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_fwd(
     Table imgs, int n_img, const PairRec* __restrict__ pairs,
     const int2* __restrict__ ranges, float* __restrict__ out,
-    const uint32_t* __restrict__ order, WsHeader* __restrict__ hdr, int64_t n_tiles,
-    int persistent) {
+    const uint32_t* __restrict__ order, const WsHeader* __restrict__ hdr, int64_t n_tiles,
+    int persistent, uint32_t* __restrict__ sched) {
     __shared__ FwdLds<T, B> sm;
-    __shared__ uint32_t s_item;
     if (!persistent) {
         fwd_tile<T, B>(sm, imgs, n_img, pairs, ranges, out, (int64_t)blockIdx.x);
         return;
     }
     // without a tile order from the matching binning, items are tiles
     const bool ordered = hdr->ordered != 0;
-    for (int64_t item = blockIdx.x; item < n_tiles; item = next_item(&hdr->work[0], &s_item)) {
+    run_persistent(sched, n_tiles, [&](int64_t item) {
         const int64_t tile = ordered ? (int64_t)order[item] : item;
         if (tile < n_tiles) fwd_tile<T, B>(sm, imgs, n_img, pairs, ranges, out, tile);
-    }
-    leave(&hdr->work[0], &hdr->work[2]);
+    });
 }
 
 // kL1: the upstream gradient is the L1 loss's, sign(out - target) / numel,
 // formed here from the rendered image and the target (it is never stored),
 // and the tile's share of sum |out - target| goes to tile_loss[tile].
-// Backward: Gaussians staged per round.
-template <int T>
-struct BwdShape {
-    static constexpr int kBatch = T == 8 ? 64 : (T == 16 ? 128 : 32);
-};
-
-template <int T>
+template <int T, int B>
 struct BwdLds {
-    static constexpr int NB = TileShape<T>::kBlocks, NW = TileShape<T>::kWaves,
-                         B = BwdShape<T>::kBatch;
+    static constexpr int NB = TileShape<T>::kBlocks, NW = TileShape<T>::kWaves;
     float4 gt[T * T];       // upstream gradient of the tile, {g0, g1, g2, 0}
     float4 r0[B];           // staged Gaussian: {kxr, kyr, fx, fy}
     float4 r1[B];           // {a, e, g, A0}
@@ -263,15 +279,15 @@ struct BwdLds {
 // reduction, no atomics, no divergence.  Along a row z1 and z2 advance by
 // constant steps.  Each (block, Gaussian) writes its sums once; the tile's
 // sums per Gaussian add the blocks in ascending order (bitwise reproducible).
-template <int T, bool kL1, typename Table>
+template <int T, int B, bool kL1, typename Table>
 __device__ __forceinline__ void bwd_tile(
-    BwdLds<T>& sm, const Table& imgs, int n_img, const PairRec* __restrict__ pairs,
+    BwdLds<T, B>& sm, const Table& imgs, int n_img, const PairRec* __restrict__ pairs,
     const int2* __restrict__ ranges, const float* __restrict__ grad_out,
     const float* __restrict__ target, float inv_numel, double* __restrict__ tile_loss,
     float* __restrict__ moments, float4* __restrict__ partials, int atomic_grads,
     int64_t tile) {
     using S = TileShape<T>;
-    constexpr int NT = S::kThreads, NB = S::kBlocks, NW = S::kWaves, B = BwdShape<T>::kBatch;
+    constexpr int NT = S::kThreads, NB = S::kBlocks, NW = S::kWaves;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int k_img = tile_image(imgs, n_img, tile);
     const ImgDev im = imgs[k_img];
@@ -374,6 +390,7 @@ __device__ __forceinline__ void bwd_tile(
         int total = 0;
 #pragma unroll
         for (int j = 0; j < NB; ++j) total += sm.bcount[j];
+        total = __builtin_amdgcn_readfirstlane(total);  // uniform
         for (int f0 = wave * 64; f0 < total; f0 += NW * 64) {
             const int f = f0 + lane;
             const bool active = f < total;
@@ -408,14 +425,21 @@ __device__ __forceinline__ void bwd_tile(
             float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f, m5 = 0.f, m6 = 0.f, m7 = 0.f;
             for (int ry = ry0; ry <= ry1; ++ry) {
                 const uint32_t rowbits = ((ry < 4 ? mk.x : mk.y) >> (8 * (ry & 3))) & 255u;
+                // z at the block's first column, then advanced column by column
+                // (also over columns outside the union), so a lane's values do
+                // not depend on which Gaussians share its pass
                 const float Y = (q0.y + (float)(by + ry)) - q0.w;
-                const float X0 = (q0.x + (float)(bx + cx0)) - q0.z;
+                const float X0 = (q0.x + (float)bx) - q0.z;
                 float z1 = a * X0;
                 float z2 = e * Y - gg * X0;
                 const float4* grow = &sm.gt[(by + ry) * T + bx];
 #pragma unroll
                 for (int cx = 0; cx < 8; ++cx) {
-                    if (cx < cx0 || cx > cx1) continue;  // uniform
+                    if (cx < cx0 || cx > cx1) {  // uniform
+                        z1 += a;
+                        z2 -= gg;
+                        continue;
+                    }
                     const float4 G = grow[cx];
                     float w = fast_exp2(-(z1 * z1 + z2 * z2));
                     w = (rowbits & (1u << cx)) ? w : 0.f;
@@ -468,29 +492,27 @@ __device__ __forceinline__ void bwd_tile(
     }
 }
 
-template <int T, bool kL1, typename Table>
+template <int T, int B, bool kL1, typename Table>
 __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_bwd(
     Table imgs, int n_img, const PairRec* __restrict__ pairs,
     const int2* __restrict__ ranges, const float* __restrict__ grad_out,
     const float* __restrict__ target, float inv_numel, double* __restrict__ tile_loss,
     float* __restrict__ moments, float4* __restrict__ partials, int atomic_grads,
-    const uint32_t* __restrict__ order, WsHeader* __restrict__ hdr, int64_t n_tiles,
-    int persistent) {
-    __shared__ BwdLds<T> sm;
-    __shared__ uint32_t s_item;
+    const uint32_t* __restrict__ order, const WsHeader* __restrict__ hdr, int64_t n_tiles,
+    int persistent, uint32_t* __restrict__ sched) {
+    __shared__ BwdLds<T, B> sm;
     if (!persistent) {
-        bwd_tile<T, kL1>(sm, imgs, n_img, pairs, ranges, grad_out, target, inv_numel, tile_loss,
+        bwd_tile<T, B, kL1>(sm, imgs, n_img, pairs, ranges, grad_out, target, inv_numel, tile_loss,
                          moments, partials, atomic_grads, (int64_t)blockIdx.x);
         return;
     }
     const bool ordered = hdr->ordered != 0;
-    for (int64_t item = blockIdx.x; item < n_tiles; item = next_item(&hdr->work[1], &s_item)) {
+    run_persistent(sched, n_tiles, [&](int64_t item) {
         const int64_t tile = ordered ? (int64_t)order[item] : item;
         if (tile < n_tiles)
-            bwd_tile<T, kL1>(sm, imgs, n_img, pairs, ranges, grad_out, target, inv_numel,
-                             tile_loss, moments, partials, atomic_grads, tile);
-    }
-    leave(&hdr->work[1], &hdr->work[3]);
+            bwd_tile<T, B, kL1>(sm, imgs, n_img, pairs, ranges, grad_out, target, inv_numel,
+                                tile_loss, moments, partials, atomic_grads, tile);
+    });
 }
 
 // Moments -> gradients, per Gaussian, in FP64.  With K = 1/(2 pi l11 l22),
@@ -629,7 +651,11 @@ static hipError_t tile_grid(const Layout& L, const void* kernel, int threads, un
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0);
     if (e != hipSuccess) return e;
-    const int64_t resident = (int64_t)std::max(cus, 1) * std::max(per_cu, 1);
+    // at least 8 waves per SIMD (4 SIMDs per CU); workgroups beyond the
+    // resident ones start once others leave and find little or no work
+    const int waves = (threads + 63) / 64;
+    const int64_t per = std::max(per_cu, (32 + waves - 1) / waves);
+    const int64_t resident = (int64_t)std::max(cus, 1) * per;
     *grid = (unsigned)std::min<int64_t>(L.n_tiles, resident);
     return hipSuccess;
 }
@@ -644,7 +670,7 @@ static hipError_t launch_fwd_tb(const Layout& L, const Ws& w, const Table& tab, 
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(TileShape<T>::kThreads), 0, st, tab, L.n_img,
                        w.pairs, w.ranges, out, w.order, w.hdr, L.n_tiles,
-                       (L.flags & GS_FLAG_PERSISTENT) ? 1 : 0);
+                       (L.flags & GS_FLAG_PERSISTENT) ? 1 : 0, w.sched);
     return hipGetLastError();
 }
 
@@ -682,11 +708,11 @@ hipError_t launch_render_fwd(const Layout& L, const Ws& w, float* out, hipStream
     return launch_fwd_t(L, w, MemTable{w.imgs}, out, st);
 }
 
-template <int T, bool kL1, typename Table>
+template <int T, int B, bool kL1, typename Table>
 static hipError_t launch_bwd_tt(const Layout& L, const Ws& w, const Table& tab,
                                 const float* grad_out, const float* target, float inv_numel,
                                 hipStream_t st) {
-    const auto kernel = k_render_bwd<T, kL1, Table>;
+    const auto kernel = k_render_bwd<T, B, kL1, Table>;
     unsigned grid = 0;
     const hipError_t e = tile_grid(L, reinterpret_cast<const void*>(kernel),
                                    TileShape<T>::kThreads, &grid);
@@ -694,7 +720,8 @@ static hipError_t launch_bwd_tt(const Layout& L, const Ws& w, const Table& tab,
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(TileShape<T>::kThreads), 0, st, tab, L.n_img,
                        w.pairs, w.ranges, grad_out, target, inv_numel, w.tile_loss, w.moments,
                        w.partials, (L.flags & GS_FLAG_ATOMIC_GRADS) ? 1 : 0, w.order, w.hdr,
-                       L.n_tiles, (L.flags & GS_FLAG_PERSISTENT) ? 1 : 0);
+                       L.n_tiles, (L.flags & GS_FLAG_PERSISTENT) ? 1 : 0,
+                       w.sched + kSchedWords / 2);
     return hipGetLastError();
 }
 
@@ -702,12 +729,27 @@ template <bool kL1, typename Table>
 static hipError_t launch_bwd_t(const Layout& L, const Ws& w, const Table& tab,
                                const float* grad_out, const float* target, float inv_numel,
                                hipStream_t st) {
+    const int b = L.lds_batch;
     switch (L.tile) {
-        case 8: return launch_bwd_tt<8, kL1>(L, w, tab, grad_out, target, inv_numel, st);
-        case 16: return launch_bwd_tt<16, kL1>(L, w, tab, grad_out, target, inv_numel, st);
-        case 32: return launch_bwd_tt<32, kL1>(L, w, tab, grad_out, target, inv_numel, st);
-        default: return hipErrorInvalidValue;
+        case 8:
+            if (b == 32) return launch_bwd_tt<8, 32, kL1>(L, w, tab, grad_out, target, inv_numel, st);
+            if (b == 64) return launch_bwd_tt<8, 64, kL1>(L, w, tab, grad_out, target, inv_numel, st);
+            break;
+        case 16:
+            if (b == 64) return launch_bwd_tt<16, 64, kL1>(L, w, tab, grad_out, target, inv_numel, st);
+            if (b == 128)
+                return launch_bwd_tt<16, 128, kL1>(L, w, tab, grad_out, target, inv_numel, st);
+            if (b == 256)
+                return launch_bwd_tt<16, 256, kL1>(L, w, tab, grad_out, target, inv_numel, st);
+            break;
+        case 32:
+            if (b == 32) return launch_bwd_tt<32, 32, kL1>(L, w, tab, grad_out, target, inv_numel, st);
+            if (b == 64) return launch_bwd_tt<32, 64, kL1>(L, w, tab, grad_out, target, inv_numel, st);
+            break;
+        default:
+            break;
     }
+    return hipErrorInvalidValue;
 }
 
 template <bool kL1>
