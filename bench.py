@@ -45,7 +45,8 @@ FLOPEQ_BWD = 48.0
 # a plain 256 MiB device copy: FETCH_SIZE reads 131,084 KiB (factor 2.0),
 # WRITE_SIZE 262,144 KiB (factor 1.0).  Valid only while the render sources
 # hash to `sources`; otherwise reported as null.
-TRAFFIC = {"workload": "config1", "tile": 16, "sources": "f9ed41f8edf2007b",
+TRAFFIC = {"workload": "config1", "launch": {"tile": 16, "lds_batch": 0, "flags": 0},
+           "sources": "f9ed41f8edf2007b",
            "fetch_kib": 38085.5, "write_kib": 6604.7, "fetch_factor": 2.0, "write_factor": 1.0}
 TRAFFIC_SOURCES = ("paper_2501_06838_amd/csrc/gs_render.hip", "paper_2501_06838_amd/csrc/gs_internal.h")
 
@@ -59,9 +60,10 @@ def render_sources_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_bytes(workload, tile):
+def traffic_bytes(workload, launch):
     T = TRAFFIC
-    if workload != T["workload"] or tile != T["tile"] or render_sources_hash() != T["sources"]:
+    if (workload != T["workload"] or launch != T["launch"]
+            or render_sources_hash() != T["sources"]):
         return None
     return round(T["fetch_kib"] * 1024 * T["fetch_factor"] + T["write_kib"] * 1024 * T["write_factor"])
 
@@ -193,7 +195,7 @@ def pruned_comparison(args, G, synth, torch, np):
     arg = np.float64(wl.opacity) * np.float64(wl.color).max(1) * K / tau
     rcf = t(np.minimum(np.sqrt(2 * np.log(np.maximum(arg, 1.0))), 3.0).astype(np.float32))
     for mode in ("exact", "pruned", "closed_form"):
-        plan = G.RasterPlan(imgs, wl.n_gauss, tile=args.tile)
+        plan = G.RasterPlan(imgs, wl.n_gauss, tile=args.tile or 16)
         if target is None:
             target = plan.pack([t(x) for x in wl.target])
         rad = None
@@ -212,9 +214,7 @@ def pruned_comparison(args, G, synth, torch, np):
             if mode == "pruned":  # the radius is predicted inside the step
                 features(plan, chol, color, opacity, net.norm, out=feats)
                 net.radius(feats, out=radius)
-            plan.forward(mean, chol, color, opacity, ws, out, rad)
-            plan.render_backward_l1(ws, out, target)
-            plan.gradients(chol, color, opacity, ws, grads)
+            plan.step_l1(mean, chol, color, opacity, ws, out, target, grads, radius=rad)
 
         step()
         torch.cuda.synchronize()
@@ -262,7 +262,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="config1", choices=sorted(WORKLOADS))
-    ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--tile", type=int, default=0, help="0: autotuned launch configuration")
+    ap.add_argument("--lds-batch", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pruned", action="store_true")
@@ -292,23 +293,30 @@ def main():
         raise SystemExit("workload has no target")
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     mean, chol, color, opacity = t(wl.mean), t(wl.chol), t(wl.color), t(wl.opacity)
-    plan = G.RasterPlan([(im.lr_h, im.lr_w, im.scale, im.g_begin, im.g_count)
-                         for im in wl.images], wl.n_gauss, tile=args.tile)
+    imgs = [(im.lr_h, im.lr_w, im.scale, im.g_begin, im.g_count) for im in wl.images]
+    target = G.RasterPlan(imgs, wl.n_gauss).pack([t(x) for x in wl.target])
+    if args.tile:
+        launch = {"tile": args.tile, "lds_batch": args.lds_batch, "flags": 0}
+        tuned = None
+    else:
+        from paper_2501_06838_amd.autotune import tune
+        res = tune(imgs, mean, chol, color, opacity, target, reps=3, warmup=1)
+        launch = res["config"]
+        tuned = [[c["config"]["tile"], c["config"]["lds_batch"], c["config"]["flags"], c["ms"]]
+                 for c in res["timings"]]
+        log(f"autotuner picked {launch}")
+    plan = G.RasterPlan(imgs, wl.n_gauss, **launch)
     plan.ensure_capacity(mean, chol)
     ws = plan.new_workspace(dev)
     out = plan.new_output(dev)
-    target = plan.pack([t(x) for x in wl.target])
     loss_acc = torch.zeros((), dtype=torch.float64, device=dev)
     grads = (torch.empty(wl.n_gauss, 2, device=dev), torch.empty(wl.n_gauss, 3, device=dev),
              torch.empty(wl.n_gauss, 3, device=dev), torch.empty(wl.n_gauss, device=dev))
     stream = torch.cuda.current_stream()
 
     def step():
-        plan.bin(mean, chol, color, opacity, ws)
-        plan.render(ws, out)
-        plan.render_backward_l1(ws, out, target)   # L1 gradient formed per tile
-        plan.gradients(chol, color, opacity, ws, grads)
-        plan.l1_loss_value(ws, loss_acc)
+        # binning, fused tile kernel (render + L1 gradient + backward), gradients, loss
+        plan.step_l1(mean, chol, color, opacity, ws, out, target, grads, loss=loss_acc)
 
     # one eager step, then the step captured as one HIP graph
     step()
@@ -334,36 +342,53 @@ def main():
     if plan.diagnostics(ws)[1]:
         raise SystemExit("pair capacity overflow during replay")
 
-    # per-kernel durations of the two tile kernels: HIP events on the launch
-    # stream around single-kernel entry points, same inputs, same count
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    # per-kernel durations: HIP events on the launch stream around the
+    # single-kernel entry points, same inputs, same count.  The step's tile
+    # kernel is the fused one; the separate forward and backward tile kernels
+    # are timed too, for reference.
+    def events(n):
+        return [[torch.cuda.Event(enable_timing=True) for _ in range(n)] for _ in range(args.steps)]
+    ev = events(2)
     for k in range(args.steps):
         plan.bin(mean, chol, color, opacity, ws)
         ev[k][0].record(stream)
-        plan.render(ws, out)
+        plan.render_fused_l1(ws, out, target)
         ev[k][1].record(stream)
-        ev[k][2].record(stream)
+        plan.gradients(chol, color, opacity, ws, grads)
+    ev2 = events(4)
+    for k in range(args.steps):
+        plan.bin(mean, chol, color, opacity, ws)
+        ev2[k][0].record(stream)
+        plan.render(ws, out)
+        ev2[k][1].record(stream)
+        ev2[k][2].record(stream)
         plan.render_backward_l1(ws, out, target)
-        ev[k][3].record(stream)
+        ev2[k][3].record(stream)
         plan.gradients(chol, color, opacity, ws, grads)
     torch.cuda.synchronize()
-    fwd_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / args.steps
-    bwd_ms = sum(e[2].elapsed_time(e[3]) for e in ev) / args.steps
-    log(f"{ms_step:.4f} ms/step (graph replay); render fwd {fwd_ms * 1e3:.1f} us, "
-        f"bwd {bwd_ms * 1e3:.1f} us")
+    fused_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / args.steps
+    fwd_ms = sum(e[0].elapsed_time(e[1]) for e in ev2) / args.steps
+    bwd_ms = sum(e[2].elapsed_time(e[3]) for e in ev2) / args.steps
+    log(f"{ms_step:.4f} ms/step (graph replay); fused tile kernel {fused_ms * 1e3:.1f} us "
+        f"(separate: fwd {fwd_ms * 1e3:.1f} us, bwd {bwd_ms * 1e3:.1f} us)")
     graph.close()
 
-    fwd_tflops = n_support * FLOPEQ_FWD / (fwd_ms * 1e-3) / 1e12
-    bwd_tflops = n_support * FLOPEQ_BWD / (bwd_ms * 1e-3) / 1e12
+    def tf(flopeq, ms):
+        return n_support * flopeq / (ms * 1e-3) / 1e12
+    fused_tflops = tf(FLOPEQ_FWD + FLOPEQ_BWD, fused_ms)
     roofline = {
-        "bound": "alu", "kernel": "k_render_bwd (fused L1 gradient)", "achieved": round(bwd_tflops, 3),
+        "bound": "alu", "kernel": "k_render_fused (forward + L1 gradient + backward per tile)",
+        "achieved": round(fused_tflops, 3),
         "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-        "frac": round(bwd_tflops / PEAK_FP32_VECTOR_TFLOPS, 4),
-        "traffic": traffic_bytes(args.workload, args.tile),
-        "per_launch_flopeq": n_support * FLOPEQ_BWD, "avg_launch_us": round(bwd_ms * 1e3, 2),
-        "other": {"k_render_fwd": {"achieved": round(fwd_tflops, 3),
-                                   "frac": round(fwd_tflops / PEAK_FP32_VECTOR_TFLOPS, 4),
-                                   "avg_launch_us": round(fwd_ms * 1e3, 2)}},
+        "frac": round(fused_tflops / PEAK_FP32_VECTOR_TFLOPS, 4),
+        "traffic": traffic_bytes(args.workload, launch),
+        "per_launch_flopeq": n_support * (FLOPEQ_FWD + FLOPEQ_BWD),
+        "avg_launch_us": round(fused_ms * 1e3, 2),
+        "other": {name: {"achieved": round(tf(fe, ms), 3),
+                         "frac": round(tf(fe, ms) / PEAK_FP32_VECTOR_TFLOPS, 4),
+                         "avg_launch_us": round(ms * 1e3, 2)}
+                  for name, fe, ms in (("k_render_fwd", FLOPEQ_FWD, fwd_ms),
+                                       ("k_render_bwd (L1)", FLOPEQ_BWD, bwd_ms))},
     }
     pruned = None
     if not args.no_pruned:
@@ -385,7 +410,8 @@ def main():
         "ms_per_step": round(ms_step, 5), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}",
-                   "path": "exact 3-sigma support", "tile": args.tile,
+                   "path": "exact 3-sigma support", "launch_config": launch,
+                   "autotune_ms": tuned,
                    "hr_pixels": hr_px, "gaussians": wl.n_gauss, "tile_pairs": npairs,
                    "support_pairs": n_support,
                    "launch": "whole step captured in one HIP graph, replayed"},

@@ -77,7 +77,7 @@ typedef struct {
     int32_t tile;          /* square HR tile side: 8, 16 (default) or 32     */
     int32_t lds_batch;     /* Gaussians the tile kernels stage in LDS per
                               round: tile 8: 32 or 64 (default 64); tile 16:
-                              64, 128 (default) or 256; tile 32: 32 (default)
+                              64 (default), 128 or 256; tile 32: 32 (default)
                               or 64.  Neither the image nor the gradients
                               depend on it.                                  */
     int32_t flags;         /* GS_FLAG_* (other bits: GS_E_INVALID)           */
@@ -194,6 +194,27 @@ gs_status gs_raster_render_backward_l1(const gs_config* cfg, const gs_image* ima
                                        int32_t n_img, int64_t n_gauss, void* workspace,
                                        size_t ws_bytes, const float* out, const float* target,
                                        void* stream);
+
+/* gs_raster_render followed by gs_raster_render_backward_l1, in one kernel:
+ * per tile, the image is summed, stored to out, turned into the L1 gradient
+ * sign(out - target) / numel against target (with the tile's share of the
+ * loss) and fed to the backward render over the same staged Gaussians.  The
+ * workspace must hold a gs_raster_bin of the same batch.  Results are those
+ * of the two separate calls (the image bitwise). */
+gs_status gs_raster_render_fused_l1(const gs_config* cfg, const gs_image* images,
+                                    int32_t n_img, int64_t n_gauss, void* workspace,
+                                    size_t ws_bytes, float* out, const float* target,
+                                    void* stream);
+
+/* One whole training step of the L1 loss (Sec. 3.2, "Rendering"):
+ * gs_raster_bin, gs_raster_render_fused_l1, gs_raster_gradients and, when
+ * loss is not NULL, gs_l1_loss_value.  Arguments as for those calls. */
+gs_status gs_raster_step_l1(const gs_config* cfg, const gs_image* images, int32_t n_img,
+                            const float* mean, const float* chol, const float* color,
+                            const float* opacity, const float* radius, int64_t n_gauss,
+                            void* workspace, size_t ws_bytes, float* out, const float* target,
+                            float* grad_mean, float* grad_chol, float* grad_color,
+                            float* grad_opacity, double* loss, void* stream);
 
 /* Mean L1 loss of the last gs_raster_render_backward_l1 in this workspace,
  * written to *loss (device double). */
@@ -331,8 +352,8 @@ gs_status gs_sq_error(const float* a, const float* b, int64_t n, double* sum, vo
  * fixed device pointers. */
 typedef struct gs_graph_s* gs_graph;
 
-/* Captures, on a private stream, gs_raster_forward followed (when target is
- * not NULL) by gs_raster_backward_l1 with the same arguments, and
+/* Captures, on a private stream, gs_raster_step_l1 (when target is not
+ * NULL) or gs_raster_forward (when it is) with the same arguments, and
  * instantiates the result: replaying it runs the whole training step (or
  * forward pass) with one launch.  Kernel arguments, including the image
  * table, are baked in; the pointed-to device data is read at replay time, so

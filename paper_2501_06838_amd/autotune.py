@@ -8,8 +8,9 @@ forward sums every pixel's Gaussians in ascending index whatever the tile
 and batch), and the gradients are bitwise independent of the batch and of
 the persistent flag.
 
-``tune`` times one whole training step (binning, forward render, fused L1
-backward render, gradients) of the caller's own batch for each candidate
+``tune`` times one whole training step (binning, the fused tile kernel:
+render, L1 gradient and backward, then the gradients) of the caller's own
+batch for each candidate
 with HIP events on the current stream and returns the fastest; results are
 cached in a JSON file keyed by the batch layout and the device, so a serving
 loop pays the search once per layout.
@@ -90,8 +91,8 @@ class TuneCache:
 
 def time_step(plan, mean, chol, color, opacity, target, reps: int = 3, warmup: int = 1,
               headroom: float = 1.0) -> Tuple[float, int]:
-    """Median milliseconds of one fwd + fused-L1 bwd step for plan's config,
-    and its pair count."""
+    """Median milliseconds of one training step (gs_raster_step_l1) for
+    plan's config, and its pair count."""
     import torch
     dev = mean.device
     n = plan.n_gauss
@@ -103,10 +104,7 @@ def time_step(plan, mean, chol, color, opacity, target, reps: int = 3, warmup: i
     stream = torch.cuda.current_stream()
 
     def step():
-        plan.bin(mean, chol, color, opacity, ws)
-        plan.render(ws, out)
-        plan.render_backward_l1(ws, out, target)
-        plan.gradients(chol, color, opacity, ws, grads)
+        plan.step_l1(mean, chol, color, opacity, ws, out, target, grads)
 
     for _ in range(warmup):
         step()

@@ -38,7 +38,7 @@ gs_status make_layout(const gs_config* cfg, const gs_image* images, int32_t n_im
     if (l.tile != 8 && l.tile != 16 && l.tile != 32) return GS_E_UNSUPPORTED;
     // forward LDS batch: per tile size, the staged Gaussians per round whose
     // per-block record lists fit the LDS next to a useful occupancy
-    const int dflt = l.tile == 8 ? 64 : (l.tile == 16 ? 128 : 32);
+    const int dflt = l.tile == 8 ? 64 : (l.tile == 16 ? 64 : 32);
     l.lds_batch = (cfg && cfg->lds_batch) ? cfg->lds_batch : dflt;
     const bool ok_batch = (l.tile == 8 && (l.lds_batch == 32 || l.lds_batch == 64)) ||
                           (l.tile == 16 && (l.lds_batch == 64 || l.lds_batch == 128 ||
@@ -251,6 +251,43 @@ gs_status gs_raster_render_backward_l1(const gs_config* cfg, const gs_image* ima
     if (!workspace || ws_bytes < L.total) return GS_E_WORKSPACE;
     return dev(launch_render_bwd_l1(L, bind(L, workspace), out, target, batch_numel(table),
                                     static_cast<hipStream_t>(stream)));
+}
+
+gs_status gs_raster_render_fused_l1(const gs_config* cfg, const gs_image* images,
+                                    int32_t n_img, int64_t n_gauss, void* workspace,
+                                    size_t ws_bytes, float* out, const float* target,
+                                    void* stream) {
+    Layout L;
+    std::vector<ImgDev> table;
+    GS_TRY(make_layout(cfg, images, n_img, n_gauss, &L, &table));
+    if (!out || !target) return GS_E_INVALID;
+    if (!workspace || ws_bytes < L.total) return GS_E_WORKSPACE;
+    return dev(launch_render_fused_l1(L, bind(L, workspace), out, target, batch_numel(table),
+                                      static_cast<hipStream_t>(stream)));
+}
+
+gs_status gs_raster_step_l1(const gs_config* cfg, const gs_image* images, int32_t n_img,
+                            const float* mean, const float* chol, const float* color,
+                            const float* opacity, const float* radius, int64_t n_gauss,
+                            void* workspace, size_t ws_bytes, float* out, const float* target,
+                            float* grad_mean, float* grad_chol, float* grad_color,
+                            float* grad_opacity, double* loss, void* stream) {
+    Layout L;
+    std::vector<ImgDev> table;
+    GS_TRY(make_layout(cfg, images, n_img, n_gauss, &L, &table));
+    GS_TRY(check_gauss_ptrs(n_gauss, mean, chol, color, opacity));
+    if (!out || !target) return GS_E_INVALID;
+    if (n_gauss > 0 && (!grad_mean || !grad_chol || !grad_color || !grad_opacity))
+        return GS_E_INVALID;
+    if (!workspace || ws_bytes < L.total) return GS_E_WORKSPACE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const Ws w = bind(L, workspace);
+    GS_TRY(run_binning(L, w, table, mean, chol, color, opacity, radius, st));
+    GS_TRY(dev(launch_render_fused_l1(L, w, out, target, batch_numel(table), st)));
+    GS_TRY(dev(launch_finalize(L, w, chol, color, opacity, grad_mean, grad_chol, grad_color,
+                               grad_opacity, st)));
+    if (loss) GS_TRY(dev(launch_sum_loss(L, w, batch_numel(table), loss, st)));
+    return GS_OK;
 }
 
 gs_status gs_l1_loss_value(const gs_config* cfg, const gs_image* images, int32_t n_img,
@@ -488,12 +525,13 @@ gs_status gs_graph_create(const gs_config* cfg, const gs_image* images, int32_t 
         (void)hipStreamDestroy(cs);
         return GS_E_DEVICE;
     }
-    st = gs_raster_forward(cfg, images, n_img, mean, chol, color, opacity, radius, n_gauss,
-                           workspace, ws_bytes, out, cs);
-    if (st == GS_OK && target)
-        st = gs_raster_backward_l1(cfg, images, n_img, chol, color, opacity, n_gauss, workspace,
-                                   ws_bytes, out, target, grad_mean, grad_chol, grad_color,
-                                   grad_opacity, loss, cs);
+    if (target)
+        st = gs_raster_step_l1(cfg, images, n_img, mean, chol, color, opacity, radius, n_gauss,
+                               workspace, ws_bytes, out, target, grad_mean, grad_chol,
+                               grad_color, grad_opacity, loss, cs);
+    else
+        st = gs_raster_forward(cfg, images, n_img, mean, chol, color, opacity, radius,
+                               n_gauss, workspace, ws_bytes, out, cs);
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(cs, &g);
     (void)hipStreamDestroy(cs);

@@ -200,6 +200,9 @@ hipError_t launch_render_bwd(const Layout& L, const Ws& w, const float* grad_out
                              hipStream_t st);
 hipError_t launch_render_bwd_l1(const Layout& L, const Ws& w, const float* out,
                                 const float* target, int64_t numel, hipStream_t st);
+// Forward render, L1 gradient and backward render of each tile in one kernel.
+hipError_t launch_render_fused_l1(const Layout& L, const Ws& w, float* out, const float* target,
+                                  int64_t numel, hipStream_t st);
 hipError_t launch_sum_loss(const Layout& L, const Ws& w, int64_t numel, double* loss,
                            hipStream_t st);
 hipError_t launch_finalize(const Layout& L, const Ws& w, const float* chol,

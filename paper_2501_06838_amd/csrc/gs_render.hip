@@ -54,27 +54,6 @@ struct TileShape {
     static constexpr int kBatch = kThreads;
 };
 
-// Gaussians staged per forward round (lds_batch): the per-block lists hold a
-// 48-byte record per (8x8 block, Gaussian), NB * B of them in LDS.
-template <int T>
-struct FwdShape {
-    static constexpr int kDefaultBatch = T == 8 ? 64 : (T == 16 ? 128 : 32);
-};
-
-template <int T, int B>
-struct FwdLds {
-    static constexpr int NB = TileShape<T>::kBlocks;
-    // per 8x8 block j, compacted in ascending Gaussian order:
-    //   l0 = {z1, z2 at the block's first pixel, a, e}
-    //   l1 = {g, A0, A1, A2},  l2 = {lane mask lo, lane mask hi, -, -}
-    // (equal strides: one address register walks all three)
-    float4 l0[NB][B];
-    float4 l1[NB][B];
-    uint4 l2[NB][B];
-    int scount[NB];
-    int wcount[TileShape<T>::kWaves][NB];
-};
-
 // Persistent tile kernels.  The items (the longest-first tile order) are
 // dealt round-robin to K = min(16, grid) partitions, item i to partition
 // i % K, whose workgroups are p, p + K, p + 2K, ...  A workgroup's first item
@@ -117,112 +96,300 @@ __device__ __forceinline__ void run_persistent(uint32_t* ctrs, int64_t n_items, 
     }
 }
 
+// Gaussians staged per round (lds_batch).  Per 8x8 block of the tile the
+// staged Gaussians touching it are compacted, in staged (ascending Gaussian)
+// order, into a list of 48-byte records:
+//   l0 = {z1, z2 at the block's first pixel, a, e}
+//   l1 = {g, A0, A1, A2}
+//   l2 = {pixel mask lo, pixel mask hi, staged index, -}
+// (equal strides: one address register walks all three).  For the block's
+// pixel (dx, dy): z1 = z1_0 + a dx, z2 = z2_0 + e dy - g dx, and the
+// Gaussian's contribution is A_c exp2(-(z1^2 + z2^2)) where the mask is set.
+template <int T, int B>
+struct StageLds {
+    static constexpr int NB = TileShape<T>::kBlocks;
+    float4 l0[NB][B];
+    float4 l1[NB][B];
+    uint4 l2[NB][B];
+    int scount[NB];
+    int wcount[TileShape<T>::kWaves][NB];
+};
+
+template <int T, int B>
+struct FwdLds {
+    StageLds<T, B> st;
+};
+
+// Backward and fused kernels: the records, the tile's upstream gradient and
+// the per (block, staged Gaussian) sums.
+template <int T, int B>
+struct BwdLds {
+    StageLds<T, B> st;
+    float4 gt[T * T];       // upstream gradient of the tile, {g0, g1, g2, 0}
+    float4 acc[TileShape<T>::kBlocks][B][2];
+    double lpart[TileShape<T>::kWaves];
+};
+
+// What a staging thread keeps about its Gaussian for the backward's sums.
+struct StagedMine {
+    uint32_t gid;
+    uint32_t touch;  // bit j: the Gaussian's box meets block j
+};
+
+// Stages entries [base, base + nb) of the tile's sorted pair records and
+// builds the per-block record lists.  Ends with a barrier.
+template <int T, int B>
+__device__ __forceinline__ StagedMine stage_round(StageLds<T, B>& st,
+                                                  const PairRec* __restrict__ pairs, int base,
+                                                  int nb) {
+    using S = TileShape<T>;
+    constexpr int NB = S::kBlocks;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    StagedMine mine{0u, 0u};
+    PairRec r;
+    uint64_t my_mask[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) my_mask[j] = 0;
+    if (t < nb) {
+        r = pairs[base + t];
+        mine.gid = r.gid;
+        const int lx0 = r.box & 255, lx1 = (r.box >> 8) & 255;
+        const int ly0 = (r.box >> 16) & 255, ly1 = r.box >> 24;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int bx = (j % S::kBlocksX) * 8, by = (j / S::kBlocksX) * 8;
+            const int c0 = max(lx0, bx) - bx, c1 = min(lx1, bx + 7) - bx;
+            const int r0 = max(ly0, by) - by, r1 = min(ly1, by + 7) - by;
+            if (c0 <= c1 && r0 <= r1) {
+                const uint64_t cols = ((1ull << (c1 - c0 + 1)) - 1ull) << c0;
+                my_mask[j] = (cols * 0x0101010101010101ull) & rows_mask(r0, r1);
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const uint64_t bal = __ballot(my_mask[j] != 0);
+        if (lane == 0) st.wcount[wave][j] = __popcll(bal);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const uint64_t bal = __ballot(my_mask[j] != 0);
+        if (my_mask[j] != 0) {
+            int pos = __popcll(bal & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+            for (int w = 0; w < wave; ++w) pos += st.wcount[w][j];
+            const int bx = (j % S::kBlocksX) * 8, by = (j / S::kBlocksX) * 8;
+            // block origin relative to the HR centre: exact integer part, one
+            // rounding for the fraction
+            const float Xb = (r.kxr + (float)bx) - r.fx;
+            const float Yb = (r.kyr + (float)by) - r.fy;
+            st.l0[j][pos] = make_float4(r.a * Xb, r.e * Yb - r.g * Xb, r.a, r.e);
+            st.l1[j][pos] = make_float4(r.g, r.A[0], r.A[1], r.A[2]);
+            st.l2[j][pos] = make_uint4((uint32_t)my_mask[j], (uint32_t)(my_mask[j] >> 32),
+                                       (uint32_t)t, 0u);
+            mine.touch |= 1u << j;
+        }
+    }
+    if (t < NB) {
+        int c = 0;
+        for (int w = 0; w < S::kWaves; ++w) c += st.wcount[w][t];
+        st.scount[t] = c;
+    }
+    __syncthreads();
+    return mine;
+}
+
+// Forward sums of one round: lane = pixel of the wave's blocks, the block's
+// records in list order (wave-uniform), out-of-box lanes masked by the SGPR
+// lane mask.
+template <int T, int B>
+__device__ __forceinline__ void fwd_round(const StageLds<T, B>& st,
+                                          float (&acc)[TileShape<T>::kBlocksPerWave][3]) {
+    using S = TileShape<T>;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const float lxf = (float)(lane & 7), lyf = (float)(lane >> 3);
+#pragma unroll
+    for (int m = 0; m < S::kBlocksPerWave; ++m) {
+        const int j = wave + S::kWaves * m;
+        const int cnt = __builtin_amdgcn_readfirstlane(st.scount[j]);  // uniform
+        for (int q = 0; q < cnt; ++q) {
+            const float4 c0 = st.l0[j][q], c1 = st.l1[j][q];
+            const uint32_t mlo = __builtin_amdgcn_readfirstlane(st.l2[j][q].x);
+            const uint32_t mhi = __builtin_amdgcn_readfirstlane(st.l2[j][q].y);
+            const uint64_t mask = ((uint64_t)mhi << 32) | mlo;
+            const float z1 = __builtin_fmaf(c0.z, lxf, c0.x);
+            const float z2 = __builtin_fmaf(c0.w, lyf, __builtin_fmaf(-c1.x, lxf, c0.y));
+            float w = fast_exp2(-(z1 * z1 + z2 * z2));
+            w = __builtin_amdgcn_inverse_ballot_w64(mask) ? w : 0.f;
+            acc[m][0] += c1.y * w;
+            acc[m][1] += c1.z * w;
+            acc[m][2] += c1.w * w;
+        }
+    }
+}
+
+// Backward sums of one round.  The (block, Gaussian) records of all blocks,
+// block after block, go 64 to a wave, one per lane; a pass walks the
+// block-local pixels of the union of its lanes' boxes with all lanes
+// together, each lane reading the upstream gradient of its own block, so the
+// loop is uniform and each lane accumulates the eight sums of its own
+// Gaussian in registers (no cross-lane reduction, no atomics).  A lane's
+// values depend only on its own record, never on which records share its
+// pass.  Each (block, staged Gaussian) writes its sums once.  Ends with a
+// barrier.
+template <int T, int B>
+__device__ __forceinline__ void bwd_round(BwdLds<T, B>& sm) {
+    using S = TileShape<T>;
+    constexpr int NB = S::kBlocks, NW = S::kWaves;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int total = 0;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) total += sm.st.scount[j];
+    total = __builtin_amdgcn_readfirstlane(total);  // uniform
+    for (int f0 = wave * 64; f0 < total; f0 += NW * 64) {
+        const int f = f0 + lane;
+        const bool active = f < total;
+        int j = 0, pos = f;
+#pragma unroll
+        for (int k = 0; k + 1 < NB; ++k) {
+            if (j == k && pos >= sm.st.scount[k]) { pos -= sm.st.scount[k]; j = k + 1; }
+        }
+        if (!active) { j = 0; pos = 0; }
+        const float4 c0 = sm.st.l0[j][pos], c1 = sm.st.l1[j][pos];
+        const uint4 c2 = sm.st.l2[j][pos];
+        const uint32_t mlo = active ? c2.x : 0u, mhi = active ? c2.y : 0u;
+        const int bx = (j % S::kBlocksX) * 8, by = (j / S::kBlocksX) * 8;
+        // block-local rows and columns the wave's boxes cover
+        uint32_t cm = mlo | mhi;
+        cm |= cm >> 16;
+        cm |= cm >> 8;
+        uint32_t rows = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            rows |= ((mlo >> (8 * k)) & 255u) ? (1u << k) : 0u;
+            rows |= ((mhi >> (8 * k)) & 255u) ? (1u << (k + 4)) : 0u;
+        }
+        uint32_t any = (cm & 255u) | (rows << 8);
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) any |= (uint32_t)__shfl_xor((int)any, o, 64);
+        any = __builtin_amdgcn_readfirstlane(any);
+        const int cx0 = __builtin_ctz(any & 255u), cx1 = 31 - __builtin_clz(any & 255u);
+        const int ry0 = __builtin_ctz(any >> 8), ry1 = 31 - __builtin_clz(any >> 8);
+        const float a = c0.z, e = c0.w, gg = c1.x;
+        float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f, m5 = 0.f, m6 = 0.f, m7 = 0.f;
+        for (int ry = ry0; ry <= ry1; ++ry) {
+            const uint32_t rowbits = ((ry < 4 ? mlo : mhi) >> (8 * (ry & 3))) & 255u;
+            const float4* grow = &sm.gt[(by + ry) * T + bx];
+#pragma unroll
+            for (int cx = 0; cx < 8; ++cx) {
+                if (cx < cx0 || cx > cx1) continue;  // uniform
+                const float4 G = grow[cx];
+                const float z1 = __builtin_fmaf(a, (float)cx, c0.x);
+                const float z2 = __builtin_fmaf(e, (float)ry, __builtin_fmaf(-gg, (float)cx, c0.y));
+                float w = fast_exp2(-(z1 * z1 + z2 * z2));
+                w = (rowbits & (1u << cx)) ? w : 0.f;
+                m0 += G.x * w;
+                m1 += G.y * w;
+                m2 += G.z * w;
+                const float hw = (c1.y * G.x + c1.z * G.y + c1.w * G.z) * w;
+                const float t1 = hw * z1, t2 = hw * z2;
+                m3 += t1;
+                m4 += t2;
+                m5 += t1 * z1;
+                m6 += t1 * z2;
+                m7 += t2 * z2;
+            }
+        }
+        if (active) {
+            sm.acc[j][c2.z][0] = make_float4(m0, m1, m2, m3);
+            sm.acc[j][c2.z][1] = make_float4(m4, m5, m6, m7);
+        }
+    }
+    __syncthreads();
+}
+
+// The round's sums per (tile, Gaussian): blocks added in ascending order,
+// stored per sorted pair (or added with global atomics).  Ends with a barrier.
+template <int T, int B>
+__device__ __forceinline__ void bwd_round_store(BwdLds<T, B>& sm, StagedMine mine, int base,
+                                                int nb, float* __restrict__ moments,
+                                                float4* __restrict__ partials,
+                                                int atomic_grads) {
+    constexpr int NB = TileShape<T>::kBlocks;
+    const int t = threadIdx.x;
+    if (t < nb) {
+        float4 u = make_float4(0.f, 0.f, 0.f, 0.f), v = u;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            if (mine.touch & (1u << j)) {
+                const float4 a0 = sm.acc[j][t][0], a1 = sm.acc[j][t][1];
+                u.x += a0.x; u.y += a0.y; u.z += a0.z; u.w += a0.w;
+                v.x += a1.x; v.y += a1.y; v.z += a1.z; v.w += a1.w;
+            }
+        }
+        if (atomic_grads) {
+            // one FP32 global atomic per (tile, Gaussian, sum)
+            float* dst = moments + (int64_t)mine.gid * 8;
+            const float vals[8] = {u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int m = 0; m < 8; ++m)
+                if (vals[m] != 0.f) atomicAdd(dst + m, vals[m]);
+        } else {
+            // the (tile, Gaussian) sums, coalesced in sorted pair order; the
+            // gradient kernel adds each Gaussian's pairs in a fixed order
+            float4* dst = partials + 2 * (int64_t)(base + t);
+            dst[0] = u;
+            dst[1] = v;
+        }
+    }
+    __syncthreads();
+}
+
+// Tile geometry and list.
+struct TileInfo {
+    ImgDev im;
+    int px0, py0;
+    int2 rg;
+};
+
+template <int T, typename Table>
+__device__ __forceinline__ TileInfo tile_info(const Table& imgs, int n_img,
+                                              const int2* __restrict__ ranges, int64_t tile) {
+    TileInfo ti;
+    const int k_img = tile_image(imgs, n_img, tile);
+    ti.im = imgs[k_img];
+    const int64_t lt = tile - ti.im.tile_base;
+    ti.px0 = (int)(lt % ti.im.tiles_x) * T;
+    ti.py0 = (int)(lt / ti.im.tiles_x) * T;
+    ti.rg = ranges[tile];
+    return ti;
+}
+
 template <int T, int B, typename Table>
 __device__ __forceinline__ void fwd_tile(FwdLds<T, B>& sm, const Table& imgs, int n_img,
                                          const PairRec* __restrict__ pairs,
                                          const int2* __restrict__ ranges,
                                          float* __restrict__ out, int64_t tile) {
     using S = TileShape<T>;
-    constexpr int NB = S::kBlocks;
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int k_img = tile_image(imgs, n_img, tile);
-    const ImgDev im = imgs[k_img];
-    const int64_t lt = tile - im.tile_base;
-    const int px0 = (int)(lt % im.tiles_x) * T, py0 = (int)(lt / im.tiles_x) * T;
-    const int2 rg = ranges[tile];
-
-    const float lxf = (float)(lane & 7), lyf = (float)(lane >> 3);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const TileInfo ti = tile_info<T>(imgs, n_img, ranges, tile);
     float acc[S::kBlocksPerWave][3];
 #pragma unroll
     for (int m = 0; m < S::kBlocksPerWave; ++m) acc[m][0] = acc[m][1] = acc[m][2] = 0.f;
-
-    for (int base = rg.x; base < rg.y; base += B) {
-        const int nb = min(B, rg.y - base);
-        PairRec r;
-        uint64_t my_mask[NB];
-#pragma unroll
-        for (int j = 0; j < NB; ++j) my_mask[j] = 0;
-        if (t < nb) {
-            r = pairs[base + t];
-            const int lx0 = r.box & 255, lx1 = (r.box >> 8) & 255;
-            const int ly0 = (r.box >> 16) & 255, ly1 = r.box >> 24;
-#pragma unroll
-            for (int j = 0; j < NB; ++j) {
-                const int bx = (j % S::kBlocksX) * 8, by = (j / S::kBlocksX) * 8;
-                const int c0 = max(lx0, bx) - bx, c1 = min(lx1, bx + 7) - bx;
-                const int r0 = max(ly0, by) - by, r1 = min(ly1, by + 7) - by;
-                if (c0 <= c1 && r0 <= r1) {
-                    const uint64_t cols = ((1ull << (c1 - c0 + 1)) - 1ull) << c0;
-                    my_mask[j] = (cols * 0x0101010101010101ull) & rows_mask(r0, r1);
-                }
-            }
-        }
-        // compaction, preserving the staged (ascending Gaussian) order
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-            const uint64_t bal = __ballot(my_mask[j] != 0);
-            if (lane == 0) sm.wcount[wave][j] = __popcll(bal);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-            const uint64_t bal = __ballot(my_mask[j] != 0);
-            if (my_mask[j] != 0) {
-                int pos = __popcll(bal & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
-                for (int w = 0; w < wave; ++w) pos += sm.wcount[w][j];
-                const int bx = (j % S::kBlocksX) * 8, by = (j / S::kBlocksX) * 8;
-                // block origin relative to the HR centre: exact integer part,
-                // one rounding for the fraction
-                const float Xb = (r.kxr + (float)bx) - r.fx;
-                const float Yb = (r.kyr + (float)by) - r.fy;
-                sm.l0[j][pos] = make_float4(r.a * Xb, r.e * Yb - r.g * Xb, r.a, r.e);
-                sm.l1[j][pos] = make_float4(r.g, r.A[0], r.A[1], r.A[2]);
-                sm.l2[j][pos] = make_uint4((uint32_t)my_mask[j], (uint32_t)(my_mask[j] >> 32), 0u, 0u);
-            }
-        }
-        if (t < NB) {
-            int c = 0;
-            for (int w = 0; w < S::kWaves; ++w) c += sm.wcount[w][t];
-            sm.scount[t] = c;
-        }
-        __syncthreads();
-
-#pragma unroll
-        for (int m = 0; m < S::kBlocksPerWave; ++m) {
-            const int j = wave + S::kWaves * m;
-            const int cnt = __builtin_amdgcn_readfirstlane(sm.scount[j]);  // uniform
-            if (cnt == 0) continue;
-            // records are read one iteration ahead (fixed stride, no indirection)
-#pragma unroll 2
-            for (int q = 0; q < cnt; ++q) {
-                const float4 c0 = sm.l0[j][q], c1 = sm.l1[j][q];
-                const uint2 c2 = make_uint2(sm.l2[j][q].x, sm.l2[j][q].y);
-                const uint32_t mlo = __builtin_amdgcn_readfirstlane(c2.x);
-                const uint32_t mhi = __builtin_amdgcn_readfirstlane(c2.y);
-                const uint64_t mask = ((uint64_t)mhi << 32) | mlo;
-                // z at this lane's pixel: the block's first pixel plus the
-                // in-block offset (dx, dy)
-                const float z1 = __builtin_fmaf(c0.z, lxf, c0.x);
-                const float z2 = __builtin_fmaf(c0.w, lyf, __builtin_fmaf(-c1.x, lxf, c0.y));
-                float w = fast_exp2(-(z1 * z1 + z2 * z2));
-                w = __builtin_amdgcn_inverse_ballot_w64(mask) ? w : 0.f;
-                acc[m][0] += c1.y * w;
-                acc[m][1] += c1.z * w;
-                acc[m][2] += c1.w * w;
-            }
-        }
+    for (int base = ti.rg.x; base < ti.rg.y; base += B) {
+        stage_round<T, B>(sm.st, pairs, base, min(B, ti.rg.y - base));
+        fwd_round<T, B>(sm.st, acc);
         __syncthreads();
     }
-
-    const int64_t plane = (int64_t)im.out_w * im.out_h;
-    float* o = out + im.out_offset;
+    const int64_t plane = (int64_t)ti.im.out_w * ti.im.out_h;
+    float* o = out + ti.im.out_offset;
 #pragma unroll
     for (int m = 0; m < S::kBlocksPerWave; ++m) {
         const int j = wave + S::kWaves * m;
-        const int x = px0 + (j % S::kBlocksX) * 8 + (lane & 7);
-        const int y = py0 + (j / S::kBlocksX) * 8 + (lane >> 3);
-        if (x < im.out_w && y < im.out_h) {
-            const int64_t p = (int64_t)y * im.out_w + x;
+        const int x = ti.px0 + (j % S::kBlocksX) * 8 + (lane & 7);
+        const int y = ti.py0 + (j / S::kBlocksX) * 8 + (lane >> 3);
+        if (x < ti.im.out_w && y < ti.im.out_h) {
+            const int64_t p = (int64_t)y * ti.im.out_w + x;
             o[p] = acc[m][0];
             o[plane + p] = acc[m][1];
             o[2 * plane + p] = acc[m][2];
@@ -230,55 +397,24 @@ __device__ __forceinline__ void fwd_tile(FwdLds<T, B>& sm, const Table& imgs, in
     }
 }
 
-// One tile per workgroup (grid of n_tiles), or, with `persistent`, a grid
-// sized to the resident workgroups that walks the longest-first tile order.
-template <int T, int B, typename Table>
-__global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_fwd(
-    Table imgs, int n_img, const PairRec* __restrict__ pairs,
-    const int2* __restrict__ ranges, float* __restrict__ out,
-    const uint32_t* __restrict__ order, const WsHeader* __restrict__ hdr, int64_t n_tiles,
-    int persistent, uint32_t* __restrict__ sched) {
-    __shared__ FwdLds<T, B> sm;
-    if (!persistent) {
-        fwd_tile<T, B>(sm, imgs, n_img, pairs, ranges, out, (int64_t)blockIdx.x);
-        return;
+// Reduces the tile's L1 partial sum (one per thread) into tile_loss[tile].
+template <int T, int B>
+__device__ __forceinline__ void tile_loss_sum(BwdLds<T, B>& sm, double lsum,
+                                              double* __restrict__ tile_loss, int64_t tile) {
+    constexpr int NW = TileShape<T>::kWaves;
+    for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o, 64);
+    if ((threadIdx.x & 63) == 0) sm.lpart[threadIdx.x >> 6] = lsum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sum = 0.0;
+        for (int k = 0; k < NW; ++k) sum += sm.lpart[k];
+        tile_loss[tile] = sum;
     }
-    // without a tile order from the matching binning, items are tiles
-    const bool ordered = hdr->ordered != 0;
-    run_persistent(sched, n_tiles, [&](int64_t item) {
-        const int64_t tile = ordered ? (int64_t)order[item] : item;
-        if (tile < n_tiles) fwd_tile<T, B>(sm, imgs, n_img, pairs, ranges, out, tile);
-    });
 }
 
 // kL1: the upstream gradient is the L1 loss's, sign(out - target) / numel,
 // formed here from the rendered image and the target (it is never stored),
 // and the tile's share of sum |out - target| goes to tile_loss[tile].
-template <int T, int B>
-struct BwdLds {
-    static constexpr int NB = TileShape<T>::kBlocks, NW = TileShape<T>::kWaves;
-    float4 gt[T * T];       // upstream gradient of the tile, {g0, g1, g2, 0}
-    float4 r0[B];           // staged Gaussian: {kxr, kyr, fx, fy}
-    float4 r1[B];           // {a, e, g, A0}
-    float2 r2[B];           // {A1, A2}
-    uint2 bm[NB][B];        // per 8x8 block, compacted: pixel mask of the box
-    short lst[NB][B];       // per 8x8 block, compacted: staged index
-    int bcount[NB];
-    int wcount[NW][NB];
-    float4 acc[NB][B][2];   // per (block, staged Gaussian): the eight sums
-    double lpart[NW];
-};
-
-// One tile of the backward.  Per round, B listed Gaussians are staged and,
-// per 8x8 block, compacted into the list of those whose box touches it (with
-// the box's 64-bit pixel mask), as in the forward.  A wave then takes a
-// block and puts one Gaussian of its list on each lane; all lanes walk the
-// block's pixels together (the union of their boxes), so the pixel, its
-// upstream gradient and the loop are uniform over the wave, and each lane
-// accumulates its own Gaussian's eight sums in registers: no cross-lane
-// reduction, no atomics, no divergence.  Along a row z1 and z2 advance by
-// constant steps.  Each (block, Gaussian) writes its sums once; the tile's
-// sums per Gaussian add the blocks in ascending order (bitwise reproducible).
 template <int T, int B, bool kL1, typename Table>
 __device__ __forceinline__ void bwd_tile(
     BwdLds<T, B>& sm, const Table& imgs, int n_img, const PairRec* __restrict__ pairs,
@@ -287,25 +423,21 @@ __device__ __forceinline__ void bwd_tile(
     float* __restrict__ moments, float4* __restrict__ partials, int atomic_grads,
     int64_t tile) {
     using S = TileShape<T>;
-    constexpr int NT = S::kThreads, NB = S::kBlocks, NW = S::kWaves;
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int k_img = tile_image(imgs, n_img, tile);
-    const ImgDev im = imgs[k_img];
-    const int64_t lt = tile - im.tile_base;
-    const int px0 = (int)(lt % im.tiles_x) * T, py0 = (int)(lt / im.tiles_x) * T;
-    const int2 rg = ranges[tile];
-    if (!kL1 && rg.y <= rg.x) return;  // uniform: nothing listed in this tile
+    constexpr int NT = S::kThreads;
+    const int t = threadIdx.x;
+    const TileInfo ti = tile_info<T>(imgs, n_img, ranges, tile);
+    if (!kL1 && ti.rg.y <= ti.rg.x) return;  // uniform: nothing listed in this tile
 
-    const int64_t plane = (int64_t)im.out_w * im.out_h;
-    const float* g = grad_out + im.out_offset;
+    const int64_t plane = (int64_t)ti.im.out_w * ti.im.out_h;
+    const float* g = grad_out + ti.im.out_offset;
     double lsum = 0.0;
     for (int p = t; p < T * T; p += NT) {
-        const int x = px0 + (p % T), y = py0 + (p / T);
+        const int x = ti.px0 + (p % T), y = ti.py0 + (p / T);
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (x < im.out_w && y < im.out_h) {
-            const int64_t q = (int64_t)y * im.out_w + x;
+        if (x < ti.im.out_w && y < ti.im.out_h) {
+            const int64_t q = (int64_t)y * ti.im.out_w + x;
             if (kL1) {
-                const float* tg = target + im.out_offset;
+                const float* tg = target + ti.im.out_offset;
                 float gv[3];
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
@@ -320,176 +452,103 @@ __device__ __forceinline__ void bwd_tile(
         }
         sm.gt[p] = v;
     }
-    if (kL1) {
-        for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o, 64);
-        if (lane == 0) sm.lpart[wave] = lsum;
-        __syncthreads();
-        if (t == 0) {
-            double sum = 0.0;
-            for (int k = 0; k < NW; ++k) sum += sm.lpart[k];
-            tile_loss[tile] = sum;
-        }
-        if (rg.y <= rg.x) return;  // uniform
-    } else {
-        __syncthreads();
-    }
+    if (kL1) tile_loss_sum<T, B>(sm, lsum, tile_loss, tile);  // has a barrier
 
-    for (int base = rg.x; base < rg.y; base += B) {
-        const int nb = min(B, rg.y - base);
-        uint64_t my_mask[NB];
-#pragma unroll
-        for (int j = 0; j < NB; ++j) my_mask[j] = 0;
-        uint32_t my_gid = 0, touch = 0;
-        if (t < nb) {
-            const PairRec r = pairs[base + t];
-            my_gid = r.gid;
-            sm.r0[t] = make_float4(r.kxr, r.kyr, r.fx, r.fy);
-            sm.r1[t] = make_float4(r.a, r.e, r.g, r.A[0]);
-            sm.r2[t] = make_float2(r.A[1], r.A[2]);
-            const int lx0 = r.box & 255, lx1 = (r.box >> 8) & 255;
-            const int ly0 = (r.box >> 16) & 255, ly1 = r.box >> 24;
-#pragma unroll
-            for (int j = 0; j < NB; ++j) {
-                const int bx = (j % S::kBlocksX) * 8, by = (j / S::kBlocksX) * 8;
-                const int c0 = max(lx0, bx) - bx, c1 = min(lx1, bx + 7) - bx;
-                const int r0 = max(ly0, by) - by, r1 = min(ly1, by + 7) - by;
-                if (c0 <= c1 && r0 <= r1) {
-                    const uint64_t cols = ((1ull << (c1 - c0 + 1)) - 1ull) << c0;
-                    my_mask[j] = (cols * 0x0101010101010101ull) & rows_mask(r0, r1);
-                }
-            }
-        }
-        // per-block lists, in staged order
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-            const uint64_t bal = __ballot(my_mask[j] != 0);
-            if (lane == 0) sm.wcount[wave][j] = __popcll(bal);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-            const uint64_t bal = __ballot(my_mask[j] != 0);
-            if (my_mask[j] != 0) {
-                int pos = __popcll(bal & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
-                for (int w = 0; w < wave; ++w) pos += sm.wcount[w][j];
-                sm.bm[j][pos] = make_uint2((uint32_t)my_mask[j], (uint32_t)(my_mask[j] >> 32));
-                sm.lst[j][pos] = (short)t;
-                touch |= 1u << j;
-            }
-        }
-        if (t < NB) {
-            int c = 0;
-            for (int w = 0; w < NW; ++w) c += sm.wcount[w][t];
-            sm.bcount[t] = c;
-        }
-        __syncthreads();
-
-        // The (block, Gaussian) records of all blocks, block after block, go
-        // 64 to a wave: a pass walks the block-local pixels of the union of
-        // its lanes' boxes, each lane reading the gradient of its own block.
-        int total = 0;
-#pragma unroll
-        for (int j = 0; j < NB; ++j) total += sm.bcount[j];
-        total = __builtin_amdgcn_readfirstlane(total);  // uniform
-        for (int f0 = wave * 64; f0 < total; f0 += NW * 64) {
-            const int f = f0 + lane;
-            const bool active = f < total;
-            int j = 0, pos = f;
-#pragma unroll
-            for (int k = 0; k + 1 < NB; ++k) {
-                if (j == k && pos >= sm.bcount[k]) { pos -= sm.bcount[k]; j = k + 1; }
-            }
-            if (!active) { j = 0; pos = 0; }
-            const int ti = active ? (int)sm.lst[j][pos] : 0;
-            const uint2 mk = active ? sm.bm[j][pos] : make_uint2(0u, 0u);
-            const int bx = (j % S::kBlocksX) * 8, by = (j / S::kBlocksX) * 8;
-            const float4 q0 = sm.r0[ti], q1 = sm.r1[ti];
-            const float2 q2 = sm.r2[ti];
-            // block-local rows and columns the wave's boxes cover
-            uint32_t cm = mk.x | mk.y;
-            cm |= cm >> 16;
-            cm |= cm >> 8;
-            uint32_t rows = 0;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                rows |= ((mk.x >> (8 * k)) & 255u) ? (1u << k) : 0u;
-                rows |= ((mk.y >> (8 * k)) & 255u) ? (1u << (k + 4)) : 0u;
-            }
-            uint32_t any = (cm & 255u) | (rows << 8);
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) any |= (uint32_t)__shfl_xor((int)any, o, 64);
-            any = __builtin_amdgcn_readfirstlane(any);
-            const int cx0 = __builtin_ctz(any & 255u), cx1 = 31 - __builtin_clz(any & 255u);
-            const int ry0 = __builtin_ctz(any >> 8), ry1 = 31 - __builtin_clz(any >> 8);
-            const float a = q1.x, e = q1.y, gg = q1.z;
-            float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f, m5 = 0.f, m6 = 0.f, m7 = 0.f;
-            for (int ry = ry0; ry <= ry1; ++ry) {
-                const uint32_t rowbits = ((ry < 4 ? mk.x : mk.y) >> (8 * (ry & 3))) & 255u;
-                // z at the block's first column, then advanced column by column
-                // (also over columns outside the union), so a lane's values do
-                // not depend on which Gaussians share its pass
-                const float Y = (q0.y + (float)(by + ry)) - q0.w;
-                const float X0 = (q0.x + (float)bx) - q0.z;
-                float z1 = a * X0;
-                float z2 = e * Y - gg * X0;
-                const float4* grow = &sm.gt[(by + ry) * T + bx];
-#pragma unroll
-                for (int cx = 0; cx < 8; ++cx) {
-                    if (cx < cx0 || cx > cx1) {  // uniform
-                        z1 += a;
-                        z2 -= gg;
-                        continue;
-                    }
-                    const float4 G = grow[cx];
-                    float w = fast_exp2(-(z1 * z1 + z2 * z2));
-                    w = (rowbits & (1u << cx)) ? w : 0.f;
-                    m0 += G.x * w;
-                    m1 += G.y * w;
-                    m2 += G.z * w;
-                    const float hw = (q1.w * G.x + q2.x * G.y + q2.y * G.z) * w;
-                    const float t1 = hw * z1, t2 = hw * z2;
-                    m3 += t1;
-                    m4 += t2;
-                    m5 += t1 * z1;
-                    m6 += t1 * z2;
-                    m7 += t2 * z2;
-                    z1 += a;
-                    z2 -= gg;
-                }
-            }
-            if (active) {
-                sm.acc[j][ti][0] = make_float4(m0, m1, m2, m3);
-                sm.acc[j][ti][1] = make_float4(m4, m5, m6, m7);
-            }
-        }
-        __syncthreads();
-        if (t < nb) {
-            float4 u = make_float4(0.f, 0.f, 0.f, 0.f), v = u;
-#pragma unroll
-            for (int j = 0; j < NB; ++j) {
-                if (touch & (1u << j)) {
-                    const float4 a0 = sm.acc[j][t][0], a1 = sm.acc[j][t][1];
-                    u.x += a0.x; u.y += a0.y; u.z += a0.z; u.w += a0.w;
-                    v.x += a1.x; v.y += a1.y; v.z += a1.z; v.w += a1.w;
-                }
-            }
-            if (atomic_grads) {
-                // one FP32 global atomic per (tile, Gaussian, sum)
-                float* dst = moments + (int64_t)my_gid * 8;
-                const float vals[8] = {u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
-#pragma unroll
-                for (int m = 0; m < 8; ++m)
-                    if (vals[m] != 0.f) atomicAdd(dst + m, vals[m]);
-            } else {
-                // the (tile, Gaussian) sums, coalesced in sorted pair order;
-                // the gradient kernel adds each Gaussian's pairs in a fixed order
-                float4* dst = partials + 2 * (int64_t)(base + t);
-                dst[0] = u;
-                dst[1] = v;
-            }
-        }
-        __syncthreads();
+    for (int base = ti.rg.x; base < ti.rg.y; base += B) {
+        const int nb = min(B, ti.rg.y - base);
+        const StagedMine mine = stage_round<T, B>(sm.st, pairs, base, nb);
+        bwd_round<T, B>(sm);
+        bwd_round_store<T, B>(sm, mine, base, nb, moments, partials, atomic_grads);
     }
+}
+
+// Forward, L1 gradient and backward of one tile in one pass: the image is
+// summed in registers and stored; each lane forms the L1 gradient of its own
+// pixels from them and the target into LDS (with the tile's L1 sum); the
+// backward then runs over the same records, which stay staged when the
+// tile's list fits one round.
+template <int T, int B, typename Table>
+__device__ __forceinline__ void fused_tile(
+    BwdLds<T, B>& sm, const Table& imgs, int n_img, const PairRec* __restrict__ pairs,
+    const int2* __restrict__ ranges, float* __restrict__ out, const float* __restrict__ target,
+    float inv_numel, double* __restrict__ tile_loss, float* __restrict__ moments,
+    float4* __restrict__ partials, int atomic_grads, int64_t tile) {
+    using S = TileShape<T>;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const TileInfo ti = tile_info<T>(imgs, n_img, ranges, tile);
+    float acc[S::kBlocksPerWave][3];
+#pragma unroll
+    for (int m = 0; m < S::kBlocksPerWave; ++m) acc[m][0] = acc[m][1] = acc[m][2] = 0.f;
+    const bool one_round = ti.rg.y - ti.rg.x <= B;
+    StagedMine mine{0u, 0u};
+    for (int base = ti.rg.x; base < ti.rg.y; base += B) {
+        mine = stage_round<T, B>(sm.st, pairs, base, min(B, ti.rg.y - base));
+        fwd_round<T, B>(sm.st, acc);
+        if (!one_round) __syncthreads();
+    }
+    const int64_t plane = (int64_t)ti.im.out_w * ti.im.out_h;
+    float* o = out + ti.im.out_offset;
+    const float* tg = target + ti.im.out_offset;
+    double lsum = 0.0;
+#pragma unroll
+    for (int m = 0; m < S::kBlocksPerWave; ++m) {
+        const int j = wave + S::kWaves * m;
+        const int lx = (j % S::kBlocksX) * 8 + (lane & 7);
+        const int ly = (j / S::kBlocksX) * 8 + (lane >> 3);
+        const int x = ti.px0 + lx, y = ti.py0 + ly;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (x < ti.im.out_w && y < ti.im.out_h) {
+            const int64_t p = (int64_t)y * ti.im.out_w + x;
+            o[p] = acc[m][0];
+            o[plane + p] = acc[m][1];
+            o[2 * plane + p] = acc[m][2];
+            float gv[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float tv = tg[c * plane + p];
+                const float d = acc[m][c] - tv;
+                gv[c] = d > 0.f ? inv_numel : (d < 0.f ? -inv_numel : 0.f);
+                lsum += fabs((double)acc[m][c] - (double)tv);
+            }
+            v = make_float4(gv[0], gv[1], gv[2], 0.f);
+        }
+        sm.gt[ly * T + lx] = v;
+    }
+    tile_loss_sum<T, B>(sm, lsum, tile_loss, tile);  // has a barrier
+    if (ti.rg.y <= ti.rg.x) return;  // uniform
+    if (one_round) {
+        bwd_round<T, B>(sm);
+        bwd_round_store<T, B>(sm, mine, ti.rg.x, ti.rg.y - ti.rg.x, moments, partials,
+                              atomic_grads);
+        return;
+    }
+    for (int base = ti.rg.x; base < ti.rg.y; base += B) {
+        const int nb = min(B, ti.rg.y - base);
+        mine = stage_round<T, B>(sm.st, pairs, base, nb);
+        bwd_round<T, B>(sm);
+        bwd_round_store<T, B>(sm, mine, base, nb, moments, partials, atomic_grads);
+    }
+}
+
+// One tile per workgroup (grid of n_tiles), or, with `persistent`, a grid
+// sized to the resident workgroups that walks the longest-first tile order
+// (without a tile order from the matching binning, items are tiles).
+template <int T, int B, typename Table>
+__global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_fwd(
+    Table imgs, int n_img, const PairRec* __restrict__ pairs,
+    const int2* __restrict__ ranges, float* __restrict__ out,
+    const uint32_t* __restrict__ order, const WsHeader* __restrict__ hdr, int64_t n_tiles,
+    int persistent, uint32_t* __restrict__ sched) {
+    __shared__ FwdLds<T, B> sm;
+    if (!persistent) {
+        fwd_tile<T, B>(sm, imgs, n_img, pairs, ranges, out, (int64_t)blockIdx.x);
+        return;
+    }
+    const bool ordered = hdr->ordered != 0;
+    run_persistent(sched, n_tiles, [&](int64_t item) {
+        const int64_t tile = ordered ? (int64_t)order[item] : item;
+        if (tile < n_tiles) fwd_tile<T, B>(sm, imgs, n_img, pairs, ranges, out, tile);
+    });
 }
 
 template <int T, int B, bool kL1, typename Table>
@@ -502,8 +561,8 @@ __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_bwd(
     int persistent, uint32_t* __restrict__ sched) {
     __shared__ BwdLds<T, B> sm;
     if (!persistent) {
-        bwd_tile<T, B, kL1>(sm, imgs, n_img, pairs, ranges, grad_out, target, inv_numel, tile_loss,
-                         moments, partials, atomic_grads, (int64_t)blockIdx.x);
+        bwd_tile<T, B, kL1>(sm, imgs, n_img, pairs, ranges, grad_out, target, inv_numel,
+                            tile_loss, moments, partials, atomic_grads, (int64_t)blockIdx.x);
         return;
     }
     const bool ordered = hdr->ordered != 0;
@@ -512,6 +571,29 @@ __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_bwd(
         if (tile < n_tiles)
             bwd_tile<T, B, kL1>(sm, imgs, n_img, pairs, ranges, grad_out, target, inv_numel,
                                 tile_loss, moments, partials, atomic_grads, tile);
+    });
+}
+
+template <int T, int B, typename Table>
+__global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_fused(
+    Table imgs, int n_img, const PairRec* __restrict__ pairs,
+    const int2* __restrict__ ranges, float* __restrict__ out,
+    const float* __restrict__ target, float inv_numel, double* __restrict__ tile_loss,
+    float* __restrict__ moments, float4* __restrict__ partials, int atomic_grads,
+    const uint32_t* __restrict__ order, const WsHeader* __restrict__ hdr, int64_t n_tiles,
+    int persistent, uint32_t* __restrict__ sched) {
+    __shared__ BwdLds<T, B> sm;
+    if (!persistent) {
+        fused_tile<T, B>(sm, imgs, n_img, pairs, ranges, out, target, inv_numel, tile_loss,
+                         moments, partials, atomic_grads, (int64_t)blockIdx.x);
+        return;
+    }
+    const bool ordered = hdr->ordered != 0;
+    run_persistent(sched, n_tiles, [&](int64_t item) {
+        const int64_t tile = ordered ? (int64_t)order[item] : item;
+        if (tile < n_tiles)
+            fused_tile<T, B>(sm, imgs, n_img, pairs, ranges, out, target, inv_numel, tile_loss,
+                             moments, partials, atomic_grads, tile);
     });
 }
 
@@ -772,6 +854,58 @@ hipError_t launch_render_bwd(const Layout& L, const Ws& w, const float* grad_out
 hipError_t launch_render_bwd_l1(const Layout& L, const Ws& w, const float* out,
                                 const float* target, int64_t numel, hipStream_t st) {
     return launch_bwd_any<true>(L, w, out, target, (float)(1.0 / (double)numel), st);
+}
+
+template <int T, int B, typename Table>
+static hipError_t launch_fused_tt(const Layout& L, const Ws& w, const Table& tab, float* out,
+                                  const float* target, float inv_numel, hipStream_t st) {
+    const auto kernel = k_render_fused<T, B, Table>;
+    unsigned grid = 0;
+    const hipError_t e = tile_grid(L, reinterpret_cast<const void*>(kernel),
+                                   TileShape<T>::kThreads, &grid);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(TileShape<T>::kThreads), 0, st, tab, L.n_img,
+                       w.pairs, w.ranges, out, target, inv_numel, w.tile_loss, w.moments,
+                       w.partials, (L.flags & GS_FLAG_ATOMIC_GRADS) ? 1 : 0, w.order, w.hdr,
+                       L.n_tiles, (L.flags & GS_FLAG_PERSISTENT) ? 1 : 0,
+                       w.sched + kSchedWords / 2);
+    return hipGetLastError();
+}
+
+template <typename Table>
+static hipError_t launch_fused_t(const Layout& L, const Ws& w, const Table& tab, float* out,
+                                 const float* target, float inv_numel, hipStream_t st) {
+    const int b = L.lds_batch;
+    switch (L.tile) {
+        case 8:
+            if (b == 32) return launch_fused_tt<8, 32>(L, w, tab, out, target, inv_numel, st);
+            if (b == 64) return launch_fused_tt<8, 64>(L, w, tab, out, target, inv_numel, st);
+            break;
+        case 16:
+            if (b == 64) return launch_fused_tt<16, 64>(L, w, tab, out, target, inv_numel, st);
+            if (b == 128) return launch_fused_tt<16, 128>(L, w, tab, out, target, inv_numel, st);
+            if (b == 256) return launch_fused_tt<16, 256>(L, w, tab, out, target, inv_numel, st);
+            break;
+        case 32:
+            if (b == 32) return launch_fused_tt<32, 32>(L, w, tab, out, target, inv_numel, st);
+            if (b == 64) return launch_fused_tt<32, 64>(L, w, tab, out, target, inv_numel, st);
+            break;
+        default:
+            break;
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_render_fused_l1(const Layout& L, const Ws& w, float* out, const float* target,
+                                  int64_t numel, hipStream_t st) {
+    if (L.n_tiles == 0) return hipSuccess;
+    const float inv = (float)(1.0 / (double)numel);
+    if (L.n_img <= kSetupChunk && L.host_imgs) {
+        ArgTable tab;
+        for (int k = 0; k < kSetupChunk; ++k) tab.c.img[k] = k < L.n_img ? L.host_imgs[k] : ImgDev{};
+        return launch_fused_t(L, w, tab, out, target, inv, st);
+    }
+    return launch_fused_t(L, w, MemTable{w.imgs}, out, target, inv, st);
 }
 
 hipError_t launch_finalize(const Layout& L, const Ws& w, const float* chol,

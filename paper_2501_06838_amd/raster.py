@@ -201,6 +201,29 @@ class RasterPlan:
                                                      _ptr(out), _ptr(target), _stream(stream)),
                 "render backward l1")
 
+    def render_fused_l1(self, workspace, out, target, stream=None, capacity=None):
+        """Forward render into out, L1 gradient against target and backward
+        render, per tile in one kernel (workspace from bin())."""
+        cfg = self.config(capacity)
+        N.check(N.lib().gs_raster_render_fused_l1(ctypes.byref(cfg), self._arr, len(self.images),
+                                                  self.n_gauss, _ptr(workspace),
+                                                  workspace.numel(), _ptr(out), _ptr(target),
+                                                  _stream(stream)), "render fused l1")
+
+    def step_l1(self, mean, chol, color, opacity, workspace, out, target, grads, loss=None,
+                radius=None, stream=None, capacity=None):
+        """One training step of the L1 loss: binning, fused render, gradients
+        (overwritten into grads = (mean, chol, color, opacity)) and, when
+        given, the mean loss into loss (device double)."""
+        cfg = self.config(capacity)
+        gm, gc, gcol, gop = grads
+        N.check(N.lib().gs_raster_step_l1(ctypes.byref(cfg), self._arr, len(self.images),
+                                          _ptr(mean), _ptr(chol), _ptr(color), _ptr(opacity),
+                                          _ptr(radius), self.n_gauss, _ptr(workspace),
+                                          workspace.numel(), _ptr(out), _ptr(target), _ptr(gm),
+                                          _ptr(gc), _ptr(gcol), _ptr(gop), _ptr(loss),
+                                          _stream(stream)), "step l1")
+
     def l1_loss_value(self, workspace, loss, stream=None, capacity=None):
         """Mean L1 loss of the last fused backward into `loss` (0-d float64 tensor)."""
         cfg = self.config(capacity)
