@@ -39,15 +39,15 @@ PEAK_HBM_GBS = 8000.0
 FLOPEQ_FWD = 32.0
 FLOPEQ_BWD = 48.0
 
-# HBM traffic of one k_render_bwd launch (fused L1) on config1 at tile 16, from
-# two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch,
-# averaged over the dispatches), each scaled by what the same counter reads for
-# a plain 256 MiB device copy: FETCH_SIZE reads 131,084 KiB (factor 2.0),
-# WRITE_SIZE 262,144 KiB (factor 1.0).  Valid only while the render sources
-# hash to `sources`; otherwise reported as null.
-TRAFFIC = {"workload": "config1", "launch": {"tile": 16, "lds_batch": 0, "flags": 0},
-           "sources": "f9ed41f8edf2007b",
-           "fetch_kib": 38085.5, "write_kib": 6604.7, "fetch_factor": 2.0, "write_factor": 1.0}
+# HBM traffic of one fused tile-kernel launch (k_render_fused) on config1 at
+# tile 16, LDS batch 64, from two rocprofv3 --pmc passes (FETCH_SIZE,
+# WRITE_SIZE; KiB per dispatch, averaged over the dispatches), each scaled by
+# what the same counter reads for a plain 256 MiB device copy: FETCH_SIZE
+# reads 131,085 KiB (factor 2.0), WRITE_SIZE 262,144 KiB (factor 1.0).  Valid
+# only while the render sources hash to `sources`; otherwise null.
+TRAFFIC = {"workload": "config1", "launch": {"tile": 16, "lds_batch": 64, "flags": 0},
+           "sources": "acd046206372b221",
+           "fetch_kib": 22634.6, "write_kib": 21821.3, "fetch_factor": 2.0, "write_factor": 1.0}
 TRAFFIC_SOURCES = ("paper_2501_06838_amd/csrc/gs_render.hip", "paper_2501_06838_amd/csrc/gs_internal.h")
 
 
