@@ -284,10 +284,8 @@ gs_status gs_raster_step_l1(const gs_config* cfg, const gs_image* images, int32_
     const Ws w = bind(L, workspace);
     GS_TRY(run_binning(L, w, table, mean, chol, color, opacity, radius, st));
     GS_TRY(dev(launch_render_fused_l1(L, w, out, target, batch_numel(table), st)));
-    GS_TRY(dev(launch_finalize(L, w, chol, color, opacity, grad_mean, grad_chol, grad_color,
-                               grad_opacity, st)));
-    if (loss) GS_TRY(dev(launch_sum_loss(L, w, batch_numel(table), loss, st)));
-    return GS_OK;
+    return dev(launch_finalize(L, w, chol, color, opacity, grad_mean, grad_chol, grad_color,
+                               grad_opacity, st, batch_numel(table), loss));
 }
 
 gs_status gs_l1_loss_value(const gs_config* cfg, const gs_image* images, int32_t n_img,

@@ -91,6 +91,7 @@ struct WsHeader {
     uint32_t reserved[4];
 };
 
+
 // Host-side workspace layout for one batch shape.
 struct Layout {
     int32_t n_img = 0;
@@ -205,10 +206,12 @@ hipError_t launch_render_fused_l1(const Layout& L, const Ws& w, float* out, cons
                                   int64_t numel, hipStream_t st);
 hipError_t launch_sum_loss(const Layout& L, const Ws& w, int64_t numel, double* loss,
                            hipStream_t st);
+// With loss not NULL, one more workgroup writes the mean of the per-tile L1
+// sums (numel output elements) to *loss.
 hipError_t launch_finalize(const Layout& L, const Ws& w, const float* chol,
                            const float* color, const float* opacity, float* grad_mean,
                            float* grad_chol, float* grad_color, float* grad_opacity,
-                           hipStream_t st);
+                           hipStream_t st, int64_t numel = 0, double* loss = nullptr);
 hipError_t launch_l1(const float* img, const float* target, int64_t numel, float* grad,
                      double* loss_sum, hipStream_t st);
 

@@ -597,6 +597,24 @@ __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_fused(
     });
 }
 
+// One workgroup of kBlockG threads: mean of the per-tile L1 partial sums,
+// in a fixed order.
+__device__ __forceinline__ void sum_loss_block(const double* __restrict__ tile_loss,
+                                               int64_t n_tiles, double inv_numel,
+                                               double* __restrict__ loss) {
+    __shared__ double part[kBlockG / 64];
+    double s = 0.0;
+    for (int64_t t = threadIdx.x; t < n_tiles; t += kBlockG) s += tile_loss[t];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sum = 0.0;
+        for (int k = 0; k < kBlockG / 64; ++k) sum += part[k];
+        *loss = sum * inv_numel;
+    }
+}
+
 // Moments -> gradients, per Gaussian, in FP64.  With K = 1/(2 pi l11 l22),
 // w = exp(-(z1^2 + z2^2)/2), z1 = (x/s - mu_x)/l11,
 // z2 = ((y/s - mu_y) - l21 z1)/l22, H = sum_c A_c dL/dI_c:
@@ -614,7 +632,13 @@ __global__ __launch_bounds__(kBlockG) void k_finalize(
     const int32_t* __restrict__ offsets, const uint32_t* __restrict__ inv,
     const float4* __restrict__ partials, const WsHeader* __restrict__ hdr, int64_t cap,
     int atomic_grads, float* __restrict__ grad_mean, float* __restrict__ grad_chol,
-    float* __restrict__ grad_color, float* __restrict__ grad_opacity) {
+    float* __restrict__ grad_color, float* __restrict__ grad_opacity,
+    const double* __restrict__ tile_loss, int64_t n_tiles, double inv_numel,
+    double* __restrict__ loss) {
+    if (loss && blockIdx.x == gridDim.x - 1) {  // the extra block: the L1 loss value
+        sum_loss_block(tile_loss, n_tiles, inv_numel, loss);
+        return;
+    }
     const int64_t i = (int64_t)blockIdx.x * kBlockG + threadIdx.x;
     if (i >= n_gauss) return;
     const GRec r = recs[i];
@@ -695,21 +719,10 @@ __global__ __launch_bounds__(kBlockG) void k_l1(const float* __restrict__ img,
     }
 }
 
-// One workgroup: mean of the per-tile L1 partial sums.
-__global__ __launch_bounds__(1024) void k_sum_loss(const double* __restrict__ tile_loss,
-                                                   int64_t n_tiles, double inv_numel,
-                                                   double* __restrict__ loss) {
-    __shared__ double part[1024 / 64];
-    double s = 0.0;
-    for (int64_t t = threadIdx.x; t < n_tiles; t += 1024) s += tile_loss[t];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double sum = 0.0;
-        for (int k = 0; k < 1024 / 64; ++k) sum += part[k];
-        *loss = sum * inv_numel;
-    }
+__global__ __launch_bounds__(kBlockG) void k_sum_loss(const double* __restrict__ tile_loss,
+                                                      int64_t n_tiles, double inv_numel,
+                                                      double* __restrict__ loss) {
+    sum_loss_block(tile_loss, n_tiles, inv_numel, loss);
 }
 
 inline int blocks_for(int64_t n, int per) { return (int)((n + per - 1) / per); }
@@ -718,7 +731,7 @@ inline int blocks_for(int64_t n, int per) { return (int)((n + per - 1) / per); }
 
 hipError_t launch_sum_loss(const Layout& L, const Ws& w, int64_t numel, double* loss,
                            hipStream_t st) {
-    hipLaunchKernelGGL(k_sum_loss, dim3(1), dim3(1024), 0, st, w.tile_loss, L.n_tiles,
+    hipLaunchKernelGGL(k_sum_loss, dim3(1), dim3(kBlockG), 0, st, w.tile_loss, L.n_tiles,
                        1.0 / (double)numel, loss);
     return hipGetLastError();
 }
@@ -911,13 +924,14 @@ hipError_t launch_render_fused_l1(const Layout& L, const Ws& w, float* out, cons
 hipError_t launch_finalize(const Layout& L, const Ws& w, const float* chol,
                            const float* color, const float* opacity, float* grad_mean,
                            float* grad_chol, float* grad_color, float* grad_opacity,
-                           hipStream_t st) {
-    if (L.n_gauss == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_finalize, dim3(blocks_for(L.n_gauss, kBlockG)), dim3(kBlockG), 0, st,
-                       w.recs, L.n_gauss, chol, color, opacity, w.moments, w.counts, w.offsets,
-                       w.inv, w.partials, w.hdr, L.cap,
-                       (L.flags & GS_FLAG_ATOMIC_GRADS) ? 1 : 0, grad_mean, grad_chol,
-                       grad_color, grad_opacity);
+                           hipStream_t st, int64_t numel, double* loss) {
+    const int nb = (int)blocks_for(L.n_gauss, kBlockG) + (loss ? 1 : 0);
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_finalize, dim3(nb), dim3(kBlockG), 0, st, w.recs, L.n_gauss, chol,
+                       color, opacity, w.moments, w.counts, w.offsets, w.inv, w.partials, w.hdr,
+                       L.cap, (L.flags & GS_FLAG_ATOMIC_GRADS) ? 1 : 0, grad_mean, grad_chol,
+                       grad_color, grad_opacity, w.tile_loss, L.n_tiles,
+                       loss ? 1.0 / (double)numel : 0.0, loss);
     return hipGetLastError();
 }
 
