@@ -113,8 +113,6 @@ gs_status make_layout(const gs_config* cfg, const gs_image* images, int32_t n_im
     l.off_keys1 = off; off = align_up(off + sizeof(uint32_t) * (size_t)cap);
     l.off_vals1 = off; off = align_up(off + sizeof(uint32_t) * (size_t)cap);
     l.off_hist = off; off = align_up(off + sizeof(int32_t) * ((size_t)kRadix * l.nblk_sort + kRadix));
-    l.off_pairs = off; off = align_up(off + sizeof(PairRec) * (size_t)cap);
-    l.off_inv = off; off = align_up(off + sizeof(uint32_t) * (size_t)cap);
     l.off_partials = off; off = align_up(off + sizeof(float) * 8 * (size_t)cap);
     l.total = off;
     l.host_imgs = table->data();

@@ -454,53 +454,16 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
 
 __global__ void k_mark_ordered(WsHeader* __restrict__ hdr) { hdr->ordered = 1; }
 
-// One thread per sorted pair: tile range boundaries, and the pair's render
-// record (the Gaussian's record located in its tile).
-__global__ __launch_bounds__(kBlockG) void k_pairs(const uint32_t* __restrict__ keys,
-                                                   const uint32_t* __restrict__ vals,
-                                                   const WsHeader* __restrict__ hdr,
-                                                   int64_t cap, int tile,
-                                                   const ImgDev* __restrict__ imgs,
-                                                   const GRec* __restrict__ recs,
-                                                   const int32_t* __restrict__ offsets,
-                                                   int2* __restrict__ ranges,
-                                                   PairRec* __restrict__ pairs,
-                                                   uint32_t* __restrict__ inv) {
+// One thread per sorted pair: the tile range boundaries.
+__global__ __launch_bounds__(kBlockG) void k_ranges(const uint32_t* __restrict__ keys,
+                                                    const WsHeader* __restrict__ hdr,
+                                                    int64_t cap, int2* __restrict__ ranges) {
     const int64_t p = (int64_t)blockIdx.x * kBlockG + threadIdx.x;
     const int64_t P = pairs_in_use(hdr, cap);
     if (p >= P) return;
     const uint32_t k = keys[p];
     if (p == 0 || keys[p - 1] != k) ranges[k].x = (int)p;
     if (p == P - 1 || keys[p + 1] != k) ranges[k].y = (int)(p + 1);
-    const uint32_t gid = vals[p];
-    const GRec r = recs[gid];
-    const ImgDev im = imgs[r.img];
-    const int64_t lt = (int64_t)k - im.tile_base;
-    const int px0 = (int)(lt % im.tiles_x) * tile, py0 = (int)(lt / im.tiles_x) * tile;
-    const int lx0 = max(r.x0 - px0, 0), lx1 = min(r.x1 - px0, tile - 1);
-    const int ly0 = max(r.y0 - py0, 0), ly1 = min(r.y1 - py0, tile - 1);
-    PairRec q;
-    q.kxr = (float)(px0 - r.kx);
-    q.kyr = (float)(py0 - r.ky);
-    q.fx = r.fx;
-    q.fy = r.fy;
-    q.a = r.a;
-    q.e = r.e;
-    q.g = r.g;
-    q.A[0] = r.A[0];
-    q.A[1] = r.A[1];
-    q.A[2] = r.A[2];
-    q.gid = gid;
-    q.box = (uint32_t)lx0 | ((uint32_t)lx1 << 8) | ((uint32_t)ly0 << 16) | ((uint32_t)ly1 << 24);
-    q.dead = (uint32_t)r.pad;
-    q.pad[0] = q.pad[1] = q.pad[2] = 0;
-    pairs[p] = q;
-    // this pair's emission index: the Gaussian's offset plus the tile's
-    // row-major rank inside the Gaussian's tile range
-    const int tx = (int)(lt % im.tiles_x), ty = (int)(lt / im.tiles_x);
-    const int tx0 = r.x0 / tile, tx1 = r.x1 / tile, ty0 = r.y0 / tile;
-    const int64_t e = (int64_t)offsets[gid] + (int64_t)(ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0);
-    if (e < cap) inv[e] = (uint32_t)p;
 }
 
 inline int blocks_for(int64_t n, int per) { return (int)((n + per - 1) / per); }
@@ -583,10 +546,8 @@ hipError_t launch_order(const Layout& L, const Ws& w, hipStream_t st) {
 }
 
 hipError_t launch_ranges(const Layout& L, const Ws& w, hipStream_t st) {
-    const int src = L.n_passes & 1;
-    hipLaunchKernelGGL(k_pairs, dim3(blocks_for(L.cap, kBlockG)), dim3(kBlockG), 0, st,
-                       w.keys[src], w.vals[src], w.hdr, L.cap, L.tile, w.imgs, w.recs,
-                       w.offsets, w.ranges, w.pairs, w.inv);
+    hipLaunchKernelGGL(k_ranges, dim3(blocks_for(L.cap, kBlockG)), dim3(kBlockG), 0, st,
+                       w.keys[L.n_passes & 1], w.hdr, L.cap, w.ranges);
     return hipGetLastError();
 }
 

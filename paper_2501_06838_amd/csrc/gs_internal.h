@@ -57,22 +57,6 @@ struct GRec {
 };
 static_assert(sizeof(GRec) == 64, "GRec layout");
 
-// Per (tile, Gaussian) render record, written in sorted order (tile after
-// tile, ascending Gaussian within a tile) by the range kernel (64 B), so that
-// the tile kernels stage their lists with one coalesced load per entry.
-//   For tile-local pixel (dx, dy): X = (kxr + dx) - fx, Y = (kyr + dy) - fy
-//   (kxr, kyr exact integers), z1 = a X, z2 = e Y - g X.
-struct PairRec {
-    float kxr, kyr;    // tile origin minus the integer part of the HR centre
-    float fx, fy;      // fractional part of the HR centre
-    float a, e, g;
-    float A[3];
-    uint32_t gid;      // Gaussian index
-    uint32_t box;      // box inside the tile: lx0 | lx1 << 8 | ly0 << 16 | ly1 << 24
-    uint32_t dead;     // 1: listed, but contributes and receives nothing
-    uint32_t pad[3];
-};
-static_assert(sizeof(PairRec) == 64, "PairRec layout");
 
 // Per-block partial counts written by the support kernel.
 struct BlockSums {
@@ -108,8 +92,8 @@ struct Layout {
     size_t off_order = 0, off_order_hist = 0, off_sched = 0;
     size_t off_header = 0, off_imgs = 0, off_recs = 0, off_counts = 0, off_offsets = 0,
            off_blocksums = 0, off_keys0 = 0, off_vals0 = 0, off_keys1 = 0, off_vals1 = 0,
-           off_hist = 0, off_ranges = 0, off_moments = 0, off_tile_loss = 0, off_pairs = 0,
-           off_inv = 0, off_partials = 0, total = 0;
+           off_hist = 0, off_ranges = 0, off_moments = 0, off_tile_loss = 0,
+           off_partials = 0, total = 0;
     // buffer holding the sorted result after n_passes ping-pong passes
     const ImgDev* host_imgs = nullptr;  // host copy of the table (valid during a call)
     size_t sorted_keys() const { return (n_passes & 1) ? off_keys1 : off_keys0; }
@@ -130,9 +114,7 @@ struct Ws {
     int2* ranges;
     float* moments;
     double* tile_loss;
-    PairRec* pairs;
-    uint32_t* inv;       // emission index -> sorted position
-    float4* partials;    // per sorted pair: 8 backward sums (2 x float4)
+    float4* partials;    // per emitted pair (emission order): 8 backward sums (2 x float4)
     uint32_t* order;     // tiles, longest list first (persistent kernels)
     int32_t* order_hist; // histograms of the tile-order sort
     uint32_t* sched;     // persistent-kernel counters (kSchedWords, zeroed by the binning)
@@ -155,8 +137,6 @@ inline Ws bind(const Layout& L, void* base) {
     w.ranges = reinterpret_cast<int2*>(b + L.off_ranges);
     w.moments = reinterpret_cast<float*>(b + L.off_moments);
     w.tile_loss = reinterpret_cast<double*>(b + L.off_tile_loss);
-    w.pairs = reinterpret_cast<PairRec*>(b + L.off_pairs);
-    w.inv = reinterpret_cast<uint32_t*>(b + L.off_inv);
     w.partials = reinterpret_cast<float4*>(b + L.off_partials);
     w.order = reinterpret_cast<uint32_t*>(b + L.off_order);
     w.order_hist = reinterpret_cast<int32_t*>(b + L.off_order_hist);

@@ -134,27 +134,48 @@ struct BwdLds {
 struct StagedMine {
     uint32_t gid;
     uint32_t touch;  // bit j: the Gaussian's box meets block j
+    int64_t e;       // emission index of this (tile, Gaussian) pair
 };
 
-// Stages entries [base, base + nb) of the tile's sorted pair records and
-// builds the per-block record lists.  Ends with a barrier.
+// Tile geometry and list.
+struct TileInfo {
+    ImgDev im;
+    int tx, ty;      // tile coordinates within the image
+    int px0, py0;    // HR origin
+    int2 rg;
+};
+
+// Stages entries [base, base + nb) of the tile's sorted list (Gaussian ids)
+// from the Gaussians' render records and builds the per-block record lists.
+// Ends with a barrier.
 template <int T, int B>
 __device__ __forceinline__ StagedMine stage_round(StageLds<T, B>& st,
-                                                  const PairRec* __restrict__ pairs, int base,
-                                                  int nb) {
+                                                  const uint32_t* __restrict__ svals,
+                                                  const GRec* __restrict__ recs,
+                                                  const int32_t* __restrict__ offsets,
+                                                  const TileInfo& ti, int base, int nb) {
     using S = TileShape<T>;
     constexpr int NB = S::kBlocks;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    StagedMine mine{0u, 0u};
-    PairRec r;
+    StagedMine mine{0u, 0u, 0};
+    GRec r;
+    float kxr = 0.f, kyr = 0.f;
     uint64_t my_mask[NB];
 #pragma unroll
     for (int j = 0; j < NB; ++j) my_mask[j] = 0;
     if (t < nb) {
-        r = pairs[base + t];
-        mine.gid = r.gid;
-        const int lx0 = r.box & 255, lx1 = (r.box >> 8) & 255;
-        const int ly0 = (r.box >> 16) & 255, ly1 = r.box >> 24;
+        mine.gid = svals[base + t];
+        r = recs[mine.gid];
+        // this pair's emission index: the Gaussian's offset plus the tile's
+        // row-major rank in the Gaussian's tile range
+        const int tx0 = r.x0 / T, tx1 = r.x1 / T, ty0 = r.y0 / T;
+        mine.e = (int64_t)offsets[mine.gid] + (int64_t)(ti.ty - ty0) * (tx1 - tx0 + 1) +
+                 (ti.tx - tx0);
+        // tile origin minus the integer part of the HR centre (exact)
+        kxr = (float)(ti.px0 - r.kx);
+        kyr = (float)(ti.py0 - r.ky);
+        const int lx0 = max(r.x0 - ti.px0, 0), lx1 = min(r.x1 - ti.px0, T - 1);
+        const int ly0 = max(r.y0 - ti.py0, 0), ly1 = min(r.y1 - ti.py0, T - 1);
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
             const int bx = (j % S::kBlocksX) * 8, by = (j / S::kBlocksX) * 8;
@@ -181,8 +202,8 @@ __device__ __forceinline__ StagedMine stage_round(StageLds<T, B>& st,
             const int bx = (j % S::kBlocksX) * 8, by = (j / S::kBlocksX) * 8;
             // block origin relative to the HR centre: exact integer part, one
             // rounding for the fraction
-            const float Xb = (r.kxr + (float)bx) - r.fx;
-            const float Yb = (r.kyr + (float)by) - r.fy;
+            const float Xb = (kxr + (float)bx) - r.fx;
+            const float Yb = (kyr + (float)by) - r.fy;
             st.l0[j][pos] = make_float4(r.a * Xb, r.e * Yb - r.g * Xb, r.a, r.e);
             st.l1[j][pos] = make_float4(r.g, r.A[0], r.A[1], r.A[2]);
             st.l2[j][pos] = make_uint4((uint32_t)my_mask[j], (uint32_t)(my_mask[j] >> 32),
@@ -335,22 +356,16 @@ __device__ __forceinline__ void bwd_round_store(BwdLds<T, B>& sm, StagedMine min
             for (int m = 0; m < 8; ++m)
                 if (vals[m] != 0.f) atomicAdd(dst + m, vals[m]);
         } else {
-            // the (tile, Gaussian) sums, coalesced in sorted pair order; the
-            // gradient kernel adds each Gaussian's pairs in a fixed order
-            float4* dst = partials + 2 * (int64_t)(base + t);
+            // the (tile, Gaussian) sums at the pair's emission index, so each
+            // Gaussian's pairs lie together; the gradient kernel adds them in
+            // that (fixed) order
+            float4* dst = partials + 2 * mine.e;
             dst[0] = u;
             dst[1] = v;
         }
     }
     __syncthreads();
 }
-
-// Tile geometry and list.
-struct TileInfo {
-    ImgDev im;
-    int px0, py0;
-    int2 rg;
-};
 
 template <int T, typename Table>
 __device__ __forceinline__ TileInfo tile_info(const Table& imgs, int n_img,
@@ -359,15 +374,18 @@ __device__ __forceinline__ TileInfo tile_info(const Table& imgs, int n_img,
     const int k_img = tile_image(imgs, n_img, tile);
     ti.im = imgs[k_img];
     const int64_t lt = tile - ti.im.tile_base;
-    ti.px0 = (int)(lt % ti.im.tiles_x) * T;
-    ti.py0 = (int)(lt / ti.im.tiles_x) * T;
+    ti.tx = (int)(lt % ti.im.tiles_x);
+    ti.ty = (int)(lt / ti.im.tiles_x);
+    ti.px0 = ti.tx * T;
+    ti.py0 = ti.ty * T;
     ti.rg = ranges[tile];
     return ti;
 }
 
 template <int T, int B, typename Table>
 __device__ __forceinline__ void fwd_tile(FwdLds<T, B>& sm, const Table& imgs, int n_img,
-                                         const PairRec* __restrict__ pairs,
+                                         const uint32_t* __restrict__ svals, const GRec* __restrict__ recs,
+    const int32_t* __restrict__ offsets,
                                          const int2* __restrict__ ranges,
                                          float* __restrict__ out, int64_t tile) {
     using S = TileShape<T>;
@@ -377,7 +395,7 @@ __device__ __forceinline__ void fwd_tile(FwdLds<T, B>& sm, const Table& imgs, in
 #pragma unroll
     for (int m = 0; m < S::kBlocksPerWave; ++m) acc[m][0] = acc[m][1] = acc[m][2] = 0.f;
     for (int base = ti.rg.x; base < ti.rg.y; base += B) {
-        stage_round<T, B>(sm.st, pairs, base, min(B, ti.rg.y - base));
+        stage_round<T, B>(sm.st, svals, recs, offsets, ti, base, min(B, ti.rg.y - base));
         fwd_round<T, B>(sm.st, acc);
         __syncthreads();
     }
@@ -417,7 +435,8 @@ __device__ __forceinline__ void tile_loss_sum(BwdLds<T, B>& sm, double lsum,
 // and the tile's share of sum |out - target| goes to tile_loss[tile].
 template <int T, int B, bool kL1, typename Table>
 __device__ __forceinline__ void bwd_tile(
-    BwdLds<T, B>& sm, const Table& imgs, int n_img, const PairRec* __restrict__ pairs,
+    BwdLds<T, B>& sm, const Table& imgs, int n_img, const uint32_t* __restrict__ svals, const GRec* __restrict__ recs,
+    const int32_t* __restrict__ offsets,
     const int2* __restrict__ ranges, const float* __restrict__ grad_out,
     const float* __restrict__ target, float inv_numel, double* __restrict__ tile_loss,
     float* __restrict__ moments, float4* __restrict__ partials, int atomic_grads,
@@ -456,7 +475,7 @@ __device__ __forceinline__ void bwd_tile(
 
     for (int base = ti.rg.x; base < ti.rg.y; base += B) {
         const int nb = min(B, ti.rg.y - base);
-        const StagedMine mine = stage_round<T, B>(sm.st, pairs, base, nb);
+        const StagedMine mine = stage_round<T, B>(sm.st, svals, recs, offsets, ti, base, nb);
         bwd_round<T, B>(sm);
         bwd_round_store<T, B>(sm, mine, base, nb, moments, partials, atomic_grads);
     }
@@ -469,7 +488,8 @@ __device__ __forceinline__ void bwd_tile(
 // tile's list fits one round.
 template <int T, int B, typename Table>
 __device__ __forceinline__ void fused_tile(
-    BwdLds<T, B>& sm, const Table& imgs, int n_img, const PairRec* __restrict__ pairs,
+    BwdLds<T, B>& sm, const Table& imgs, int n_img, const uint32_t* __restrict__ svals, const GRec* __restrict__ recs,
+    const int32_t* __restrict__ offsets,
     const int2* __restrict__ ranges, float* __restrict__ out, const float* __restrict__ target,
     float inv_numel, double* __restrict__ tile_loss, float* __restrict__ moments,
     float4* __restrict__ partials, int atomic_grads, int64_t tile) {
@@ -480,9 +500,9 @@ __device__ __forceinline__ void fused_tile(
 #pragma unroll
     for (int m = 0; m < S::kBlocksPerWave; ++m) acc[m][0] = acc[m][1] = acc[m][2] = 0.f;
     const bool one_round = ti.rg.y - ti.rg.x <= B;
-    StagedMine mine{0u, 0u};
+    StagedMine mine{0u, 0u, 0};
     for (int base = ti.rg.x; base < ti.rg.y; base += B) {
-        mine = stage_round<T, B>(sm.st, pairs, base, min(B, ti.rg.y - base));
+        mine = stage_round<T, B>(sm.st, svals, recs, offsets, ti, base, min(B, ti.rg.y - base));
         fwd_round<T, B>(sm.st, acc);
         if (!one_round) __syncthreads();
     }
@@ -524,7 +544,7 @@ __device__ __forceinline__ void fused_tile(
     }
     for (int base = ti.rg.x; base < ti.rg.y; base += B) {
         const int nb = min(B, ti.rg.y - base);
-        mine = stage_round<T, B>(sm.st, pairs, base, nb);
+        mine = stage_round<T, B>(sm.st, svals, recs, offsets, ti, base, nb);
         bwd_round<T, B>(sm);
         bwd_round_store<T, B>(sm, mine, base, nb, moments, partials, atomic_grads);
     }
@@ -535,25 +555,27 @@ __device__ __forceinline__ void fused_tile(
 // (without a tile order from the matching binning, items are tiles).
 template <int T, int B, typename Table>
 __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_fwd(
-    Table imgs, int n_img, const PairRec* __restrict__ pairs,
+    Table imgs, int n_img, const uint32_t* __restrict__ svals, const GRec* __restrict__ recs,
+    const int32_t* __restrict__ offsets,
     const int2* __restrict__ ranges, float* __restrict__ out,
     const uint32_t* __restrict__ order, const WsHeader* __restrict__ hdr, int64_t n_tiles,
     int persistent, uint32_t* __restrict__ sched) {
     __shared__ FwdLds<T, B> sm;
     if (!persistent) {
-        fwd_tile<T, B>(sm, imgs, n_img, pairs, ranges, out, (int64_t)blockIdx.x);
+        fwd_tile<T, B>(sm, imgs, n_img, svals, recs, offsets, ranges, out, (int64_t)blockIdx.x);
         return;
     }
     const bool ordered = hdr->ordered != 0;
     run_persistent(sched, n_tiles, [&](int64_t item) {
         const int64_t tile = ordered ? (int64_t)order[item] : item;
-        if (tile < n_tiles) fwd_tile<T, B>(sm, imgs, n_img, pairs, ranges, out, tile);
+        if (tile < n_tiles) fwd_tile<T, B>(sm, imgs, n_img, svals, recs, offsets, ranges, out, tile);
     });
 }
 
 template <int T, int B, bool kL1, typename Table>
 __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_bwd(
-    Table imgs, int n_img, const PairRec* __restrict__ pairs,
+    Table imgs, int n_img, const uint32_t* __restrict__ svals, const GRec* __restrict__ recs,
+    const int32_t* __restrict__ offsets,
     const int2* __restrict__ ranges, const float* __restrict__ grad_out,
     const float* __restrict__ target, float inv_numel, double* __restrict__ tile_loss,
     float* __restrict__ moments, float4* __restrict__ partials, int atomic_grads,
@@ -561,7 +583,7 @@ __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_bwd(
     int persistent, uint32_t* __restrict__ sched) {
     __shared__ BwdLds<T, B> sm;
     if (!persistent) {
-        bwd_tile<T, B, kL1>(sm, imgs, n_img, pairs, ranges, grad_out, target, inv_numel,
+        bwd_tile<T, B, kL1>(sm, imgs, n_img, svals, recs, offsets, ranges, grad_out, target, inv_numel,
                             tile_loss, moments, partials, atomic_grads, (int64_t)blockIdx.x);
         return;
     }
@@ -569,14 +591,15 @@ __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_bwd(
     run_persistent(sched, n_tiles, [&](int64_t item) {
         const int64_t tile = ordered ? (int64_t)order[item] : item;
         if (tile < n_tiles)
-            bwd_tile<T, B, kL1>(sm, imgs, n_img, pairs, ranges, grad_out, target, inv_numel,
+            bwd_tile<T, B, kL1>(sm, imgs, n_img, svals, recs, offsets, ranges, grad_out, target, inv_numel,
                                 tile_loss, moments, partials, atomic_grads, tile);
     });
 }
 
 template <int T, int B, typename Table>
 __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_fused(
-    Table imgs, int n_img, const PairRec* __restrict__ pairs,
+    Table imgs, int n_img, const uint32_t* __restrict__ svals, const GRec* __restrict__ recs,
+    const int32_t* __restrict__ offsets,
     const int2* __restrict__ ranges, float* __restrict__ out,
     const float* __restrict__ target, float inv_numel, double* __restrict__ tile_loss,
     float* __restrict__ moments, float4* __restrict__ partials, int atomic_grads,
@@ -584,7 +607,7 @@ __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_fused(
     int persistent, uint32_t* __restrict__ sched) {
     __shared__ BwdLds<T, B> sm;
     if (!persistent) {
-        fused_tile<T, B>(sm, imgs, n_img, pairs, ranges, out, target, inv_numel, tile_loss,
+        fused_tile<T, B>(sm, imgs, n_img, svals, recs, offsets, ranges, out, target, inv_numel, tile_loss,
                          moments, partials, atomic_grads, (int64_t)blockIdx.x);
         return;
     }
@@ -592,7 +615,7 @@ __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_fused(
     run_persistent(sched, n_tiles, [&](int64_t item) {
         const int64_t tile = ordered ? (int64_t)order[item] : item;
         if (tile < n_tiles)
-            fused_tile<T, B>(sm, imgs, n_img, pairs, ranges, out, target, inv_numel, tile_loss,
+            fused_tile<T, B>(sm, imgs, n_img, svals, recs, offsets, ranges, out, target, inv_numel, tile_loss,
                              moments, partials, atomic_grads, tile);
     });
 }
@@ -629,8 +652,7 @@ __global__ __launch_bounds__(kBlockG) void k_finalize(
     const GRec* __restrict__ recs, int64_t n_gauss, const float* __restrict__ chol,
     const float* __restrict__ color, const float* __restrict__ opacity,
     float* __restrict__ moments, const int32_t* __restrict__ counts,
-    const int32_t* __restrict__ offsets, const uint32_t* __restrict__ inv,
-    const float4* __restrict__ partials, const WsHeader* __restrict__ hdr, int64_t cap,
+    const int32_t* __restrict__ offsets, const float4* __restrict__ partials, int64_t cap,
     int atomic_grads, float* __restrict__ grad_mean, float* __restrict__ grad_chol,
     float* __restrict__ grad_color, float* __restrict__ grad_opacity,
     const double* __restrict__ tile_loss, int64_t n_tiles, double inv_numel,
@@ -652,14 +674,13 @@ __global__ __launch_bounds__(kBlockG) void k_finalize(
         mp[0] = make_float4(0.f, 0.f, 0.f, 0.f);  // ready for the next backward
         mp[1] = make_float4(0.f, 0.f, 0.f, 0.f);
     } else {
-        // this Gaussian's pairs, in emission (tile row-major) order
+        // this Gaussian's pairs, stored at their emission indices (tile
+        // row-major within the Gaussian), added in that order; the pairs at
+        // or past the capacity were never emitted
         for (int k = 0; k < 8; ++k) m[k] = 0.f;
-        const int64_t P = hdr->n_pairs < cap ? hdr->n_pairs : cap;
         const int64_t e0 = offsets[i], e1 = e0 + counts[i];
         for (int64_t e = e0; e < e1 && e < cap; ++e) {
-            const uint32_t p = inv[e];
-            if (p >= P) continue;
-            const float4 u = partials[2 * (int64_t)p], v = partials[2 * (int64_t)p + 1];
+            const float4 u = partials[2 * e], v = partials[2 * e + 1];
             m[0] += u.x; m[1] += u.y; m[2] += u.z; m[3] += u.w;
             m[4] += v.x; m[5] += v.y; m[6] += v.z; m[7] += v.w;
         }
@@ -764,7 +785,7 @@ static hipError_t launch_fwd_tb(const Layout& L, const Ws& w, const Table& tab, 
                                    TileShape<T>::kThreads, &grid);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(TileShape<T>::kThreads), 0, st, tab, L.n_img,
-                       w.pairs, w.ranges, out, w.order, w.hdr, L.n_tiles,
+                       w.vals[L.n_passes & 1], w.recs, w.offsets, w.ranges, out, w.order, w.hdr, L.n_tiles,
                        (L.flags & GS_FLAG_PERSISTENT) ? 1 : 0, w.sched);
     return hipGetLastError();
 }
@@ -813,7 +834,7 @@ static hipError_t launch_bwd_tt(const Layout& L, const Ws& w, const Table& tab,
                                    TileShape<T>::kThreads, &grid);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(TileShape<T>::kThreads), 0, st, tab, L.n_img,
-                       w.pairs, w.ranges, grad_out, target, inv_numel, w.tile_loss, w.moments,
+                       w.vals[L.n_passes & 1], w.recs, w.offsets, w.ranges, grad_out, target, inv_numel, w.tile_loss, w.moments,
                        w.partials, (L.flags & GS_FLAG_ATOMIC_GRADS) ? 1 : 0, w.order, w.hdr,
                        L.n_tiles, (L.flags & GS_FLAG_PERSISTENT) ? 1 : 0,
                        w.sched + kSchedWords / 2);
@@ -878,7 +899,7 @@ static hipError_t launch_fused_tt(const Layout& L, const Ws& w, const Table& tab
                                    TileShape<T>::kThreads, &grid);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(TileShape<T>::kThreads), 0, st, tab, L.n_img,
-                       w.pairs, w.ranges, out, target, inv_numel, w.tile_loss, w.moments,
+                       w.vals[L.n_passes & 1], w.recs, w.offsets, w.ranges, out, target, inv_numel, w.tile_loss, w.moments,
                        w.partials, (L.flags & GS_FLAG_ATOMIC_GRADS) ? 1 : 0, w.order, w.hdr,
                        L.n_tiles, (L.flags & GS_FLAG_PERSISTENT) ? 1 : 0,
                        w.sched + kSchedWords / 2);
@@ -928,8 +949,7 @@ hipError_t launch_finalize(const Layout& L, const Ws& w, const float* chol,
     const int nb = (int)blocks_for(L.n_gauss, kBlockG) + (loss ? 1 : 0);
     if (nb == 0) return hipSuccess;
     hipLaunchKernelGGL(k_finalize, dim3(nb), dim3(kBlockG), 0, st, w.recs, L.n_gauss, chol,
-                       color, opacity, w.moments, w.counts, w.offsets, w.inv, w.partials, w.hdr,
-                       L.cap, (L.flags & GS_FLAG_ATOMIC_GRADS) ? 1 : 0, grad_mean, grad_chol,
+                       color, opacity, w.moments, w.counts, w.offsets, w.partials, L.cap, (L.flags & GS_FLAG_ATOMIC_GRADS) ? 1 : 0, grad_mean, grad_chol,
                        grad_color, grad_opacity, w.tile_loss, L.n_tiles,
                        loss ? 1.0 / (double)numel : 0.0, loss);
     return hipGetLastError();

@@ -356,36 +356,31 @@ __global__ __launch_bounds__(256) void k_mlp_features(Table imgs, int n_img, int
         X[i * kIn + j] = standardise ? (f[j] - norm.mu[j]) / norm.sd[j] : f[j];
 }
 
-// Labels from the exact rasterizer's tile pairs (workspace of a forward):
-// per pair, walk the Gaussian's box inside the tile and keep the largest
-// z1^2 + z2^2 among pixels with max_c(A_c) * w >= tau (A_c = alpha c_c K,
-// w = exp(-(z1^2 + z2^2) / 2)); the per-Gaussian maximum is taken with an
-// integer atomicMax on the (non-negative) FP32 bits.
-template <int T>
-__global__ __launch_bounds__(256) void k_radius_stats(const PairRec* __restrict__ pairs,
-                                                      const WsHeader* __restrict__ hdr,
-                                                      int64_t cap, float tau,
+// Labels from the exact rasterizer's render records (workspace of a forward
+// with the exact 3-sigma boxes): per Gaussian, walk its box and keep the
+// largest z1^2 + z2^2 among pixels with max_c(A_c) * w >= tau (A_c =
+// alpha c_c K, w = exp(-(z1^2 + z2^2) / 2)); FP32 bits in best.
+__global__ __launch_bounds__(256) void k_radius_stats(const GRec* __restrict__ recs,
+                                                      int64_t n, float tau,
                                                       uint32_t* __restrict__ best) {
-    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t P = hdr->n_pairs < cap ? hdr->n_pairs : cap;
-    if (p >= P) return;
-    const PairRec r = pairs[p];
-    if (r.dead) return;
-    const int lx0 = r.box & 255, lx1 = (r.box >> 8) & 255;
-    const int ly0 = (r.box >> 16) & 255, ly1 = r.box >> 24;
-    const float amax = fmaxf(r.A[0], fmaxf(r.A[1], r.A[2]));
-    const float inv_kc2 = (float)(1.0 / (kZScale * kZScale));
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const GRec r = recs[i];
     float m = 0.f;
-    for (int y = ly0; y <= ly1; ++y) {
-        const float Y = (r.kyr + (float)y) - r.fy;
-        for (int x = lx0; x <= lx1; ++x) {
-            const float X = (r.kxr + (float)x) - r.fx;
-            const float z1 = r.a * X, z2 = r.e * Y - r.g * X;
-            const float q = z1 * z1 + z2 * z2;
-            if (amax * __builtin_amdgcn_exp2f(-q) >= tau) m = fmaxf(m, q * inv_kc2);
+    if (r.x0 <= r.x1 && r.y0 <= r.y1 && r.pad == 0) {
+        const float amax = fmaxf(r.A[0], fmaxf(r.A[1], r.A[2]));
+        const float inv_kc2 = (float)(1.0 / (kZScale * kZScale));
+        for (int y = r.y0; y <= r.y1; ++y) {
+            const float Y = (float)(y - r.ky) - r.fy;
+            for (int x = r.x0; x <= r.x1; ++x) {
+                const float X = (float)(x - r.kx) - r.fx;
+                const float z1 = r.a * X, z2 = r.e * Y - r.g * X;
+                const float q = z1 * z1 + z2 * z2;
+                if (amax * __builtin_amdgcn_exp2f(-q) >= tau) m = fmaxf(m, q * inv_kc2);
+            }
         }
     }
-    if (m > 0.f) atomicMax(best + r.gid, __float_as_uint(m));
+    best[i] = __float_as_uint(m);
 }
 
 __global__ __launch_bounds__(256) void k_sqrt_labels(const uint32_t* __restrict__ best,
@@ -478,16 +473,11 @@ hipError_t launch_adam(float* p, float* m, float* v, const float* grad, int t, f
 hipError_t launch_radius_stats(const Layout& L, const Ws& w, float tau, float* R,
                                hipStream_t st) {
     uint32_t* best = reinterpret_cast<uint32_t*>(R);  // FP32 bits, then sqrt in place
-    if (L.n_gauss > 0) {
-        const int nb = blocks_for(L.n_gauss, 256);
-        hipLaunchKernelGGL(k_fill_u32, dim3(nb < 2048 ? nb : 2048), dim3(256), 0, st, best,
-                           L.n_gauss);
-    }
-    hipLaunchKernelGGL(k_radius_stats<16>, dim3(blocks_for(L.cap, 256)), dim3(256), 0, st,
-                       w.pairs, w.hdr, L.cap, tau, best);
-    if (L.n_gauss > 0)
-        hipLaunchKernelGGL(k_sqrt_labels, dim3(blocks_for(L.n_gauss, 256)), dim3(256), 0, st,
-                           best, L.n_gauss, R);
+    if (L.n_gauss == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_radius_stats, dim3(blocks_for(L.n_gauss, 256)), dim3(256), 0, st,
+                       w.recs, L.n_gauss, tau, best);
+    hipLaunchKernelGGL(k_sqrt_labels, dim3(blocks_for(L.n_gauss, 256)), dim3(256), 0, st,
+                       best, L.n_gauss, R);
     return hipGetLastError();
 }
 
