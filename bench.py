@@ -174,7 +174,7 @@ def pruned_comparison(args, G, synth, torch, np):
     train the radius network on labels the exact rasterizer measures on 10k
     seeded images, then time both steps (each captured as one graph) and
     report the PSNR of the pruned render against the exact one."""
-    from paper_2501_06838_amd.surrogate import features, psnr
+    from paper_2501_06838_amd.surrogate import psnr
     from paper_2501_06838_amd.surrogate_train import train_radius_mlp
     dev = torch.device("cuda:0")
     tau = 4e-3
@@ -188,7 +188,6 @@ def pruned_comparison(args, G, synth, torch, np):
     imgs = [(im.lr_h, im.lr_w, im.scale, im.g_begin, im.g_count) for im in wl.images]
     target = None
     results = {}
-    feats = torch.empty(wl.n_gauss, 8, device=dev)
     radius = torch.empty(wl.n_gauss, device=dev)
     # closed-form control radius sqrt(2 ln(alpha max(c) K / tau)), K = 1/(2 pi l11 l22)
     K = 1.0 / (2 * np.pi * np.float64(wl.chol[:, 0]) * np.float64(wl.chol[:, 2]))
@@ -200,8 +199,7 @@ def pruned_comparison(args, G, synth, torch, np):
             target = plan.pack([t(x) for x in wl.target])
         rad = None
         if mode == "pruned":
-            features(plan, chol, color, opacity, net.norm, out=feats)
-            net.radius(feats, out=radius)
+            net.radius_for(plan, chol, color, opacity, out=radius)
             rad = radius
         elif mode == "closed_form":
             rad = rcf
@@ -211,9 +209,8 @@ def pruned_comparison(args, G, synth, torch, np):
                  torch.empty(wl.n_gauss, 3, device=dev), torch.empty(wl.n_gauss, device=dev))
 
         def step():
-            if mode == "pruned":  # the radius is predicted inside the step
-                features(plan, chol, color, opacity, net.norm, out=feats)
-                net.radius(feats, out=radius)
+            if mode == "pruned":  # the radius is predicted inside the step (one kernel)
+                net.radius_for(plan, chol, color, opacity, out=radius)
             plan.step_l1(mean, chol, color, opacity, ws, out, target, grads, radius=rad)
 
         step()

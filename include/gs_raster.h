@@ -317,6 +317,14 @@ gs_status gs_mlp_features(const gs_image* images, int32_t n_img, const float* ch
 gs_status gs_mlp_forward(const float* params, const float* feats, int64_t n,
                          const gs_mlp_norm* norm, float* out, void* stream);
 
+/* gs_mlp_features (standardised with norm) followed by gs_mlp_forward with
+ * norm, in one kernel that forms the features inside the network's first
+ * layer: radius (device [n_gauss]) receives the support half-width of every
+ * Gaussian of the batch, bitwise as the two calls.  norm must not be NULL. */
+gs_status gs_mlp_radius(const gs_image* images, int32_t n_img, const float* params,
+                        const float* chol, const float* color, const float* opacity,
+                        int64_t n_gauss, const gs_mlp_norm* norm, float* radius, void* stream);
+
 /* Device workspace bytes of gs_mlp_grad for n rows. */
 gs_status gs_mlp_workspace_size(int64_t n, size_t* bytes);
 

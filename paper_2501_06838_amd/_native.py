@@ -30,7 +30,7 @@ EXPORTED = (
     "gs_l1_loss_value", "gs_raster_backward_l1", "gs_graph_create", "gs_graph_launch",
     "gs_graph_destroy", "gs_mlp_features", "gs_mlp_forward", "gs_mlp_workspace_size",
     "gs_mlp_grad", "gs_mlp_adam", "gs_radius_stats", "gs_sq_error", "gs_tile_order",
-    "gs_raster_render_fused_l1", "gs_raster_step_l1",
+    "gs_raster_render_fused_l1", "gs_raster_step_l1", "gs_mlp_radius",
 )
 
 

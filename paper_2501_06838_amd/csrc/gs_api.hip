@@ -436,6 +436,39 @@ gs_status gs_mlp_features(const gs_image* images, int32_t n_img, const float* ch
     return GS_OK;
 }
 
+gs_status gs_mlp_radius(const gs_image* images, int32_t n_img, const float* params,
+                        const float* chol, const float* color, const float* opacity,
+                        int64_t n_gauss, const gs_mlp_norm* norm, float* radius, void* stream) {
+    if (!norm) return GS_E_INVALID;
+    if (n_gauss > 0 && (!params || !chol || !color || !opacity || !radius)) return GS_E_INVALID;
+    const gs_mlp_norm nm = *norm;
+    for (int k = 0; k < 8; ++k)
+        if (!(nm.sd[k] > 0.f) || !std::isfinite(nm.mu[k])) return GS_E_INVALID;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // one launch per chunk of images (the chunk's table travels by value)
+    for (int first = 0; first < n_img; first += kSetupChunk) {
+        const int count = std::min(kSetupChunk, n_img - first);
+        std::vector<gs_image> sub(images + first, images + first + count);
+        const int64_t g0 = sub.front().g_begin;
+        const int64_t g1 = sub.back().g_begin + sub.back().g_count;
+        int64_t off = 0;
+        for (auto& im : sub) {
+            im.g_begin -= g0;
+            int32_t oh, ow;
+            GS_TRY(size_of(im.lr_h, im.lr_w, im.scale, &oh, &ow));
+            im.out_offset = off;  // irrelevant here; disjoint blocks for validation
+            off += 3LL * oh * ow;
+        }
+        Layout L;
+        std::vector<ImgDev> table;
+        GS_TRY(make_layout(nullptr, sub.data(), count, g1 - g0, &L, &table));
+        Ws w{};
+        GS_TRY(dev(launch_mlp_radius(L, w, params, chol + 3 * g0, color + 3 * g0, opacity + g0,
+                                     nm, radius + g0, st)));
+    }
+    return GS_OK;
+}
+
 gs_status gs_mlp_forward(const float* params, const float* feats, int64_t n,
                          const gs_mlp_norm* norm, float* out, void* stream) {
     if (n < 0) return GS_E_INVALID;

@@ -201,6 +201,9 @@ hipError_t launch_mlp_features(const Layout& L, const Ws& w, const float* chol,
                                const float* color, const float* opacity,
                                const gs_mlp_norm& norm, int standardise, float* X,
                                hipStream_t st);
+hipError_t launch_mlp_radius(const Layout& L, const Ws& w, const float* params,
+                             const float* chol, const float* color, const float* opacity,
+                             const gs_mlp_norm& norm, float* out, hipStream_t st);
 hipError_t launch_mlp_forward(const float* params, const float* X, int64_t n,
                               const gs_mlp_norm& norm, int radius_mode, float* out,
                               hipStream_t st);

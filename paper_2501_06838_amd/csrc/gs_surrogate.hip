@@ -333,6 +333,34 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, float* __re
     p[i] -= lr * mh / (sqrtf(vh) + eps);
 }
 
+// The image a Gaussian belongs to (images hold ascending Gaussian ranges).
+template <typename Table>
+__device__ __forceinline__ int image_of(const Table& imgs, int n_img, int64_t i) {
+    int lo = 0, hi = n_img - 1, k = 0;
+    while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        if (imgs[mid].g_begin <= i) { k = mid; lo = mid + 1; } else { hi = mid - 1; }
+    }
+    return k;
+}
+
+// Raw features of a Gaussian at scale s: [log s, log sigma_x, log sigma_y,
+// rho, alpha, c_r, c_g, c_b] with sigma_x = l11, sigma_y = sqrt(l21^2 + l22^2),
+// rho = l21 / sigma_y (fixed operation order: the same bits wherever used).
+// Features 0..3 from (s, l11, l21, l22), features 4..7 from (alpha, c).
+__device__ __forceinline__ void shape_features(double s, float l11, float l21, float l22,
+                                               float* f) {
+    const float sy = sqrtf(__builtin_fmaf(l21, l21, l22 * l22));
+    f[0] = logf((float)s);
+    f[1] = logf(l11);
+    f[2] = logf(sy);
+    f[3] = l21 / sy;
+}
+
+__device__ __forceinline__ float standardised(float f, int k, const gs_mlp_norm& norm) {
+    return (f - norm.mu[k]) / norm.sd[k];
+}
+
 // Features of every Gaussian, standardised: (f - mu) / sd.
 template <typename Table>
 __global__ __launch_bounds__(256) void k_mlp_features(Table imgs, int n_img, int64_t n_gauss,
@@ -343,17 +371,104 @@ __global__ __launch_bounds__(256) void k_mlp_features(Table imgs, int n_img, int
                                                       float* __restrict__ X) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n_gauss) return;
-    int lo = 0, hi = n_img - 1, k = 0;
-    while (lo <= hi) {
-        const int mid = (lo + hi) >> 1;
-        if (imgs[mid].g_begin <= i) { k = mid; lo = mid + 1; } else { hi = mid - 1; }
+    const double s = imgs[image_of(imgs, n_img, i)].scale;
+    float f[kIn];
+    shape_features(s, chol[3 * i], chol[3 * i + 1], chol[3 * i + 2], f);
+    f[4] = opacity[i];
+    f[5] = color[3 * i];
+    f[6] = color[3 * i + 1];
+    f[7] = color[3 * i + 2];
+    for (int j = 0; j < kIn; ++j) X[i * kIn + j] = standardise ? standardised(f[j], j, norm) : f[j];
+}
+
+// Features, MLP forward and pruned radius in one kernel: per tile of 16
+// Gaussians, lane (g, c) forms features 4g..4g+3 of Gaussian c (the MFMA B
+// operand) straight from the Gaussian parameters; the range check combines
+// lanes g = 0 and 1.  Same bits as k_mlp_features + k_mlp_forward.
+constexpr int kRadiusThreads = 1024;  // one workgroup per CU shares the staged weights
+
+template <typename Table>
+__global__ __launch_bounds__(kRadiusThreads) void k_mlp_radius(
+    Table imgs, int n_img, int64_t n, const float* __restrict__ chol,
+    const float* __restrict__ color, const float* __restrict__ opacity,
+    const float* __restrict__ params, gs_mlp_norm norm, float* __restrict__ out) {
+    __shared__ MlpLds L;
+    stage_weights(params, L);
+    __syncthreads();
+    const int l = threadIdx.x & 63, g = l >> 4, c = l & 15;
+    bf16x4 w1[4], w2[16], w3[4];
+    for (int p = 0; p < 4; ++p) w1[p] = a_tile_w1(L, p, g, c);
+    for (int q = 0; q < 4; ++q)
+        for (int p = 0; p < 4; ++p) w2[4 * q + p] = a_tile_w2(L, q, p, g, c);
+    for (int q = 0; q < 4; ++q) w3[q] = a_tile_w3(L, q, g, c);
+    float b1[4][4], b2[4][4];
+    for (int p = 0; p < 4; ++p)
+        for (int e = 0; e < 4; ++e) {
+            b1[p][e] = params[kOffB1 + 16 * p + 4 * g + e];
+            b2[p][e] = params[kOffB2 + 16 * p + 4 * g + e];
+        }
+    const float b3 = params[kOffB3];
+    const int64_t wave = ((int64_t)blockIdx.x * kRadiusThreads + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * kRadiusThreads) >> 6;
+    // lanes g = 0 read (l11, l21, l22, scale), lanes g = 1 (alpha, c): the raw
+    // values of the next tile are loaded while the current one is computed
+    auto fetch = [&](int64_t n0, float* v, double* s) {
+        const int64_t col = n0 + c;
+        v[0] = v[1] = v[2] = v[3] = 0.f;
+        *s = 1.0;
+        if (col >= n) return;
+        if (g == 0) {
+            v[0] = chol[3 * col]; v[1] = chol[3 * col + 1]; v[2] = chol[3 * col + 2];
+            *s = imgs[image_of(imgs, n_img, col)].scale;
+        } else if (g == 1) {
+            v[0] = opacity[col]; v[1] = color[3 * col]; v[2] = color[3 * col + 1];
+            v[3] = color[3 * col + 2];
+        }
+    };
+    float nv[4];
+    double ns;
+    fetch(wave * 16, nv, &ns);
+    for (int64_t n0 = wave * 16; n0 < n; n0 += nwaves * 16) {
+        const int64_t col = n0 + c;
+        float rv[4] = {nv[0], nv[1], nv[2], nv[3]};
+        const double rs = ns;
+        fetch(n0 + nwaves * 16, nv, &ns);
+        bf16x4 x;
+        bool inside = true;
+        if (g < 2 && col < n) {
+            float f[4];
+            if (g == 0) shape_features(rs, rv[0], rv[1], rv[2], f);
+            else { f[0] = rv[0]; f[1] = rv[1]; f[2] = rv[2]; f[3] = rv[3]; }
+            for (int e = 0; e < 4; ++e) {
+                const int k = 4 * g + e;
+                const float v = standardised(f[e], k, norm);
+                inside = inside && v >= norm.fmin[k] && v <= norm.fmax[k];
+                x[e] = bf16_bits(v);
+            }
+        } else {
+            for (int e = 0; e < 4; ++e) x[e] = 0;
+        }
+        bf16x4 h1[4], h2[4];
+        for (int p = 0; p < 4; ++p) {
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            acc = mfma(w1[p], x, acc);
+            for (int e = 0; e < 4; ++e) h1[p][e] = bf16_bits(fmaxf(acc[e] + b1[p][e], 0.f));
+        }
+        for (int q = 0; q < 4; ++q) {
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            for (int p = 0; p < 4; ++p) acc = mfma(w2[4 * q + p], h1[p], acc);
+            for (int e = 0; e < 4; ++e) h2[q][e] = bf16_bits(fmaxf(acc[e] + b2[q][e], 0.f));
+        }
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        for (int q = 0; q < 4; ++q) acc = mfma(w3[q], h2[q], acc);
+        const float pred = acc[0] + b3;  // row 0 of the output tile: lanes g == 0
+        const bool in_hi = __shfl_xor((int)inside, 16, 64) != 0;  // features 4..7
+        if (g == 0 && col < n) {
+            float r = pred;
+            r = (inside && in_hi && isfinite(r)) ? fminf(fmaxf(r + norm.margin, 0.f), 3.f) : 3.f;
+            out[col] = r;
+        }
     }
-    const float l11 = chol[3 * i], l21 = chol[3 * i + 1], l22 = chol[3 * i + 2];
-    const float sy = sqrtf(l21 * l21 + l22 * l22);
-    float f[kIn] = {logf((float)imgs[k].scale), logf(l11), logf(sy), l21 / sy, opacity[i],
-                    color[3 * i], color[3 * i + 1], color[3 * i + 2]};
-    for (int j = 0; j < kIn; ++j)
-        X[i * kIn + j] = standardise ? (f[j] - norm.mu[j]) / norm.sd[j] : f[j];
 }
 
 // Labels from the exact rasterizer's render records (workspace of a forward
@@ -436,6 +551,27 @@ hipError_t launch_mlp_features(const Layout& L, const Ws& w, const float* chol,
     } else {
         hipLaunchKernelGGL(k_mlp_features<MemTable>, grid, dim3(256), 0, st, MemTable{w.imgs},
                            L.n_img, L.n_gauss, chol, color, opacity, norm, standardise, X);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_radius(const Layout& L, const Ws& w, const float* params,
+                             const float* chol, const float* color, const float* opacity,
+                             const gs_mlp_norm& norm, float* out, hipStream_t st) {
+    if (L.n_gauss == 0) return hipSuccess;
+    const int64_t tiles = (L.n_gauss + 15) / 16;
+    int nb = (int)((tiles + 63) / 64);  // 16 waves, about four tiles each
+    if (nb > 256) nb = 256;
+    if (nb < 1) nb = 1;
+    if (L.n_img <= kSetupChunk && L.host_imgs) {
+        ArgTable tab;
+        for (int k = 0; k < kSetupChunk; ++k) tab.c.img[k] = k < L.n_img ? L.host_imgs[k] : ImgDev{};
+        hipLaunchKernelGGL(k_mlp_radius<ArgTable>, dim3(nb), dim3(kRadiusThreads), 0, st, tab,
+                           L.n_img, L.n_gauss, chol, color, opacity, params, norm, out);
+    } else {
+        hipLaunchKernelGGL(k_mlp_radius<MemTable>, dim3(nb), dim3(kRadiusThreads), 0, st,
+                           MemTable{w.imgs}, L.n_img, L.n_gauss, chol, color, opacity, params,
+                           norm, out);
     }
     return hipGetLastError();
 }

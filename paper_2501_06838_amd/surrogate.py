@@ -41,6 +41,9 @@ def _bind():
     L.gs_mlp_features.restype = i32
     L.gs_mlp_forward.argtypes = [vp, vp, i64, normp, vp, vp]
     L.gs_mlp_forward.restype = i32
+    L.gs_mlp_radius.argtypes = [ctypes.POINTER(N.gs_image), i32, vp, vp, vp, vp, i64, normp,
+                                vp, vp]
+    L.gs_mlp_radius.restype = i32
     L.gs_mlp_workspace_size.argtypes = [i64, ctypes.POINTER(ctypes.c_size_t)]
     L.gs_mlp_workspace_size.restype = i32
     L.gs_mlp_grad.argtypes = [vp, vp, vp, vp, i64, f32, vp, ctypes.c_size_t, vp, vp, vp]
@@ -138,6 +141,20 @@ class RadiusMLP:
         N.check(L.gs_mlp_forward(_ptr(self.params), _ptr(feats), feats.shape[0],
                                  ctypes.byref(self.norm), _ptr(out), _stream(stream)),
                 "mlp radius")
+        return out
+
+    def radius_for(self, plan: RasterPlan, chol, color, opacity, out=None, stream=None):
+        """Support half-widths of a batch's Gaussians in one kernel (features
+        formed inside the network's first layer; needs self.norm)."""
+        L = _bind()
+        if self.norm is None:
+            raise RuntimeError("calibrate the network first")
+        if out is None:
+            out = torch.empty(plan.n_gauss, dtype=torch.float32, device=chol.device)
+        N.check(L.gs_mlp_radius(plan._arr, len(plan.images), _ptr(self.params), _ptr(chol),
+                                _ptr(color), _ptr(opacity), plan.n_gauss,
+                                ctypes.byref(self.norm), _ptr(out), _stream(stream)),
+                "mlp radius (fused)")
         return out
 
     def _workspace(self, n, device):

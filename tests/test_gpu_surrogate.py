@@ -151,3 +151,28 @@ def test_trained_radius_gain_at_50db():
     ref = O.forward_batch(wl, radius=R.cpu().numpy())
     from tests._gpu import assert_forward_close
     assert_forward_close(plan2.split(pruned)[0].cpu().numpy(), ref[0])
+
+
+def test_fused_radius_matches_features_then_forward():
+    """gs_mlp_radius (features formed inside the first layer) gives bitwise
+    the radii of gs_mlp_features + gs_mlp_forward, also over more than one
+    32-image chunk and with Gaussians outside the training range."""
+    from paper_2501_06838_amd.surrogate import RadiusMLP, features, make_norm
+    from paper_2501_06838_amd.surrogate_train import init_params
+    wl = synth.concat([synth.tiny(H=9, W=7, s=2.0 + 0.3 * k, seed=40 + k, sigma=(0.8, 0.5))
+                       for k in range(37)], "c37")
+    plan = plan_for(wl, 16)
+    m, c, col, op = to_dev(wl)
+    F = S.features(np.array([im.scale for im in wl.images for _ in range(im.g_count)]),
+                   wl.chol, wl.color, wl.opacity)
+    mu, sd = F.mean(0), F.std(0)
+    Z = (F - mu) / sd
+    lo, hi = np.quantile(Z, 0.05, axis=0), np.quantile(Z, 0.95, axis=0)  # some fall outside
+    net = RadiusMLP(init_params(3))
+    net.norm = make_norm(mu, sd, lo, hi, 0.25)
+    say("fused radius")
+    ref = net.radius(features(plan, c, col, op, net.norm))
+    got = net.radius_for(plan, c, col, op)
+    torch.cuda.synchronize()
+    assert torch.equal(got, ref)
+    assert (got == 3.0).float().mean().item() > 0.2 and (got < 3.0).any()
