@@ -54,6 +54,14 @@ struct TileShape {
     static constexpr int kBatch = kThreads;
 };
 
+// Waves per SIMD the backward and fused kernels are compiled for: at 16 x 16
+// with 64 Gaussians per round the LDS fits six workgroups per CU, so the
+// register budget is held to 80 VGPRs (elsewhere the LDS limits occupancy).
+template <int T, int B>
+struct BwdOccupancy {
+    static constexpr int kMinWaves = (T == 16 && B == 64) ? 6 : 1;
+};
+
 // Persistent tile kernels.  The items (the longest-first tile order) are
 // dealt round-robin to K = min(16, grid) partitions, item i to partition
 // i % K, whose workgroups are p, p + K, p + 2K, ...  A workgroup's first item
@@ -573,7 +581,8 @@ __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_fwd(
 }
 
 template <int T, int B, bool kL1, typename Table>
-__global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_bwd(
+__global__ __launch_bounds__(TileShape<T>::kThreads)
+__attribute__((amdgpu_waves_per_eu(BwdOccupancy<T, B>::kMinWaves, 8))) void k_render_bwd(
     Table imgs, int n_img, const uint32_t* __restrict__ svals, const GRec* __restrict__ recs,
     const int32_t* __restrict__ offsets,
     const int2* __restrict__ ranges, const float* __restrict__ grad_out,
@@ -597,7 +606,8 @@ __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_bwd(
 }
 
 template <int T, int B, typename Table>
-__global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_fused(
+__global__ __launch_bounds__(TileShape<T>::kThreads)
+__attribute__((amdgpu_waves_per_eu(BwdOccupancy<T, B>::kMinWaves, 8))) void k_render_fused(
     Table imgs, int n_img, const uint32_t* __restrict__ svals, const GRec* __restrict__ recs,
     const int32_t* __restrict__ offsets,
     const int2* __restrict__ ranges, float* __restrict__ out,
