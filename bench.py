@@ -46,8 +46,8 @@ FLOPEQ_BWD = 48.0
 # reads 131,085 KiB (factor 2.0), WRITE_SIZE 262,144 KiB (factor 1.0).  Valid
 # only while the render sources hash to `sources`; otherwise null.
 TRAFFIC = {"workload": "config1", "launch": {"tile": 16, "lds_batch": 64, "flags": 0},
-           "sources": "acd046206372b221",
-           "fetch_kib": 22634.6, "write_kib": 21821.3, "fetch_factor": 2.0, "write_factor": 1.0}
+           "sources": "3f779e79183f2add",
+           "fetch_kib": 23959.9, "write_kib": 21881.5, "fetch_factor": 2.0, "write_factor": 1.0}
 TRAFFIC_SOURCES = ("paper_2501_06838_amd/csrc/gs_render.hip", "paper_2501_06838_amd/csrc/gs_internal.h")
 
 
@@ -339,33 +339,30 @@ def main():
     if plan.diagnostics(ws)[1]:
         raise SystemExit("pair capacity overflow during replay")
 
-    # per-kernel durations: HIP events on the launch stream around the
-    # single-kernel entry points, same inputs, same count.  The step's tile
-    # kernel is the fused one; the separate forward and backward tile kernels
-    # are timed too, for reference.
-    def events(n):
-        return [[torch.cuda.Event(enable_timing=True) for _ in range(n)] for _ in range(args.steps)]
-    ev = events(2)
-    for k in range(args.steps):
-        plan.bin(mean, chol, color, opacity, ws)
-        ev[k][0].record(stream)
-        plan.render_fused_l1(ws, out, target)
-        ev[k][1].record(stream)
-        plan.gradients(chol, color, opacity, ws, grads)
-    ev2 = events(4)
-    for k in range(args.steps):
-        plan.bin(mean, chol, color, opacity, ws)
-        ev2[k][0].record(stream)
-        plan.render(ws, out)
-        ev2[k][1].record(stream)
-        ev2[k][2].record(stream)
-        plan.render_backward_l1(ws, out, target)
-        ev2[k][3].record(stream)
-        plan.gradients(chol, color, opacity, ws, grads)
+    # per-kernel durations: HIP events on the launch stream around K
+    # back-to-back launches of the single-kernel entry points on the bound
+    # batch (same inputs, same launch config), so the host's launch latency
+    # never leaves the queue empty inside the bracket.  The step's tile kernel
+    # is the fused one; the separate forward and backward tile kernels are
+    # timed too, for reference.
+    def bracket(fn):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(args.steps):
+            fn()
+        b.record(stream)
+        return a, b
+    plan.bin(mean, chol, color, opacity, ws)
+    plan.render_fused_l1(ws, out, target)
+    ev_fused = bracket(lambda: plan.render_fused_l1(ws, out, target))
+    ev_fwd = bracket(lambda: plan.render(ws, out))
+    ev_bwd = bracket(lambda: plan.render_backward_l1(ws, out, target))
     torch.cuda.synchronize()
-    fused_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / args.steps
-    fwd_ms = sum(e[0].elapsed_time(e[1]) for e in ev2) / args.steps
-    bwd_ms = sum(e[2].elapsed_time(e[3]) for e in ev2) / args.steps
+    fused_ms, fwd_ms, bwd_ms = (a.elapsed_time(b) / args.steps for a, b in (ev_fused, ev_fwd, ev_bwd))
+    # leave the buffers as one eager step leaves them
+    step()
+    torch.cuda.synchronize()
     log(f"{ms_step:.4f} ms/step (graph replay); fused tile kernel {fused_ms * 1e3:.1f} us "
         f"(separate: fwd {fwd_ms * 1e3:.1f} us, bwd {bwd_ms * 1e3:.1f} us)")
     graph.close()
