@@ -110,10 +110,10 @@ gs_status gs_output_size(int32_t H, int32_t W, double s, int32_t* out_h, int32_t
 
 /* Bytes of device workspace needed by gs_raster_forward / backward for this
  * batch layout (cfg may be NULL for defaults).  The workspace holds the
- * per-Gaussian render records, the (tile, Gaussian) pair lists before and
- * after sorting, the per-tile ranges and the backward's per-Gaussian
- * accumulators; it is written by the forward and read by the matching
- * backward, so it must persist between the two. */
+ * per-Gaussian render records, the per-tile lists of Gaussian ids and their
+ * ranges, and the backward's per-pair sums; it is written by the forward and
+ * read by the matching backward, so it must persist between the two.
+ * GS_E_UNSUPPORTED if the batch has 2^24 tiles or more. */
 gs_status gs_workspace_size(const gs_config* cfg, const gs_image* images, int32_t n_img,
                             int64_t n_gauss, size_t* bytes);
 
@@ -127,16 +127,18 @@ gs_status gs_workspace_size(const gs_config* cfg, const gs_image* images, int32_
  *   out     device, each image's [3][out_h][out_w] block at its out_offset;
  *           every pixel of every block is written (background 0).
  * Kernels: per-Gaussian support box and tile count, prefix sum, pair
- * emission, device radix sort of (tile, Gaussian) keys, per-tile ranges, and
- * the per-tile render.  Within a tile, Gaussians are summed in ascending
- * index, so the result is bitwise deterministic for a given configuration. */
+ * emission (each pair counted into its tile), per-tile ranges (prefix sum of
+ * the tile counts), the Gaussian ids placed into the tiles' lists and each
+ * list sorted ascending, and the per-tile render.  Within a tile, Gaussians
+ * are summed in ascending index, so the result is bitwise deterministic for a given configuration. */
 gs_status gs_raster_forward(const gs_config* cfg, const gs_image* images, int32_t n_img,
                             const float* mean, const float* chol, const float* color,
                             const float* opacity, const float* radius, int64_t n_gauss,
                             void* workspace, size_t ws_bytes, float* out, void* stream);
 
 /* First stage of gs_raster_forward: support boxes, tile counts, prefix sum,
- * pair emission, radix sort and per-tile ranges, all into the workspace.
+ * pair emission, per-tile ranges and the sorted per-tile lists, all into the
+ * workspace.
  * Arguments as for gs_raster_forward. */
 gs_status gs_raster_bin(const gs_config* cfg, const gs_image* images, int32_t n_img,
                         const float* mean, const float* chol, const float* color,

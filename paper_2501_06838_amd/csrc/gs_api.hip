@@ -14,6 +14,9 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int64_t kMaxPairs = 2147483647LL;
+// one workgroup of up to 256 threads per tile: the dispatch's work-item
+// count must stay below 2^32
+constexpr int64_t kMaxTiles = (int64_t)1 << 24;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -78,18 +81,15 @@ gs_status make_layout(const gs_config* cfg, const gs_image* images, int32_t n_im
     std::sort(blocks.begin(), blocks.end());
     for (size_t k = 1; k < blocks.size(); ++k)
         if (blocks[k].first < blocks[k - 1].second) return GS_E_INVALID;  // outputs overlap
-    if (tiles >= kMaxPairs) return GS_E_UNSUPPORTED;
+    if (tiles >= kMaxTiles) return GS_E_UNSUPPORTED;
     l.n_tiles = tiles;
 
     int64_t cap = (cfg && cfg->pair_capacity) ? cfg->pair_capacity : n_gauss * 16;
     if (cap < 1) cap = 1;
     if (cap > kMaxPairs) return GS_E_UNSUPPORTED;
     l.cap = cap;
-    int bits = 0;
-    while (bits < 32 && ((int64_t)1 << bits) < tiles) ++bits;
-    l.n_passes = (bits + kRadixBits - 1) / kRadixBits;
     l.nblk_g = (int32_t)std::max<int64_t>(1, (n_gauss + kBlockG - 1) / kBlockG);
-    l.nblk_sort = (int32_t)std::max<int64_t>(1, (cap + kSortTile - 1) / kSortTile);
+    l.nblk_scan = (int32_t)std::max<int64_t>(1, (tiles + kScanTile - 1) / kScanTile);
     l.nblk_order = (int32_t)std::max<int64_t>(1, (tiles + kSortTile - 1) / kSortTile);
 
     // Capacity-independent sections first, so a small workspace can run the
@@ -102,17 +102,17 @@ gs_status make_layout(const gs_config* cfg, const gs_image* images, int32_t n_im
     l.off_offsets = off; off = align_up(off + sizeof(int32_t) * (size_t)n_gauss);
     l.off_blocksums = off; off = align_up(off + sizeof(BlockSums) * (size_t)l.nblk_g);
     l.off_ranges = off; off = align_up(off + sizeof(int2) * (size_t)tiles);
+    l.off_tile_cnt = off; off = align_up(off + sizeof(int32_t) * (size_t)tiles);
     l.off_moments = off; off = align_up(off + sizeof(float) * 8 * (size_t)n_gauss);
     l.off_tile_loss = off; off = align_up(off + sizeof(double) * (size_t)tiles);
     l.off_order = off; off = align_up(off + sizeof(uint32_t) * (size_t)tiles);
     l.off_order_hist = off;
     off = align_up(off + sizeof(int32_t) * ((size_t)kRadix * l.nblk_order + kRadix));
     l.off_sched = off; off = align_up(off + sizeof(uint32_t) * kSchedWords);
-    l.off_keys0 = off; off = align_up(off + sizeof(uint32_t) * (size_t)cap);
-    l.off_vals0 = off; off = align_up(off + sizeof(uint32_t) * (size_t)cap);
-    l.off_keys1 = off; off = align_up(off + sizeof(uint32_t) * (size_t)cap);
-    l.off_vals1 = off; off = align_up(off + sizeof(uint32_t) * (size_t)cap);
-    l.off_hist = off; off = align_up(off + sizeof(int32_t) * ((size_t)kRadix * l.nblk_sort + kRadix));
+    l.off_scan_sums = off; off = align_up(off + sizeof(int64_t) * (size_t)l.nblk_scan);
+    l.off_slots = off; off = align_up(off + sizeof(uint32_t) * (size_t)cap);
+    l.off_lists = off; off = align_up(off + sizeof(uint32_t) * (size_t)cap);
+    l.off_spare = off; off = align_up(off + sizeof(uint32_t) * (size_t)cap);
     l.off_partials = off; off = align_up(off + sizeof(float) * 8 * (size_t)cap);
     l.total = off;
     l.host_imgs = table->data();
@@ -128,7 +128,7 @@ int64_t batch_numel(const std::vector<ImgDev>& table) {
 }
 
 // Bytes of the capacity-independent prefix of a layout.
-size_t counting_bytes(const Layout& L) { return L.off_keys0; }
+size_t counting_bytes(const Layout& L) { return L.off_slots; }
 
 gs_status check_gauss_ptrs(int64_t n, const float* a, const float* b, const float* c,
                            const float* d) {
@@ -150,8 +150,7 @@ gs_status run_binning(const Layout& L, const Ws& w, const std::vector<ImgDev>& t
     GS_TRY(dev(launch_support(L, w, table.data(), mean, chol, color, opacity, radius, false,
                               st)));
     GS_TRY(dev(launch_emit(L, w, st)));
-    GS_TRY(dev(launch_sort(L, w, st)));
-    GS_TRY(dev(launch_ranges(L, w, st)));
+    GS_TRY(dev(launch_lists(L, w, st)));
     if (L.flags & GS_FLAG_PERSISTENT) GS_TRY(dev(launch_order(L, w, st)));
     return GS_OK;
 }
@@ -620,7 +619,7 @@ gs_status gs_tile_lists(const gs_config* cfg, const gs_image* images, int32_t n_
                                   hipMemcpyDeviceToHost, st)));
     if (gids_host) {
         if (max_pairs < h.n_pairs) return GS_E_INVALID;
-        GS_TRY(dev(hipMemcpyAsync(gids_host, b + L.sorted_vals(), sizeof(uint32_t) * h.n_pairs,
+        GS_TRY(dev(hipMemcpyAsync(gids_host, b + L.off_lists, sizeof(uint32_t) * h.n_pairs,
                                   hipMemcpyDeviceToHost, st)));
     }
     return dev(hipStreamSynchronize(st));

@@ -2,12 +2,15 @@
 //   setup    - image table into the workspace, counters zeroed
 //   support  - per Gaussian (FP64): support box, tile range, tile count and
 //              the FP32 render record
-//   scan     - exclusive prefix sum of the tile counts (per-block sums in the
-//              support kernel, one workgroup over the block sums, local scans
-//              in the emission kernel)
-//   emit     - (tile id, Gaussian id) pairs, Gaussian-major, ascending id
-//   sort     - stable LSD radix sort of the pairs by tile id (8-bit digits)
-//   ranges   - [begin, end) of every tile in the sorted pairs
+//   scan     - exclusive prefix sum of the per-Gaussian pair counts
+//              (per-block sums in the support kernel, one workgroup over the
+//              block sums, local scans in the emission kernel)
+//   emit     - each (tile, Gaussian) pair counted into its tile with an
+//              atomic, which hands the pair a place in the tile's list
+//   lists    - exclusive scan of the per-tile counts (the tile ranges), every
+//              Gaussian id written to its place, then each tile's list sorted
+//              ascending (the atomics' order is arbitrary; the sorted lists
+//              are unique)
 //
 // The support box follows Algorithm 1's strict window test with the window
 // replaced by R standard deviations per axis, evaluated in HR pixels:
@@ -91,7 +94,7 @@ __device__ bool support_box(double s, int out_w, int out_h, double mx, double my
 
 // One thread per Gaussian: box, record, tile count; per-block sums of the
 // pair counts, in-support areas and invalid flags.  Also clears the per-tile
-// ranges and the backward accumulators (grid-stride / per Gaussian).  With a
+// pair counts and the backward accumulators (grid-stride / per Gaussian).  With a
 // by-value image table (kArgTable, batches of at most kSetupChunk images) the
 // first block also writes the table into the workspace for later kernels.
 template <bool kArgTable>
@@ -100,7 +103,7 @@ __global__ __launch_bounds__(kBlockG) void k_support(
     const float* __restrict__ mean, const float* __restrict__ chol,
     const float* __restrict__ color, const float* __restrict__ opacity,
     const float* __restrict__ radius, GRec* __restrict__ recs, int32_t* __restrict__ counts,
-    BlockSums* __restrict__ blocksums, int2* __restrict__ ranges, int64_t n_tiles,
+    BlockSums* __restrict__ blocksums, int32_t* __restrict__ tile_cnt, int64_t n_tiles,
     float4* __restrict__ moments, uint32_t* __restrict__ sched) {
     __shared__ int64_t tmp[3][kBlockG / 64];
     const int64_t i = (int64_t)blockIdx.x * kBlockG + threadIdx.x;
@@ -110,8 +113,7 @@ __global__ __launch_bounds__(kBlockG) void k_support(
 
     if (kArgTable && blockIdx.x == 0 && threadIdx.x < n_img)
         imgs[threadIdx.x] = arg_imgs.img[threadIdx.x];
-    for (int64_t t = i; t < n_tiles; t += (int64_t)gridDim.x * kBlockG)
-        ranges[t] = make_int2(0, 0);
+    for (int64_t t = i; t < n_tiles; t += (int64_t)gridDim.x * kBlockG) tile_cnt[t] = 0;
 
     int cnt = 0;
     int64_t area = 0;
@@ -231,18 +233,27 @@ __global__ __launch_bounds__(kBlockG) void k_scan_blocks(BlockSums* __restrict__
     }
 }
 
-// One thread per Gaussian: local exclusive scan + block offset, then the
-// Gaussian's pairs in tile row-major order.  Pairs past the capacity are
-// dropped (the overflow flag says so).  With kFold the block computes its
+// One thread per Gaussian: local exclusive scan + block offset (the
+// Gaussian's first emission index), then the Gaussian's tiles in row-major
+// order: each pair is counted into its tile (tile_cnt, cleared by the support
+// kernel), and the count before the pair's increment is its place in the
+// tile's list.  When the block's tiles span at most kEmitBins ids, the
+// pairs are counted in LDS first and the block adds one total per tile to the
+// global count (its place = the block's base + the LDS rank); otherwise each
+// pair takes a global atomic.  Pairs past the capacity are neither counted
+// nor placed (the overflow flag says so).  With kFold the block computes its
 // offset from the unscanned block sums itself, and the last block writes the
 // header totals (k_scan_blocks does both otherwise).
-template <bool kFold>
+template <bool kFold, typename Table>
 __global__ __launch_bounds__(kBlockG) void k_emit(
-    const ImgDev* __restrict__ imgs, const GRec* __restrict__ recs,
-    const int32_t* __restrict__ counts, const BlockSums* __restrict__ bs, int nblk,
-    int64_t n_gauss, int tile, int64_t cap, uint32_t* __restrict__ keys,
-    uint32_t* __restrict__ vals, int32_t* __restrict__ offsets, WsHeader* __restrict__ hdr) {
+    Table imgs, const GRec* __restrict__ recs, const int32_t* __restrict__ counts,
+    const BlockSums* __restrict__ bs, int nblk, int64_t n_gauss, int tile, int64_t cap,
+    int32_t* __restrict__ tile_cnt, uint32_t* __restrict__ slots, int32_t* __restrict__ offsets,
+    WsHeader* __restrict__ hdr) {
     __shared__ int64_t tmp[kBlockG / 64];
+    __shared__ int64_t win[2][kBlockG / 64];
+    __shared__ int32_t bins[kEmitBins];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int64_t base;
     if (kFold) {
         const int b = blockIdx.x;
@@ -254,7 +265,6 @@ __global__ __launch_bounds__(kBlockG) void k_emit(
         }
         lower = wave_sum_i64(lower);
         __shared__ int64_t t3[3][kBlockG / 64];
-        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
         if (last_block) { sup = wave_sum_i64(sup); inv = wave_sum_i64(inv); }
         if (lane == 0) { t3[0][wave] = lower; t3[1][wave] = sup; t3[2][wave] = inv; }
         __syncthreads();
@@ -267,8 +277,7 @@ __global__ __launch_bounds__(kBlockG) void k_emit(
             hdr->overflow = total > cap ? 1 : 0;
             hdr->n_support = sa;
             hdr->n_invalid = sb;
-                hdr->ordered = 0;
-        hdr->ordered = 0;
+            hdr->ordered = 0;
         }
     } else {
         base = bs[blockIdx.x].pairs;  // scanned by k_scan_blocks
@@ -276,58 +285,366 @@ __global__ __launch_bounds__(kBlockG) void k_emit(
     const int64_t i = (int64_t)blockIdx.x * kBlockG + threadIdx.x;
     const int cnt = i < n_gauss ? counts[i] : 0;
     const int64_t inc = block_inclusive_scan((int64_t)cnt, tmp);
-    int64_t off = base + inc - cnt;
+    const int64_t off = base + inc - cnt;
     if (i < n_gauss) offsets[i] = (int32_t)(off < cap ? off : cap);
-    if (cnt == 0) return;
-    const GRec r = recs[i];
-    const ImgDev im = imgs[r.img];
-    const int tx0 = r.x0 / tile, tx1 = r.x1 / tile;
-    const int ty0 = r.y0 / tile, ty1 = r.y1 / tile;
-    for (int ty = ty0; ty <= ty1; ++ty) {
-        for (int tx = tx0; tx <= tx1; ++tx) {
-            if (off < cap) {
-                keys[off] = (uint32_t)(im.tile_base + (int64_t)ty * im.tiles_x + tx);
-                vals[off] = (uint32_t)i;
+
+    // pairs kept, the first tile id and the box's tile geometry
+    int n = 0, tx0 = 0, tx1 = -1, ty0 = 0, tiles_x = 0;
+    int64_t tb = 0, lo = INT64_MAX, hi = -1;
+    if (cnt > 0 && off < cap) {
+        const GRec r = recs[i];
+        const ImgDev& im = imgs[r.img];
+        tx0 = r.x0 / tile; tx1 = r.x1 / tile; ty0 = r.y0 / tile;
+        const int ty1 = r.y1 / tile;
+        tiles_x = im.tiles_x;
+        tb = im.tile_base;
+        n = (int)(cap - off < (int64_t)cnt ? cap - off : (int64_t)cnt);
+        lo = tb + (int64_t)ty0 * tiles_x + tx0;
+        hi = tb + (int64_t)ty1 * tiles_x + tx1;
+    }
+    // the block's tile window
+    for (int o = 32; o > 0; o >>= 1) {
+        lo = min(lo, (int64_t)__shfl_xor(lo, o, 64));
+        hi = max(hi, (int64_t)__shfl_xor(hi, o, 64));
+    }
+    if (lane == 0) { win[0][wave] = lo; win[1][wave] = hi; }
+    __syncthreads();
+    int64_t wlo = win[0][0], whi = win[1][0];
+    for (int k = 1; k < kBlockG / 64; ++k) { wlo = min(wlo, win[0][k]); whi = max(whi, win[1][k]); }
+    if (whi < wlo) return;  // uniform: no pairs in this block
+
+    if (whi - wlo < kEmitBins) {  // uniform
+        const int nw = (int)(whi - wlo + 1);
+        for (int j = threadIdx.x; j < nw; j += kBlockG) bins[j] = 0;
+        __syncthreads();
+        // LDS ranks; the first kKeep in registers, the rest parked in slots
+        constexpr int kKeep = 8;
+        uint32_t rk[kKeep];
+        int tx = tx0, ty = ty0;
+#pragma unroll
+        for (int k = 0; k < kKeep; ++k) {
+            rk[k] = 0;
+            if (k < n) {
+                rk[k] = (uint32_t)atomicAdd(&bins[(int)(tb + (int64_t)ty * tiles_x + tx - wlo)], 1);
+                if (++tx > tx1) { tx = tx0; ++ty; }
             }
-            ++off;
+        }
+        for (int k = kKeep; k < n; ++k) {
+            slots[off + k] = (uint32_t)atomicAdd(&bins[(int)(tb + (int64_t)ty * tiles_x + tx - wlo)], 1);
+            if (++tx > tx1) { tx = tx0; ++ty; }
+        }
+        __syncthreads();
+        // one global atomic per tile: the block's base in the tile's list
+        for (int j = threadIdx.x; j < nw; j += kBlockG) {
+            const int c = bins[j];
+            if (c) bins[j] = atomicAdd(&tile_cnt[wlo + j], c);
+        }
+        __syncthreads();
+        tx = tx0; ty = ty0;
+#pragma unroll
+        for (int k = 0; k < kKeep; ++k) {
+            if (k < n) {
+                slots[off + k] = (uint32_t)bins[(int)(tb + (int64_t)ty * tiles_x + tx - wlo)] + rk[k];
+                if (++tx > tx1) { tx = tx0; ++ty; }
+            }
+        }
+        for (int k = kKeep; k < n; ++k) {
+            slots[off + k] += (uint32_t)bins[(int)(tb + (int64_t)ty * tiles_x + tx - wlo)];
+            if (++tx > tx1) { tx = tx0; ++ty; }
+        }
+        return;
+    }
+    // wide block: a global atomic per pair, four in flight per thread
+    int tx = tx0, ty = ty0;
+    for (int k0 = 0; k0 < n; k0 += 4) {
+        uint32_t slot[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            slot[u] = 0;
+            if (k0 + u < n) {
+                slot[u] = (uint32_t)atomicAdd(&tile_cnt[tb + (int64_t)ty * tiles_x + tx], 1);
+                if (++tx > tx1) { tx = tx0; ++ty; }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (k0 + u < n) slots[off + k0 + u] = slot[u];
+    }
+}
+
+// Inclusive scan of one int64 value per thread across a workgroup of
+// kScanThreads threads; `tmp` holds kScanThreads / 64 entries.
+__device__ __forceinline__ int64_t scan_block_inclusive(int64_t v, int64_t* tmp) {
+    constexpr int NW = kScanThreads / 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
+    }
+    if (lane == 63) tmp[wave] = v;
+    __syncthreads();
+    if (wave == 0) {
+        int64_t x = lane < NW ? tmp[lane] : 0;
+        for (int o = 1; o < NW; o <<= 1) {
+            const int64_t u = __shfl_up(x, o, 64);
+            if (lane >= o) x += u;
+        }
+        if (lane < NW) tmp[lane] = x;  // inclusive over waves
+    }
+    __syncthreads();
+    const int64_t carry = wave > 0 ? tmp[wave - 1] : 0;
+    __syncthreads();
+    return v + carry;
+}
+
+// Tile-count scan, blocks of kScanTile tiles (kScanPer consecutive tiles per
+// thread).  With several blocks: k_tile_sums writes each block's count,
+// k_scan_sums scans them, k_tile_ranges adds the block's base.
+__global__ __launch_bounds__(kScanThreads) void k_tile_sums(const int32_t* __restrict__ tile_cnt,
+                                                            int64_t n_tiles,
+                                                            int64_t* __restrict__ sums) {
+    __shared__ int64_t tmp[kScanThreads / 64];
+    const int64_t b0 = (int64_t)blockIdx.x * kScanTile;
+    int64_t v = 0;
+#pragma unroll
+    for (int u = 0; u < kScanPer; ++u) {
+        const int64_t j = b0 + u * kScanThreads + threadIdx.x;
+        if (j < n_tiles) v += tile_cnt[j];
+    }
+    v = wave_sum_i64(v);
+    if ((threadIdx.x & 63) == 0) tmp[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t b = 0;
+        for (int k = 0; k < kScanThreads / 64; ++k) b += tmp[k];
+        sums[blockIdx.x] = b;
+    }
+}
+
+// One workgroup: exclusive scan of the block sums, in place.
+__global__ __launch_bounds__(kScanThreads) void k_scan_sums(int64_t* __restrict__ sums, int nblk) {
+    __shared__ int64_t tmp[kScanThreads / 64];
+    __shared__ int64_t last;
+    int64_t carry = 0;
+    for (int base = 0; base < nblk; base += kScanThreads) {
+        const int j = base + threadIdx.x;
+        const int64_t v = j < nblk ? sums[j] : 0;
+        const int64_t inc = scan_block_inclusive(v, tmp);
+        if (j < nblk) sums[j] = carry + inc - v;
+        if (threadIdx.x == kScanThreads - 1) last = inc;
+        __syncthreads();
+        carry += last;
+        __syncthreads();
+    }
+}
+
+// The tile ranges: [begin, end) from the exclusive scan of the counts
+// ([0, 0) for an empty tile).
+__global__ __launch_bounds__(kScanThreads) void k_tile_ranges(const int32_t* __restrict__ tile_cnt,
+                                                              int2* __restrict__ ranges,
+                                                              int64_t n_tiles,
+                                                              const int64_t* __restrict__ sums,
+                                                              int multi) {
+    __shared__ int64_t tmp[kScanThreads / 64];
+    __shared__ int32_t sc[kScanTile];
+    const int64_t b0 = (int64_t)blockIdx.x * kScanTile;
+    // coalesced loads into LDS, then kScanPer consecutive counts per thread
+#pragma unroll
+    for (int u = 0; u < kScanPer; ++u) {
+        const int j = u * kScanThreads + threadIdx.x;
+        sc[j] = b0 + j < n_tiles ? tile_cnt[b0 + j] : 0;
+    }
+    __syncthreads();
+    const int64_t t0 = b0 + (int64_t)threadIdx.x * kScanPer;
+    int c[kScanPer];
+    int64_t v = 0;
+#pragma unroll
+    for (int u = 0; u < kScanPer; ++u) {
+        c[u] = sc[threadIdx.x * kScanPer + u];
+        v += c[u];
+    }
+    const int64_t inc = scan_block_inclusive(v, tmp);
+    int64_t b = (multi ? sums[blockIdx.x] : 0) + inc - v;
+#pragma unroll
+    for (int u = 0; u < kScanPer; ++u) {
+        if (t0 + u < n_tiles)
+            ranges[t0 + u] = c[u] ? make_int2((int)b, (int)(b + c[u])) : make_int2(0, 0);
+        b += c[u];
+    }
+}
+
+// One thread per Gaussian: its id written at its place in each of its tiles'
+// lists (the tiles in the emission's order).  With kLocalScan (at most
+// kPlaceScanTiles tiles) every block scans the tile counts into LDS itself
+// and block 0 writes the tile ranges; otherwise the ranges come from the scan
+// kernels.
+template <bool kLocalScan, typename Table>
+__global__ __launch_bounds__(kBlockG) void k_place(
+    Table imgs, const GRec* __restrict__ recs, const int32_t* __restrict__ counts,
+    const int32_t* __restrict__ offsets, int64_t n_gauss, int tile, int64_t cap,
+    const int32_t* __restrict__ tile_cnt, int64_t n_tiles, int2* __restrict__ ranges,
+    const uint32_t* __restrict__ slots, uint32_t* __restrict__ lists) {
+    constexpr int kPer = kPlaceScanTiles / kBlockG;
+    // LDS index of tile j: one pad word every 32, so that a thread's kPer
+    // consecutive tiles and the coalesced fill are both free of bank conflicts
+    auto lds = [](int j) { return j + (j >> 5); };
+    __shared__ int32_t s_off[kLocalScan ? kPlaceScanTiles + kPlaceScanTiles / 32 : 1];
+    __shared__ int64_t tmp[kBlockG / 64];
+    // this Gaussian's inputs first: their latency overlaps the scan below
+    const int64_t i = (int64_t)blockIdx.x * kBlockG + threadIdx.x;
+    int cnt = 0;
+    int64_t off = cap;
+    GRec r;
+    if (i < n_gauss) {
+        cnt = counts[i];
+        off = offsets[i];
+        if (cnt > 0 && off < cap) r = recs[i];
+    }
+    if (kLocalScan) {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int j = u * kBlockG + threadIdx.x;
+            s_off[lds(j)] = j < n_tiles ? tile_cnt[j] : 0;
+        }
+        __syncthreads();
+        const int t0 = threadIdx.x * kPer;
+        int c[kPer];
+        int64_t v = 0;
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            c[u] = s_off[lds(t0 + u)];
+            v += c[u];
+        }
+        const int64_t inc = block_inclusive_scan(v, tmp);  // has barriers
+        int b = (int)(inc - v);
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            s_off[lds(t0 + u)] = b;
+            if (blockIdx.x == 0 && t0 + u < n_tiles)
+                ranges[t0 + u] = c[u] ? make_int2(b, b + c[u]) : make_int2(0, 0);
+            b += c[u];
+        }
+        __syncthreads();
+    }
+    if (cnt == 0 || off >= cap) return;
+    const ImgDev& im = imgs[r.img];
+    const int tx0 = r.x0 / tile, tx1 = r.x1 / tile, ty0 = r.y0 / tile;
+    const int n = (int)(cap - off < (int64_t)cnt ? cap - off : (int64_t)cnt);
+    const int64_t tb = im.tile_base;
+    int tx = tx0, ty = ty0;
+    for (int k0 = 0; k0 < n; k0 += 4) {
+        int pos[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            pos[u] = -1;
+            if (k0 + u < n) {
+                const int64_t t = tb + (int64_t)ty * im.tiles_x + tx;
+                pos[u] = (kLocalScan ? s_off[lds((int)t)] : ranges[t].x) + (int)slots[off + k0 + u];
+                if (++tx > tx1) { tx = tx0; ++ty; }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (pos[u] >= 0) lists[pos[u]] = (uint32_t)i;
+    }
+}
+
+// Ascending bitonic sort of one value per lane across the wave.
+__device__ __forceinline__ uint32_t wave_sort64(uint32_t v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const uint32_t p = (uint32_t)__shfl_xor((int)v, j, 64);
+            const bool up = (lane & k) == 0;
+            const bool low = (lane & j) == 0;
+            v = (low == up) ? min(v, p) : max(v, p);
         }
     }
+    return v;
 }
 
-__device__ __forceinline__ int64_t pairs_in_use(const WsHeader* hdr, int64_t cap) {
-    const int64_t p = hdr->n_pairs;
-    return p < cap ? p : cap;
+// Number of entries of the ascending run a[0, n), n >= 1, below x.
+__device__ __forceinline__ int count_below(const uint32_t* a, int n, uint32_t x) {
+    int lo = 0;
+    for (int step = 1 << (31 - __builtin_clz((unsigned)n)); step > 0; step >>= 1)
+        if (lo + step <= n && a[lo + step - 1] < x) lo += step;
+    return lo;
 }
 
-// Sort sources.  PairDigits: the (tile, Gaussian) pairs, keyed by the 8-bit
-// digit of the tile id at `shift`.  TileDigits: the tiles themselves, keyed
-// by the bucket of their list length, longest first (the longest-processing-
-// time order the persistent tile kernels take their work in).
-struct PairDigits {
-    const uint32_t* keys;
-    const uint32_t* vals;
-    const WsHeader* hdr;
-    int64_t cap;
-    int shift;
-    __device__ __forceinline__ int64_t count() const { return pairs_in_use(hdr, cap); }
-    __device__ __forceinline__ int digit(int64_t i) const {
-        return (int)((keys[i] >> shift) & (kRadix - 1));
+// Sorts seg[0, n), n <= kSegLds, ascending (distinct values): each wave sorts
+// 64-entry runs into LDS, then every entry's rank is its place in its own run
+// plus the entries below it in the other runs.  Ends with a barrier.
+__device__ __forceinline__ void sort_chunk(uint32_t* __restrict__ seg, int n, uint32_t* sk) {
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    constexpr int NW = kSegThreads / 64;
+    const int runs = (n + 63) >> 6;
+    for (int q = wave; q < runs; q += NW) {
+        const int idx = q * 64 + lane;
+        const uint32_t v = idx < n ? seg[idx] : 0xffffffffu;
+        sk[idx] = wave_sort64(v);
     }
-    __device__ __forceinline__ void load(int64_t i, int* d, uint32_t* a, uint32_t* b) const {
-        *a = keys[i];
-        *b = vals[i];
-        *d = (int)((*a >> shift) & (kRadix - 1));
+    __syncthreads();
+    for (int i = t; i < n; i += kSegThreads) {
+        const uint32_t x = sk[i];
+        const int own = i >> 6;
+        int pos = i & 63;
+        for (int q = 0; q < runs; ++q)
+            if (q != own) pos += count_below(sk + q * 64, 64, x);
+        seg[pos] = x;
     }
-};
-struct PairSink {
-    uint32_t* keys;
-    uint32_t* vals;
-    __device__ __forceinline__ void store(int64_t pos, uint32_t a, uint32_t b) const {
-        keys[pos] = a;
-        vals[pos] = b;
-    }
-};
+    __syncthreads();
+}
 
+// One workgroup per tile: the tile's list sorted ascending.  Up to 64 ids one
+// wave sorts them in registers; up to kSegLds they go through LDS; longer
+// lists are sorted in kSegLds chunks, then merged pairwise through `spare`
+// (each entry's place: its index in its run plus the entries below it in the
+// partner run).
+__global__ __launch_bounds__(kSegThreads) void k_sort_lists(const int2* __restrict__ ranges,
+                                                            uint32_t* __restrict__ lists,
+                                                            uint32_t* __restrict__ spare) {
+    __shared__ uint32_t sk[kSegLds];
+    const int2 r = ranges[blockIdx.x];
+    const int n = r.y - r.x;
+    if (n <= 1) return;  // uniform
+    uint32_t* seg = lists + r.x;
+    if (n <= 64) {
+        if (threadIdx.x >= 64) return;
+        const int lane = threadIdx.x;
+        const uint32_t v = wave_sort64(lane < n ? seg[lane] : 0xffffffffu);
+        if (lane < n) seg[lane] = v;
+        return;
+    }
+    if (n <= kSegLds) {
+        sort_chunk(seg, n, sk);
+        return;
+    }
+    for (int c0 = 0; c0 < n; c0 += kSegLds) sort_chunk(seg + c0, min(kSegLds, n - c0), sk);
+    uint32_t* src = seg;
+    uint32_t* dst = spare + r.x;
+    for (int64_t w = kSegLds; w < n; w *= 2) {
+        for (int i = threadIdx.x; i < n; i += kSegThreads) {
+            const uint32_t x = src[i];
+            const int64_t run = i / w, first = run * w;
+            const int64_t p0 = (run ^ 1) * w;  // partner run
+            int below = 0;
+            if (p0 < n) below = count_below(src + p0, (int)min(w, (int64_t)n - p0), x);
+            dst[min(first, p0) + (i - first) + below] = x;
+        }
+        __syncthreads();
+        uint32_t* sw = src;
+        src = dst;
+        dst = sw;
+    }
+    if (src != seg)
+        for (int i = threadIdx.x; i < n; i += kSegThreads) seg[i] = src[i];
+}
+
+// Sort source of the tile order: the tiles themselves, keyed by the bucket
+// of their list length, longest first (the longest-processing-time order the
+// persistent tile kernels take their work in).
 // List length -> digit: lengths 0..127 one bucket each, then buckets 16 wide,
 // everything from 2160 on in the last; digit 255 - bucket puts long lists first.
 __device__ __forceinline__ int length_digit(int len) {
@@ -454,18 +771,6 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
 
 __global__ void k_mark_ordered(WsHeader* __restrict__ hdr) { hdr->ordered = 1; }
 
-// One thread per sorted pair: the tile range boundaries.
-__global__ __launch_bounds__(kBlockG) void k_ranges(const uint32_t* __restrict__ keys,
-                                                    const WsHeader* __restrict__ hdr,
-                                                    int64_t cap, int2* __restrict__ ranges) {
-    const int64_t p = (int64_t)blockIdx.x * kBlockG + threadIdx.x;
-    const int64_t P = pairs_in_use(hdr, cap);
-    if (p >= P) return;
-    const uint32_t k = keys[p];
-    if (p == 0 || keys[p - 1] != k) ranges[k].x = (int)p;
-    if (p == P - 1 || keys[p + 1] != k) ranges[k].y = (int)(p + 1);
-}
-
 inline int blocks_for(int64_t n, int per) { return (int)((n + per - 1) / per); }
 
 }  // namespace
@@ -491,42 +796,78 @@ hipError_t launch_support(const Layout& L, const Ws& w, const ImgDev* host_imgs,
     if (by_value)
         hipLaunchKernelGGL(k_support<true>, dim3(L.nblk_g), dim3(kBlockG), 0, st, chunk, w.imgs,
                            L.n_img, L.n_gauss, L.tile, mean, chol, color, opacity, radius,
-                           w.recs, w.counts, w.blocksums, w.ranges, L.n_tiles, mom, w.sched);
+                           w.recs, w.counts, w.blocksums, w.tile_cnt, L.n_tiles, mom, w.sched);
     else
         hipLaunchKernelGGL(k_support<false>, dim3(L.nblk_g), dim3(kBlockG), 0, st, chunk, w.imgs,
                            L.n_img, L.n_gauss, L.tile, mean, chol, color, opacity, radius,
-                           w.recs, w.counts, w.blocksums, w.ranges, L.n_tiles, mom, w.sched);
+                           w.recs, w.counts, w.blocksums, w.tile_cnt, L.n_tiles, mom, w.sched);
     if (count_only || L.nblk_g > kFoldScanBlocks)
         hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kBlockG), 0, st, w.blocksums, L.nblk_g,
                            L.cap, w.hdr);
     return hipGetLastError();
 }
 
-hipError_t launch_emit(const Layout& L, const Ws& w, hipStream_t st) {
+template <typename Table>
+void launch_emit_t(const Layout& L, const Ws& w, Table tab, hipStream_t st) {
     if (L.nblk_g > kFoldScanBlocks)
-        hipLaunchKernelGGL(k_emit<false>, dim3(L.nblk_g), dim3(kBlockG), 0, st, w.imgs, w.recs,
-                           w.counts, w.blocksums, L.nblk_g, L.n_gauss, L.tile, L.cap,
-                           w.keys[0], w.vals[0], w.offsets, w.hdr);
+        hipLaunchKernelGGL((k_emit<false, Table>), dim3(L.nblk_g), dim3(kBlockG), 0, st, tab,
+                           w.recs, w.counts, w.blocksums, L.nblk_g, L.n_gauss, L.tile, L.cap,
+                           w.tile_cnt, w.slots, w.offsets, w.hdr);
     else
-        hipLaunchKernelGGL(k_emit<true>, dim3(L.nblk_g), dim3(kBlockG), 0, st, w.imgs, w.recs,
-                           w.counts, w.blocksums, L.nblk_g, L.n_gauss, L.tile, L.cap,
-                           w.keys[0], w.vals[0], w.offsets, w.hdr);
+        hipLaunchKernelGGL((k_emit<true, Table>), dim3(L.nblk_g), dim3(kBlockG), 0, st, tab,
+                           w.recs, w.counts, w.blocksums, L.nblk_g, L.n_gauss, L.tile, L.cap,
+                           w.tile_cnt, w.slots, w.offsets, w.hdr);
+}
+
+hipError_t launch_emit(const Layout& L, const Ws& w, hipStream_t st) {
+    if (L.n_img <= kSetupChunk && L.host_imgs) {
+        ArgTable tab;
+        for (int k = 0; k < kSetupChunk; ++k) tab.c.img[k] = k < L.n_img ? L.host_imgs[k] : ImgDev{};
+        launch_emit_t(L, w, tab, st);
+    } else {
+        launch_emit_t(L, w, MemTable{w.imgs}, st);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_sort(const Layout& L, const Ws& w, hipStream_t st) {
-    int32_t* totals = w.hist + (int64_t)kRadix * L.nblk_sort;
-    for (int pass = 0; pass < L.n_passes; ++pass) {
-        const int src = pass & 1, dst = src ^ 1;
-        const PairDigits in{w.keys[src], w.vals[src], w.hdr, L.cap, pass * kRadixBits};
-        const PairSink out{w.keys[dst], w.vals[dst]};
-        hipLaunchKernelGGL(k_sort_hist<PairDigits>, dim3(L.nblk_sort), dim3(kSortThreads), 0, st,
-                           in, L.nblk_sort, w.hist);
-        hipLaunchKernelGGL(k_sort_rowscan, dim3(kRadix), dim3(kBlockG), 0, st, w.hist,
-                           L.nblk_sort, totals);
-        hipLaunchKernelGGL((k_sort_scatter<PairDigits, PairSink>), dim3(L.nblk_sort),
-                           dim3(kSortThreads), 0, st, in, out, w.hist, totals, L.nblk_sort);
+template <typename Table>
+void launch_place_t(const Layout& L, const Ws& w, Table tab, bool local_scan, hipStream_t st) {
+    if (local_scan)
+        hipLaunchKernelGGL((k_place<true, Table>), dim3(L.nblk_g), dim3(kBlockG), 0, st, tab,
+                           w.recs, w.counts, w.offsets, L.n_gauss, L.tile, L.cap, w.tile_cnt,
+                           L.n_tiles, w.ranges, w.slots, w.lists);
+    else
+        hipLaunchKernelGGL((k_place<false, Table>), dim3(L.nblk_g), dim3(kBlockG), 0, st, tab,
+                           w.recs, w.counts, w.offsets, L.n_gauss, L.tile, L.cap, w.tile_cnt,
+                           L.n_tiles, w.ranges, w.slots, w.lists);
+}
+
+hipError_t launch_lists(const Layout& L, const Ws& w, hipStream_t st) {
+    if (L.n_tiles == 0) return hipSuccess;
+    // small batches: the placement blocks scan the counts themselves (each
+    // reads all of them, so only while that stays a few MB)
+    const bool local_scan = L.n_tiles <= kPlaceScanTiles &&
+                            L.n_tiles * (int64_t)L.nblk_g <= ((int64_t)1 << 22);
+    if (!local_scan) {
+        const int multi = L.nblk_scan > 1 ? 1 : 0;
+        if (multi) {
+            hipLaunchKernelGGL(k_tile_sums, dim3(L.nblk_scan), dim3(kScanThreads), 0, st,
+                               w.tile_cnt, L.n_tiles, w.scan_sums);
+            hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanThreads), 0, st, w.scan_sums,
+                               L.nblk_scan);
+        }
+        hipLaunchKernelGGL(k_tile_ranges, dim3(L.nblk_scan), dim3(kScanThreads), 0, st,
+                           w.tile_cnt, w.ranges, L.n_tiles, w.scan_sums, multi);
     }
+    if (L.n_img <= kSetupChunk && L.host_imgs) {
+        ArgTable tab;
+        for (int k = 0; k < kSetupChunk; ++k) tab.c.img[k] = k < L.n_img ? L.host_imgs[k] : ImgDev{};
+        launch_place_t(L, w, tab, local_scan, st);
+    } else {
+        launch_place_t(L, w, MemTable{w.imgs}, local_scan, st);
+    }
+    hipLaunchKernelGGL(k_sort_lists, dim3((unsigned)L.n_tiles), dim3(kSegThreads), 0, st,
+                       w.ranges, w.lists, w.spare);
     return hipGetLastError();
 }
 
@@ -542,12 +883,6 @@ hipError_t launch_order(const Layout& L, const Ws& w, hipStream_t st) {
                        dim3(kSortThreads), 0, st, in, OrderSink{w.order}, w.order_hist, totals,
                        L.nblk_order);
     hipLaunchKernelGGL(k_mark_ordered, dim3(1), dim3(1), 0, st, w.hdr);
-    return hipGetLastError();
-}
-
-hipError_t launch_ranges(const Layout& L, const Ws& w, hipStream_t st) {
-    hipLaunchKernelGGL(k_ranges, dim3(blocks_for(L.cap, kBlockG)), dim3(kBlockG), 0, st,
-                       w.keys[L.n_passes & 1], w.hdr, L.cap, w.ranges);
     return hipGetLastError();
 }
 

@@ -15,10 +15,18 @@ constexpr int kSetupChunk = 32;        // images per table chunk (kernel argumen
 constexpr int kFoldScanBlocks = 2048;  // up to this many Gaussian blocks the
                                        // emission kernel scans the block sums itself
 constexpr int kBlockG = 256;           // threads of per-Gaussian kernels
-constexpr int kSortThreads = 256;      // radix sort workgroup
+constexpr int kSortThreads = 256;      // tile-order radix sort workgroup
 constexpr int kSortItems = 4;          // keys per thread per sort block
 constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kRadixBits = 8;
+constexpr int kScanThreads = 1024;     // tile-count scan workgroup
+constexpr int kScanPer = 16;           // tiles per scan thread
+constexpr int kScanTile = kScanThreads * kScanPer;
+constexpr int kSegThreads = 256;       // per-tile list sort workgroup
+constexpr int kSegLds = 2048;          // longest list sorted in LDS in one go
+constexpr int kEmitBins = 4096;        // widest tile window counted in LDS by one emission block
+constexpr int kPlaceScanTiles = 4096;  // up to this many tiles each placement block scans the
+                                       // tile counts itself
 // Persistent tile kernels: per kernel (forward, backward) kSchedParts work
 // counters and one exit counter, each on a 64-byte line of its own.
 constexpr int kSchedParts = 16;
@@ -86,18 +94,13 @@ struct Layout {
     int64_t n_tiles = 0;
     int64_t cap = 0;          // pair capacity
     int32_t nblk_g = 0;       // blocks of per-Gaussian kernels
-    int32_t nblk_sort = 0;    // blocks of the sort at full capacity
-    int32_t n_passes = 0;     // radix passes over the tile-id bits
+    int32_t nblk_scan = 0;    // blocks of the tile-count scan
     int32_t nblk_order = 0;   // blocks of the tile-order sort
     size_t off_order = 0, off_order_hist = 0, off_sched = 0;
     size_t off_header = 0, off_imgs = 0, off_recs = 0, off_counts = 0, off_offsets = 0,
-           off_blocksums = 0, off_keys0 = 0, off_vals0 = 0, off_keys1 = 0, off_vals1 = 0,
-           off_hist = 0, off_ranges = 0, off_moments = 0, off_tile_loss = 0,
-           off_partials = 0, total = 0;
-    // buffer holding the sorted result after n_passes ping-pong passes
+           off_blocksums = 0, off_tile_cnt = 0, off_scan_sums = 0, off_slots = 0, off_lists = 0, off_spare = 0,
+           off_ranges = 0, off_moments = 0, off_tile_loss = 0, off_partials = 0, total = 0;
     const ImgDev* host_imgs = nullptr;  // host copy of the table (valid during a call)
-    size_t sorted_keys() const { return (n_passes & 1) ? off_keys1 : off_keys0; }
-    size_t sorted_vals() const { return (n_passes & 1) ? off_vals1 : off_vals0; }
 };
 
 // Device pointers into one workspace.
@@ -108,10 +111,12 @@ struct Ws {
     int32_t* counts;
     int32_t* offsets;
     BlockSums* blocksums;
-    uint32_t* keys[2];
-    uint32_t* vals[2];
-    int32_t* hist;
-    int2* ranges;
+    int32_t* tile_cnt;   // per tile: pairs counted by the emission
+    int64_t* scan_sums;  // per scan block: tile-count sums, then their exclusive scan
+    uint32_t* slots;     // per emitted pair (emission order): its place in its tile's list
+    uint32_t* lists;     // per tile, its Gaussian ids ascending (tile ranges index it)
+    uint32_t* spare;     // merge buffer of the longest lists' sort
+    int2* ranges;        // per tile [begin, end) in lists ([0, 0) when empty)
     float* moments;
     double* tile_loss;
     float4* partials;    // per emitted pair (emission order): 8 backward sums (2 x float4)
@@ -129,11 +134,11 @@ inline Ws bind(const Layout& L, void* base) {
     w.counts = reinterpret_cast<int32_t*>(b + L.off_counts);
     w.offsets = reinterpret_cast<int32_t*>(b + L.off_offsets);
     w.blocksums = reinterpret_cast<BlockSums*>(b + L.off_blocksums);
-    w.keys[0] = reinterpret_cast<uint32_t*>(b + L.off_keys0);
-    w.vals[0] = reinterpret_cast<uint32_t*>(b + L.off_vals0);
-    w.keys[1] = reinterpret_cast<uint32_t*>(b + L.off_keys1);
-    w.vals[1] = reinterpret_cast<uint32_t*>(b + L.off_vals1);
-    w.hist = reinterpret_cast<int32_t*>(b + L.off_hist);
+    w.tile_cnt = reinterpret_cast<int32_t*>(b + L.off_tile_cnt);
+    w.scan_sums = reinterpret_cast<int64_t*>(b + L.off_scan_sums);
+    w.slots = reinterpret_cast<uint32_t*>(b + L.off_slots);
+    w.lists = reinterpret_cast<uint32_t*>(b + L.off_lists);
+    w.spare = reinterpret_cast<uint32_t*>(b + L.off_spare);
     w.ranges = reinterpret_cast<int2*>(b + L.off_ranges);
     w.moments = reinterpret_cast<float*>(b + L.off_moments);
     w.tile_loss = reinterpret_cast<double*>(b + L.off_tile_loss);
@@ -169,9 +174,11 @@ hipError_t launch_support(const Layout& L, const Ws& w, const ImgDev* host_imgs,
                           const float* mean, const float* chol, const float* color,
                           const float* opacity, const float* radius, bool count_only,
                           hipStream_t st);
+// Pairs: per-Gaussian offsets, per-tile counts and each pair's place in its
+// tile's list (counting atomics).
 hipError_t launch_emit(const Layout& L, const Ws& w, hipStream_t st);
-hipError_t launch_sort(const Layout& L, const Ws& w, hipStream_t st);
-hipError_t launch_ranges(const Layout& L, const Ws& w, hipStream_t st);
+// Tile ranges from the counts, the Gaussian ids placed, each list sorted.
+hipError_t launch_lists(const Layout& L, const Ws& w, hipStream_t st);
 // Tile work order for the persistent kernels: longest list first.
 hipError_t launch_order(const Layout& L, const Ws& w, hipStream_t st);
 

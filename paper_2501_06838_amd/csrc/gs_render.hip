@@ -795,7 +795,7 @@ static hipError_t launch_fwd_tb(const Layout& L, const Ws& w, const Table& tab, 
                                    TileShape<T>::kThreads, &grid);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(TileShape<T>::kThreads), 0, st, tab, L.n_img,
-                       w.vals[L.n_passes & 1], w.recs, w.offsets, w.ranges, out, w.order, w.hdr, L.n_tiles,
+                       w.lists, w.recs, w.offsets, w.ranges, out, w.order, w.hdr, L.n_tiles,
                        (L.flags & GS_FLAG_PERSISTENT) ? 1 : 0, w.sched);
     return hipGetLastError();
 }
@@ -844,7 +844,7 @@ static hipError_t launch_bwd_tt(const Layout& L, const Ws& w, const Table& tab,
                                    TileShape<T>::kThreads, &grid);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(TileShape<T>::kThreads), 0, st, tab, L.n_img,
-                       w.vals[L.n_passes & 1], w.recs, w.offsets, w.ranges, grad_out, target, inv_numel, w.tile_loss, w.moments,
+                       w.lists, w.recs, w.offsets, w.ranges, grad_out, target, inv_numel, w.tile_loss, w.moments,
                        w.partials, (L.flags & GS_FLAG_ATOMIC_GRADS) ? 1 : 0, w.order, w.hdr,
                        L.n_tiles, (L.flags & GS_FLAG_PERSISTENT) ? 1 : 0,
                        w.sched + kSchedWords / 2);
@@ -909,7 +909,7 @@ static hipError_t launch_fused_tt(const Layout& L, const Ws& w, const Table& tab
                                    TileShape<T>::kThreads, &grid);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(TileShape<T>::kThreads), 0, st, tab, L.n_img,
-                       w.vals[L.n_passes & 1], w.recs, w.offsets, w.ranges, out, target, inv_numel, w.tile_loss, w.moments,
+                       w.lists, w.recs, w.offsets, w.ranges, out, target, inv_numel, w.tile_loss, w.moments,
                        w.partials, (L.flags & GS_FLAG_ATOMIC_GRADS) ? 1 : 0, w.order, w.hdr,
                        L.n_tiles, (L.flags & GS_FLAG_PERSISTENT) ? 1 : 0,
                        w.sched + kSchedWords / 2);

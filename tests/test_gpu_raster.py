@@ -53,6 +53,50 @@ def test_tile_lists_bit_exact(name, make, tile):
     assert n_support == O.support_pairs_batch(wl)
 
 
+@pytest.mark.parametrize("tile", [8, 16])
+def test_tile_lists_with_empty_tiles(tile):
+    """Gaussians right of LR x = 7 moved off the image: the right-hand tiles
+    list nothing ([0, 0) ranges), the others match the oracle bit for bit."""
+    wl = synth.tiny(H=8, W=16, s=4.0, seed=6)
+    wl.mean[wl.mean[:, 0] > 7.0] = 1000.0
+    say("empty tiles", tile, wl.n_gauss)
+    plan, ws, out = render(wl, tile)
+    ranges, gids = plan.tile_lists(ws)
+    r_ref, g_ref = O.tile_lists_batch(wl, tile, tile)
+    assert ((r_ref[:, 1] - r_ref[:, 0]) == 0).sum() >= 2
+    assert np.array_equal(ranges, r_ref)
+    assert np.array_equal(gids, g_ref)
+    for g, r in zip(_gpu_images(plan, out), _oracle_images(wl)):
+        assert_forward_close(g, r)
+
+
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_crowded_tiles_long_lists(tile):
+    """9,036 Gaussians over a 24 x 24 HR image: tile lists of thousands of
+    ids (the list sort's LDS chunks and its pairwise merges), bit-exact
+    against the oracle, with the forward and the backward against it too."""
+    wl = synth.tiny(H=6, W=6, s=4.0, seed=11, extra_frac=250.0, n_images=1)
+    say("crowded tiles", tile, wl.n_gauss)
+    plan, ws, out = render(wl, tile)
+    ranges, gids = plan.tile_lists(ws)
+    r_ref, g_ref = O.tile_lists_batch(wl, tile, tile)
+    assert (r_ref[:, 1] - r_ref[:, 0]).max() > 4096  # two merge levels
+    assert np.array_equal(ranges, r_ref)
+    assert np.array_equal(gids, g_ref)
+    got = _gpu_images(plan, out)
+    ref = _oracle_images(wl)
+    for g, r in zip(got, ref):
+        assert_forward_close(g, r)
+    rng = np.random.default_rng(4)
+    G = [rng.uniform(-1.0, 1.0, size=r.shape).astype(np.float32) for r in ref]
+    m, c, col, op = to_dev(wl)
+    grads = plan.backward(m, c, col, op, ws, plan.pack([torch.from_numpy(g) for g in G]).cuda())
+    torch.cuda.synchronize()
+    refg = O.backward_batch(wl, [np.float64(g) for g in G])
+    for name, a, r in zip(("mean", "chol", "color", "opacity"), grads, refg):
+        assert_grad_close(a.cpu().numpy(), r, name=name)
+
+
 # ---------------------------------------------------------------- forward
 
 FWD_CASES = [
