@@ -241,18 +241,35 @@ __device__ __forceinline__ void fwd_round(const StageLds<T, B>& st,
     for (int m = 0; m < S::kBlocksPerWave; ++m) {
         const int j = wave + S::kWaves * m;
         const int cnt = __builtin_amdgcn_readfirstlane(st.scount[j]);  // uniform
-        for (int q = 0; q < cnt; ++q) {
-            const float4 c0 = st.l0[j][q], c1 = st.l1[j][q];
-            const uint32_t mlo = __builtin_amdgcn_readfirstlane(st.l2[j][q].x);
-            const uint32_t mhi = __builtin_amdgcn_readfirstlane(st.l2[j][q].y);
-            const uint64_t mask = ((uint64_t)mhi << 32) | mlo;
-            const float z1 = __builtin_fmaf(c0.z, lxf, c0.x);
-            const float z2 = __builtin_fmaf(c0.w, lyf, __builtin_fmaf(-c1.x, lxf, c0.y));
-            float w = fast_exp2(-(z1 * z1 + z2 * z2));
-            w = __builtin_amdgcn_inverse_ballot_w64(mask) ? w : 0.f;
-            acc[m][0] += c1.y * w;
-            acc[m][1] += c1.z * w;
-            acc[m][2] += c1.w * w;
+        // two records per iteration (the second of an odd tail repeats the
+        // first with an empty mask), so their LDS reads and sums overlap
+        for (int q = 0; q < cnt; q += 2) {
+            const bool two = q + 1 < cnt;  // uniform
+            const int q1 = two ? q + 1 : q;
+            const float4 a0 = st.l0[j][q], a1 = st.l1[j][q];
+            const float4 b0 = st.l0[j][q1], b1 = st.l1[j][q1];
+            const uint32_t alo = __builtin_amdgcn_readfirstlane(st.l2[j][q].x);
+            const uint32_t ahi = __builtin_amdgcn_readfirstlane(st.l2[j][q].y);
+            uint32_t blo = __builtin_amdgcn_readfirstlane(st.l2[j][q1].x);
+            uint32_t bhi = __builtin_amdgcn_readfirstlane(st.l2[j][q1].y);
+            blo = two ? blo : 0u;
+            bhi = two ? bhi : 0u;
+            const uint64_t amask = ((uint64_t)ahi << 32) | alo;
+            const uint64_t bmask = ((uint64_t)bhi << 32) | blo;
+            const float za1 = __builtin_fmaf(a0.z, lxf, a0.x);
+            const float za2 = __builtin_fmaf(a0.w, lyf, __builtin_fmaf(-a1.x, lxf, a0.y));
+            const float zb1 = __builtin_fmaf(b0.z, lxf, b0.x);
+            const float zb2 = __builtin_fmaf(b0.w, lyf, __builtin_fmaf(-b1.x, lxf, b0.y));
+            float wa = fast_exp2(-(za1 * za1 + za2 * za2));
+            float wb = fast_exp2(-(zb1 * zb1 + zb2 * zb2));
+            wa = __builtin_amdgcn_inverse_ballot_w64(amask) ? wa : 0.f;
+            wb = __builtin_amdgcn_inverse_ballot_w64(bmask) ? wb : 0.f;
+            acc[m][0] += a1.y * wa;
+            acc[m][1] += a1.z * wa;
+            acc[m][2] += a1.w * wa;
+            acc[m][0] += b1.y * wb;
+            acc[m][1] += b1.z * wb;
+            acc[m][2] += b1.w * wb;
         }
     }
 }
@@ -306,17 +323,25 @@ __device__ __forceinline__ void bwd_round(BwdLds<T, B>& sm) {
         const int ry0 = __builtin_ctz(any >> 8), ry1 = 31 - __builtin_clz(any >> 8);
         const float a = c0.z, e = c0.w, gg = c1.x;
         float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f, m5 = 0.f, m6 = 0.f, m7 = 0.f;
+        // the box is a rectangle: a column outside it gets a far z1 (its
+        // weight underflows to 0, and 0 times the finite z is 0), a row
+        // outside it a zero row factor
+        const uint32_t colset = cm & 255u;
+        float zc1[8];
+#pragma unroll
+        for (int cx = 0; cx < 8; ++cx)
+            zc1[cx] = ((colset >> cx) & 1u) ? __builtin_fmaf(a, (float)cx, c0.x) : 1e19f;
         for (int ry = ry0; ry <= ry1; ++ry) {
             const uint32_t rowbits = ((ry < 4 ? mlo : mhi) >> (8 * (ry & 3))) & 255u;
+            const float rmul = rowbits ? 1.f : 0.f;
             const float4* grow = &sm.gt[(by + ry) * T + bx];
 #pragma unroll
             for (int cx = 0; cx < 8; ++cx) {
                 if (cx < cx0 || cx > cx1) continue;  // uniform
                 const float4 G = grow[cx];
-                const float z1 = __builtin_fmaf(a, (float)cx, c0.x);
+                const float z1 = zc1[cx];
                 const float z2 = __builtin_fmaf(e, (float)ry, __builtin_fmaf(-gg, (float)cx, c0.y));
-                float w = fast_exp2(-(z1 * z1 + z2 * z2));
-                w = (rowbits & (1u << cx)) ? w : 0.f;
+                const float w = fast_exp2(-(z1 * z1 + z2 * z2)) * rmul;
                 m0 += G.x * w;
                 m1 += G.y * w;
                 m2 += G.z * w;
