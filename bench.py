@@ -182,7 +182,7 @@ def pruned_comparison(args, G, synth, torch, np):
     net, info = train_radius_mlp(lambda k: synth.surrogate_training_batch(11, k), 600, 25, tau,
                                  steps=600, lr=3e-3, quantile=0.9, coverage=0.999)
     log(f"surrogate trained: margin {info['margin']:.3f}, loss {info['losses'][-1]:.4f}")
-    wl = synth.by_name(args.pruned_workload)
+    wl = synth.by_name(args.pruned_workload, with_target=True)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     mean, chol, color, opacity = t(wl.mean), t(wl.chol), t(wl.color), t(wl.opacity)
     imgs = [(im.lr_h, im.lr_w, im.scale, im.g_begin, im.g_count) for im in wl.images]
@@ -285,7 +285,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     log("workload", args.workload)
-    wl = synth.by_name(args.workload)
+    wl = synth.by_name(args.workload, with_target=True)
     if wl.target is None:
         raise SystemExit("workload has no target")
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)

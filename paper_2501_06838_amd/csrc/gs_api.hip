@@ -105,6 +105,9 @@ gs_status make_layout(const gs_config* cfg, const gs_image* images, int32_t n_im
     l.off_tile_cnt = off; off = align_up(off + sizeof(int32_t) * (size_t)tiles);
     l.off_moments = off; off = align_up(off + sizeof(float) * 8 * (size_t)n_gauss);
     l.off_tile_loss = off; off = align_up(off + sizeof(double) * (size_t)tiles);
+    l.off_loss_parts = off;
+    off = align_up(off + sizeof(double) * (size_t)std::max<int64_t>(
+                             kLossParts, (tiles + kLossSlice - 1) / kLossSlice + 1));
     l.off_order = off; off = align_up(off + sizeof(uint32_t) * (size_t)tiles);
     l.off_order_hist = off;
     off = align_up(off + sizeof(int32_t) * ((size_t)kRadix * l.nblk_order + kRadix));

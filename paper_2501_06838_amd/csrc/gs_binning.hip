@@ -439,37 +439,50 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_sums(int64_t* __restrict_
 }
 
 // The tile ranges: [begin, end) from the exclusive scan of the counts
-// ([0, 0) for an empty tile).
+// ([0, 0) for an empty tile).  Counts are loaded and ranges stored coalesced
+// through LDS (one pad word every 32, so that a thread's kScanPer consecutive
+// entries are free of bank conflicts too).
 __global__ __launch_bounds__(kScanThreads) void k_tile_ranges(const int32_t* __restrict__ tile_cnt,
                                                               int2* __restrict__ ranges,
                                                               int64_t n_tiles,
                                                               const int64_t* __restrict__ sums,
                                                               int multi) {
+    auto lds = [](int j) { return j + (j >> 5); };
     __shared__ int64_t tmp[kScanThreads / 64];
-    __shared__ int32_t sc[kScanTile];
+    __shared__ int32_t sc[kScanTile + kScanTile / 32];
+    __shared__ int32_t s_end;
     const int64_t b0 = (int64_t)blockIdx.x * kScanTile;
-    // coalesced loads into LDS, then kScanPer consecutive counts per thread
 #pragma unroll
     for (int u = 0; u < kScanPer; ++u) {
         const int j = u * kScanThreads + threadIdx.x;
-        sc[j] = b0 + j < n_tiles ? tile_cnt[b0 + j] : 0;
+        sc[lds(j)] = b0 + j < n_tiles ? tile_cnt[b0 + j] : 0;
     }
     __syncthreads();
-    const int64_t t0 = b0 + (int64_t)threadIdx.x * kScanPer;
+    const int t0 = threadIdx.x * kScanPer;
     int c[kScanPer];
     int64_t v = 0;
 #pragma unroll
     for (int u = 0; u < kScanPer; ++u) {
-        c[u] = sc[threadIdx.x * kScanPer + u];
+        c[u] = sc[lds(t0 + u)];
         v += c[u];
     }
-    const int64_t inc = scan_block_inclusive(v, tmp);
-    int64_t b = (multi ? sums[blockIdx.x] : 0) + inc - v;
+    const int64_t inc = scan_block_inclusive(v, tmp);  // has barriers
+    int b = (int)((multi ? sums[blockIdx.x] : 0) + inc - v);
 #pragma unroll
     for (int u = 0; u < kScanPer; ++u) {
-        if (t0 + u < n_tiles)
-            ranges[t0 + u] = c[u] ? make_int2((int)b, (int)(b + c[u])) : make_int2(0, 0);
+        sc[lds(t0 + u)] = b;
         b += c[u];
+    }
+    if (threadIdx.x == kScanThreads - 1) s_end = b;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kScanPer; ++u) {
+        const int j = u * kScanThreads + threadIdx.x;
+        if (b0 + j < n_tiles) {
+            const int beg = sc[lds(j)];
+            const int end = j + 1 < kScanTile ? sc[lds(j + 1)] : s_end;
+            ranges[b0 + j] = end > beg ? make_int2(beg, end) : make_int2(0, 0);
+        }
     }
 }
 
@@ -549,20 +562,50 @@ __global__ __launch_bounds__(kBlockG) void k_place(
     }
 }
 
-// Ascending bitonic sort of one value per lane across the wave.
-__device__ __forceinline__ uint32_t wave_sort64(uint32_t v) {
+// Ascending bitonic sort of 64 K values held K per lane across the wave:
+// element i = 64 k + lane is v[k] of that lane.  Partners closer than 64 are
+// exchanged across lanes, farther ones between a lane's own registers.
+template <int K>
+__device__ __forceinline__ void wave_sort(uint32_t (&v)[K]) {
     const int lane = threadIdx.x & 63;
 #pragma unroll
-    for (int k = 2; k <= 64; k <<= 1) {
+    for (int s = 2; s <= 64 * K; s <<= 1) {
 #pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            const uint32_t p = (uint32_t)__shfl_xor((int)v, j, 64);
-            const bool up = (lane & k) == 0;
-            const bool low = (lane & j) == 0;
-            v = (low == up) ? min(v, p) : max(v, p);
+        for (int d = s >> 1; d > 0; d >>= 1) {
+            if (d >= 64) {
+                const int kd = d >> 6;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    if (k & kd) continue;
+                    const bool up = (((k << 6) | lane) & s) == 0;
+                    const uint32_t lo = min(v[k], v[k | kd]), hi = max(v[k], v[k | kd]);
+                    v[k] = up ? lo : hi;
+                    v[k | kd] = up ? hi : lo;
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const uint32_t p = (uint32_t)__shfl_xor((int)v[k], d, 64);
+                    const bool up = (((k << 6) | lane) & s) == 0;
+                    const bool low = (lane & d) == 0;
+                    v[k] = (low == up) ? min(v[k], p) : max(v[k], p);
+                }
+            }
         }
     }
-    return v;
+}
+
+// One wave sorts seg[0, n), n <= 64 K, in registers and writes it back.
+template <int K>
+__device__ __forceinline__ void wave_sort_list(uint32_t* __restrict__ seg, int n) {
+    const int lane = threadIdx.x & 63;
+    uint32_t v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = 64 * k + lane < n ? seg[64 * k + lane] : 0xffffffffu;
+    wave_sort<K>(v);
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        if (64 * k + lane < n) seg[64 * k + lane] = v[k];
 }
 
 // Number of entries of the ascending run a[0, n), n >= 1, below x.
@@ -573,73 +616,90 @@ __device__ __forceinline__ int count_below(const uint32_t* a, int n, uint32_t x)
     return lo;
 }
 
-// Sorts seg[0, n), n <= kSegLds, ascending (distinct values): each wave sorts
-// 64-entry runs into LDS, then every entry's rank is its place in its own run
-// plus the entries below it in the other runs.  Ends with a barrier.
+// Sorts seg[0, n), n <= kSegLds, ascending (distinct values) with the whole
+// workgroup: each wave sorts 256-entry runs in registers into LDS, then
+// every entry's rank is its place in its own run plus the entries below it
+// in the other runs.  Ends with a barrier.
 __device__ __forceinline__ void sort_chunk(uint32_t* __restrict__ seg, int n, uint32_t* sk) {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     constexpr int NW = kSegThreads / 64;
-    const int runs = (n + 63) >> 6;
+    const int runs = (n + 255) >> 8;
     for (int q = wave; q < runs; q += NW) {
-        const int idx = q * 64 + lane;
-        const uint32_t v = idx < n ? seg[idx] : 0xffffffffu;
-        sk[idx] = wave_sort64(v);
+        uint32_t v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int idx = q * 256 + 64 * k + lane;
+            v[k] = idx < n ? seg[idx] : 0xffffffffu;
+        }
+        wave_sort<4>(v);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) sk[q * 256 + 64 * k + lane] = v[k];
     }
     __syncthreads();
     for (int i = t; i < n; i += kSegThreads) {
         const uint32_t x = sk[i];
-        const int own = i >> 6;
-        int pos = i & 63;
+        const int own = i >> 8;
+        int pos = i & 255;
         for (int q = 0; q < runs; ++q)
-            if (q != own) pos += count_below(sk + q * 64, 64, x);
+            if (q != own) pos += count_below(sk + q * 256, 256, x);
         seg[pos] = x;
     }
     __syncthreads();
 }
 
-// One workgroup per tile: the tile's list sorted ascending.  Up to 64 ids one
-// wave sorts them in registers; up to kSegLds they go through LDS; longer
-// lists are sorted in kSegLds chunks, then merged pairwise through `spare`
-// (each entry's place: its index in its run plus the entries below it in the
-// partner run).
+// Four tiles per workgroup: each wave sorts its tile's list in registers when
+// it holds at most 256 ids; longer lists are sorted by the whole workgroup
+// afterwards: up to kSegLds through LDS, beyond that in kSegLds chunks merged
+// pairwise through `spare` (each entry's place: its index in its run plus the
+// entries below it in the partner run).
 __global__ __launch_bounds__(kSegThreads) void k_sort_lists(const int2* __restrict__ ranges,
+                                                            int64_t n_tiles,
                                                             uint32_t* __restrict__ lists,
                                                             uint32_t* __restrict__ spare) {
+    constexpr int NW = kSegThreads / 64;
     __shared__ uint32_t sk[kSegLds];
-    const int2 r = ranges[blockIdx.x];
+    __shared__ int s_long[NW];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t tile = (int64_t)blockIdx.x * NW + wave;
+    int2 r = make_int2(0, 0);
+    if (tile < n_tiles) r = ranges[tile];
     const int n = r.y - r.x;
-    if (n <= 1) return;  // uniform
-    uint32_t* seg = lists + r.x;
-    if (n <= 64) {
-        if (threadIdx.x >= 64) return;
-        const int lane = threadIdx.x;
-        const uint32_t v = wave_sort64(lane < n ? seg[lane] : 0xffffffffu);
-        if (lane < n) seg[lane] = v;
-        return;
-    }
-    if (n <= kSegLds) {
-        sort_chunk(seg, n, sk);
-        return;
-    }
-    for (int c0 = 0; c0 < n; c0 += kSegLds) sort_chunk(seg + c0, min(kSegLds, n - c0), sk);
-    uint32_t* src = seg;
-    uint32_t* dst = spare + r.x;
-    for (int64_t w = kSegLds; w < n; w *= 2) {
-        for (int i = threadIdx.x; i < n; i += kSegThreads) {
-            const uint32_t x = src[i];
-            const int64_t run = i / w, first = run * w;
-            const int64_t p0 = (run ^ 1) * w;  // partner run
-            int below = 0;
-            if (p0 < n) below = count_below(src + p0, (int)min(w, (int64_t)n - p0), x);
-            dst[min(first, p0) + (i - first) + below] = x;
+    if (n > 1 && n <= 64) wave_sort_list<1>(lists + r.x, n);
+    else if (n > 64 && n <= 128) wave_sort_list<2>(lists + r.x, n);
+    else if (n > 128 && n <= 256) wave_sort_list<4>(lists + r.x, n);
+    if (lane == 0) s_long[wave] = n > 256 ? 1 : 0;
+    __syncthreads();
+    for (int wv = 0; wv < NW; ++wv) {
+        if (!s_long[wv]) continue;  // uniform
+        const int2 rl = ranges[(int64_t)blockIdx.x * NW + wv];
+        const int nl = rl.y - rl.x;
+        uint32_t* seg = lists + rl.x;
+        if (nl <= kSegLds) {
+            sort_chunk(seg, nl, sk);
+            continue;
         }
-        __syncthreads();
-        uint32_t* sw = src;
-        src = dst;
-        dst = sw;
+        for (int c0 = 0; c0 < nl; c0 += kSegLds) sort_chunk(seg + c0, min(kSegLds, nl - c0), sk);
+        uint32_t* src = seg;
+        uint32_t* dst = spare + rl.x;
+        for (int64_t w = kSegLds; w < nl; w *= 2) {
+            for (int i = threadIdx.x; i < nl; i += kSegThreads) {
+                const uint32_t x = src[i];
+                const int64_t run = i / w, first = run * w;
+                const int64_t p0 = (run ^ 1) * w;  // partner run
+                int below = 0;
+                if (p0 < nl) below = count_below(src + p0, (int)min(w, (int64_t)nl - p0), x);
+                dst[min(first, p0) + (i - first) + below] = x;
+            }
+            __syncthreads();
+            uint32_t* sw = src;
+            src = dst;
+            dst = sw;
+        }
+        if (src != seg) {
+            for (int i = threadIdx.x; i < nl; i += kSegThreads) seg[i] = src[i];
+            __syncthreads();
+        }
     }
-    if (src != seg)
-        for (int i = threadIdx.x; i < n; i += kSegThreads) seg[i] = src[i];
 }
 
 // Sort source of the tile order: the tiles themselves, keyed by the bucket
@@ -866,8 +926,8 @@ hipError_t launch_lists(const Layout& L, const Ws& w, hipStream_t st) {
     } else {
         launch_place_t(L, w, MemTable{w.imgs}, local_scan, st);
     }
-    hipLaunchKernelGGL(k_sort_lists, dim3((unsigned)L.n_tiles), dim3(kSegThreads), 0, st,
-                       w.ranges, w.lists, w.spare);
+    hipLaunchKernelGGL(k_sort_lists, dim3((unsigned)((L.n_tiles + kSegThreads / 64 - 1) / (kSegThreads / 64))), dim3(kSegThreads), 0,
+                       st, w.ranges, L.n_tiles, w.lists, w.spare);
     return hipGetLastError();
 }
 

@@ -24,6 +24,7 @@ constexpr int kScanPer = 16;           // tiles per scan thread
 constexpr int kScanTile = kScanThreads * kScanPer;
 constexpr int kSegThreads = 256;       // per-tile list sort workgroup
 constexpr int kSegLds = 2048;          // longest list sorted in LDS in one go
+constexpr int kFinChunk = 1024;        // per-pair sums staged per gradient-kernel round
 constexpr int kEmitBins = 4096;        // widest tile window counted in LDS by one emission block
 constexpr int kPlaceScanTiles = 4096;  // up to this many tiles each placement block scans the
                                        // tile counts itself
@@ -31,7 +32,13 @@ constexpr int kPlaceScanTiles = 4096;  // up to this many tiles each placement b
 // counters and one exit counter, each on a 64-byte line of its own.
 constexpr int kSchedParts = 16;
 constexpr int kSchedStride = 16;  // words
-constexpr int kSchedWords = 2 * (kSchedParts + 1) * kSchedStride;
+constexpr int kSchedKernelWords = (kSchedParts + 1) * kSchedStride;  // per tile kernel
+// after the two kernels' counters: one line for the loss reduction's count of
+// finished workgroups
+constexpr int kLossCounterWord = 2 * kSchedKernelWords;
+constexpr int kSchedWords = 2 * kSchedKernelWords + kSchedStride;
+constexpr int kLossSlice = 4096;  // tiles per workgroup of the loss-value kernel
+constexpr int kLossParts = 64;    // workgroups of the gradient kernel that reduce the loss
 constexpr int kRadix = 1 << kRadixBits;
 
 // exp(-q/2) = exp2(-(kc z)^2) with kc = sqrt(log2(e) / 2); the render
@@ -98,7 +105,7 @@ struct Layout {
     int32_t nblk_order = 0;   // blocks of the tile-order sort
     size_t off_order = 0, off_order_hist = 0, off_sched = 0;
     size_t off_header = 0, off_imgs = 0, off_recs = 0, off_counts = 0, off_offsets = 0,
-           off_blocksums = 0, off_tile_cnt = 0, off_scan_sums = 0, off_slots = 0, off_lists = 0, off_spare = 0,
+           off_blocksums = 0, off_tile_cnt = 0, off_loss_parts = 0, off_scan_sums = 0, off_slots = 0, off_lists = 0, off_spare = 0,
            off_ranges = 0, off_moments = 0, off_tile_loss = 0, off_partials = 0, total = 0;
     const ImgDev* host_imgs = nullptr;  // host copy of the table (valid during a call)
 };
@@ -119,6 +126,7 @@ struct Ws {
     int2* ranges;        // per tile [begin, end) in lists ([0, 0) when empty)
     float* moments;
     double* tile_loss;
+    double* loss_parts;  // per workgroup of the loss reduction: its tiles' sum
     float4* partials;    // per emitted pair (emission order): 8 backward sums (2 x float4)
     uint32_t* order;     // tiles, longest list first (persistent kernels)
     int32_t* order_hist; // histograms of the tile-order sort
@@ -142,6 +150,7 @@ inline Ws bind(const Layout& L, void* base) {
     w.ranges = reinterpret_cast<int2*>(b + L.off_ranges);
     w.moments = reinterpret_cast<float*>(b + L.off_moments);
     w.tile_loss = reinterpret_cast<double*>(b + L.off_tile_loss);
+    w.loss_parts = reinterpret_cast<double*>(b + L.off_loss_parts);
     w.partials = reinterpret_cast<float4*>(b + L.off_partials);
     w.order = reinterpret_cast<uint32_t*>(b + L.off_order);
     w.order_hist = reinterpret_cast<int32_t*>(b + L.off_order_hist);

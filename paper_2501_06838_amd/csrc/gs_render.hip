@@ -655,21 +655,51 @@ __attribute__((amdgpu_waves_per_eu(BwdOccupancy<T, B>::kMinWaves, 8))) void k_re
     });
 }
 
-// One workgroup of kBlockG threads: mean of the per-tile L1 partial sums,
-// in a fixed order.
-__device__ __forceinline__ void sum_loss_block(const double* __restrict__ tile_loss,
-                                               int64_t n_tiles, double inv_numel,
-                                               double* __restrict__ loss) {
-    __shared__ double part[kBlockG / 64];
-    double s = 0.0;
-    for (int64_t t = threadIdx.x; t < n_tiles; t += kBlockG) s += tile_loss[t];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
+// Distributed L1 loss value: workgroup `part` of `nparts` sums the per-tile
+// L1 sums of tiles [lo, hi) into parts[part]; the last workgroup to finish
+// adds the nparts sums in part order and writes the mean to *loss, then
+// resets the counter.  Every order is fixed, so the value is reproducible
+// whichever workgroup finishes last.  All threads of the workgroup call it.
+__device__ __forceinline__ void loss_reduce(const double* __restrict__ tile_loss, int64_t lo,
+                                            int64_t hi, double* __restrict__ parts,
+                                            int nparts, int part, uint32_t* __restrict__ counter,
+                                            double inv_numel, double* __restrict__ loss) {
+    __shared__ double red[kBlockG / 64];
+    __shared__ int s_last;
+    auto block_sum = [&](double v) {
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+        __syncthreads();
         double sum = 0.0;
-        for (int k = 0; k < kBlockG / 64; ++k) sum += part[k];
-        *loss = sum * inv_numel;
+        for (int k = 0; k < kBlockG / 64; ++k) sum += red[k];
+        __syncthreads();
+        return sum;
+    };
+    // eight independent loads in flight per thread, combined in a fixed order
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int64_t t = lo + threadIdx.x;
+    for (; t + 7 * kBlockG < hi; t += 8 * kBlockG) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] += tile_loss[t + u * kBlockG];
+    }
+    for (; t < hi; t += kBlockG) a[0] += tile_loss[t];
+    const double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    const double bs = block_sum(s);
+    if (threadIdx.x == 0) {
+        parts[part] = bs;
+        __threadfence();  // the part is visible before it is counted
+        s_last = atomicAdd(counter, 1u) == (uint32_t)nparts - 1 ? 1 : 0;
+    }
+    __syncthreads();
+    if (!s_last) return;  // uniform
+    __threadfence();
+    const volatile double* vp = parts;
+    double t2 = 0.0;
+    for (int k = threadIdx.x; k < nparts; k += kBlockG) t2 += vp[k];
+    const double total = block_sum(t2);
+    if (threadIdx.x == 0) {
+        *loss = total * inv_numel;
+        atomicExch(counter, 0u);
     }
 }
 
@@ -691,16 +721,54 @@ __global__ __launch_bounds__(kBlockG) void k_finalize(
     int atomic_grads, float* __restrict__ grad_mean, float* __restrict__ grad_chol,
     float* __restrict__ grad_color, float* __restrict__ grad_opacity,
     const double* __restrict__ tile_loss, int64_t n_tiles, double inv_numel,
-    double* __restrict__ loss) {
-    if (loss && blockIdx.x == gridDim.x - 1) {  // the extra block: the L1 loss value
-        sum_loss_block(tile_loss, n_tiles, inv_numel, loss);
+    double* __restrict__ loss, double* __restrict__ loss_parts, uint32_t* __restrict__ counter) {
+    // with the loss, workgroups past the Gaussians' (at most kLossParts, a
+    // kLossSlice of tiles each) sum the per-tile L1 sums
+    const int64_t nbg = (n_gauss + kBlockG - 1) / kBlockG;
+    if (loss && (int64_t)blockIdx.x >= nbg) {  // uniform
+        const int64_t P = (int64_t)gridDim.x - nbg, b = (int64_t)blockIdx.x - nbg;
+        loss_reduce(tile_loss, n_tiles * b / P, n_tiles * (b + 1) / P, loss_parts, (int)P, (int)b,
+                    counter, inv_numel, loss);
         return;
     }
     const int64_t i = (int64_t)blockIdx.x * kBlockG + threadIdx.x;
+    float m[8];
+    for (int k = 0; k < 8; ++k) m[k] = 0.f;
+    if (!atomic_grads && (int64_t)blockIdx.x * kBlockG < n_gauss) {  // uniform
+        // this Gaussian's pairs, stored at their emission indices (tile
+        // row-major within the Gaussian), added in that order; the pairs at
+        // or past the capacity were never emitted.  The block's Gaussians
+        // own one contiguous span of pairs, staged through LDS in coalesced
+        // chunks.
+        __shared__ float4 sp[kFinChunk][2];
+        const int64_t g0 = (int64_t)blockIdx.x * kBlockG;
+        const int64_t gl = min(g0 + kBlockG, n_gauss) - 1;
+        const int64_t s0 = offsets[g0];
+        const int64_t s1 = min((int64_t)offsets[gl] + counts[gl], cap);
+        int64_t e0 = 0, e1 = 0;
+        if (i < n_gauss) {
+            e0 = offsets[i];
+            e1 = min(e0 + counts[i], cap);
+        }
+        for (int64_t c0 = s0; c0 < s1; c0 += kFinChunk) {  // uniform
+            const int len = (int)min((int64_t)kFinChunk, s1 - c0);
+            for (int k = threadIdx.x; k < len; k += kBlockG) {
+                sp[k][0] = partials[2 * (c0 + k)];
+                sp[k][1] = partials[2 * (c0 + k) + 1];
+            }
+            __syncthreads();
+            const int64_t a = max(e0, c0), b = min(e1, c0 + len);
+            for (int64_t e = a; e < b; ++e) {
+                const float4 u = sp[e - c0][0], v = sp[e - c0][1];
+                m[0] += u.x; m[1] += u.y; m[2] += u.z; m[3] += u.w;
+                m[4] += v.x; m[5] += v.y; m[6] += v.z; m[7] += v.w;
+            }
+            __syncthreads();
+        }
+    }
     if (i >= n_gauss) return;
     const GRec r = recs[i];
     double gm0 = 0, gm1 = 0, gl0 = 0, gl1 = 0, gl2 = 0, gc0 = 0, gc1 = 0, gc2 = 0, ga = 0;
-    float m[8];
     if (atomic_grads) {
         float4* mp = reinterpret_cast<float4*>(moments + i * 8);
         const float4 u = mp[0], v = mp[1];
@@ -708,17 +776,6 @@ __global__ __launch_bounds__(kBlockG) void k_finalize(
         m[4] = v.x; m[5] = v.y; m[6] = v.z; m[7] = v.w;
         mp[0] = make_float4(0.f, 0.f, 0.f, 0.f);  // ready for the next backward
         mp[1] = make_float4(0.f, 0.f, 0.f, 0.f);
-    } else {
-        // this Gaussian's pairs, stored at their emission indices (tile
-        // row-major within the Gaussian), added in that order; the pairs at
-        // or past the capacity were never emitted
-        for (int k = 0; k < 8; ++k) m[k] = 0.f;
-        const int64_t e0 = offsets[i], e1 = e0 + counts[i];
-        for (int64_t e = e0; e < e1 && e < cap; ++e) {
-            const float4 u = partials[2 * e], v = partials[2 * e + 1];
-            m[0] += u.x; m[1] += u.y; m[2] += u.z; m[3] += u.w;
-            m[4] += v.x; m[5] += v.y; m[6] += v.z; m[7] += v.w;
-        }
     }
     if (r.x0 <= r.x1 && r.pad == 0) {
         const double l11 = chol[3 * i], l21 = chol[3 * i + 1], l22 = chol[3 * i + 2];
@@ -775,10 +832,15 @@ __global__ __launch_bounds__(kBlockG) void k_l1(const float* __restrict__ img,
     }
 }
 
+// The L1 loss value alone: kLossSlice tiles per workgroup.
 __global__ __launch_bounds__(kBlockG) void k_sum_loss(const double* __restrict__ tile_loss,
                                                       int64_t n_tiles, double inv_numel,
-                                                      double* __restrict__ loss) {
-    sum_loss_block(tile_loss, n_tiles, inv_numel, loss);
+                                                      double* __restrict__ loss,
+                                                      double* __restrict__ parts,
+                                                      uint32_t* __restrict__ counter) {
+    const int64_t b = blockIdx.x;
+    loss_reduce(tile_loss, b * kLossSlice, min(n_tiles, (b + 1) * kLossSlice), parts,
+                (int)gridDim.x, (int)b, counter, inv_numel, loss);
 }
 
 inline int blocks_for(int64_t n, int per) { return (int)((n + per - 1) / per); }
@@ -787,8 +849,9 @@ inline int blocks_for(int64_t n, int per) { return (int)((n + per - 1) / per); }
 
 hipError_t launch_sum_loss(const Layout& L, const Ws& w, int64_t numel, double* loss,
                            hipStream_t st) {
-    hipLaunchKernelGGL(k_sum_loss, dim3(1), dim3(kBlockG), 0, st, w.tile_loss, L.n_tiles,
-                       1.0 / (double)numel, loss);
+    const int nb = std::max(1, blocks_for(L.n_tiles, kLossSlice));
+    hipLaunchKernelGGL(k_sum_loss, dim3(nb), dim3(kBlockG), 0, st, w.tile_loss, L.n_tiles,
+                       1.0 / (double)numel, loss, w.loss_parts, w.sched + kLossCounterWord);
     return hipGetLastError();
 }
 
@@ -872,7 +935,7 @@ static hipError_t launch_bwd_tt(const Layout& L, const Ws& w, const Table& tab,
                        w.lists, w.recs, w.offsets, w.ranges, grad_out, target, inv_numel, w.tile_loss, w.moments,
                        w.partials, (L.flags & GS_FLAG_ATOMIC_GRADS) ? 1 : 0, w.order, w.hdr,
                        L.n_tiles, (L.flags & GS_FLAG_PERSISTENT) ? 1 : 0,
-                       w.sched + kSchedWords / 2);
+                       w.sched + kSchedKernelWords);
     return hipGetLastError();
 }
 
@@ -937,7 +1000,7 @@ static hipError_t launch_fused_tt(const Layout& L, const Ws& w, const Table& tab
                        w.lists, w.recs, w.offsets, w.ranges, out, target, inv_numel, w.tile_loss, w.moments,
                        w.partials, (L.flags & GS_FLAG_ATOMIC_GRADS) ? 1 : 0, w.order, w.hdr,
                        L.n_tiles, (L.flags & GS_FLAG_PERSISTENT) ? 1 : 0,
-                       w.sched + kSchedWords / 2);
+                       w.sched + kSchedKernelWords);
     return hipGetLastError();
 }
 
@@ -981,12 +1044,15 @@ hipError_t launch_finalize(const Layout& L, const Ws& w, const float* chol,
                            const float* color, const float* opacity, float* grad_mean,
                            float* grad_chol, float* grad_color, float* grad_opacity,
                            hipStream_t st, int64_t numel, double* loss) {
-    const int nb = (int)blocks_for(L.n_gauss, kBlockG) + (loss ? 1 : 0);
+    const int nb_loss = std::min(kLossParts, std::max(1, blocks_for(L.n_tiles, kLossSlice)));
+    const int nb = (int)blocks_for(L.n_gauss, kBlockG) + (loss ? nb_loss : 0);
     if (nb == 0) return hipSuccess;
     hipLaunchKernelGGL(k_finalize, dim3(nb), dim3(kBlockG), 0, st, w.recs, L.n_gauss, chol,
-                       color, opacity, w.moments, w.counts, w.offsets, w.partials, L.cap, (L.flags & GS_FLAG_ATOMIC_GRADS) ? 1 : 0, grad_mean, grad_chol,
+                       color, opacity, w.moments, w.counts, w.offsets, w.partials, L.cap,
+                       (L.flags & GS_FLAG_ATOMIC_GRADS) ? 1 : 0, grad_mean, grad_chol,
                        grad_color, grad_opacity, w.tile_loss, L.n_tiles,
-                       loss ? 1.0 / (double)numel : 0.0, loss);
+                       loss ? 1.0 / (double)numel : 0.0, loss, w.loss_parts,
+                       w.sched + kLossCounterWord);
     return hipGetLastError();
 }
 

@@ -144,9 +144,9 @@ def tiny(H=5, W=6, s=2.5, seed=0, sigma=(0.6, 0.3), extra_frac=0.0, n_images=1,
                   with_target)
 
 
-def config0(seed=0):
-    """48x48 LR, one Gaussian per LR pixel, x4 -> 192x192, forward only."""
-    return _build("c0_48x48_s4", [(48, 48, 4.0)], (0.6, 0.3), 0.0, seed)
+def config0(seed=0, with_target=False):
+    """48x48 LR, one Gaussian per LR pixel, x4 -> 192x192 (forward parity case)."""
+    return _build("c0_48x48_s4", [(48, 48, 4.0)], (0.6, 0.3), 0.0, seed, with_target)
 
 
 def config1(seed=0, n_images=16):
@@ -181,9 +181,12 @@ def config3(seed=0, n_images=64, with_target=False):
                   with_target)
 
 
-def by_name(name: str, seed: int = 0) -> Workload:
-    return {"config0": config0, "config1": config1, "config2a": config2a,
-            "config2b": config2b, "config3": config3}[name](seed=seed)
+def by_name(name: str, seed: int = 0, with_target: bool = False) -> Workload:
+    """The named workload; with_target adds the L1 targets to the ones that
+    are built without (config0, config3)."""
+    if name in ("config0", "config3"):
+        return {"config0": config0, "config3": config3}[name](seed=seed, with_target=with_target)
+    return {"config1": config1, "config2a": config2a, "config2b": config2b}[name](seed=seed)
 
 
 def concat(workloads: List[Workload], name="concat") -> Workload:
