@@ -384,6 +384,26 @@ def main():
                   for name, fe, ms in (("k_render_fwd", FLOPEQ_FWD, fwd_ms),
                                        ("k_render_bwd (L1)", FLOPEQ_BWD, bwd_ms))},
     }
+    # the same step with the radix-sort binning (GS_FLAG_RADIX_SORT): same
+    # lists, bitwise; timed the same way
+    rplan = G.RasterPlan(imgs, wl.n_gauss, tile=launch["tile"], lds_batch=launch["lds_batch"],
+                         flags=launch["flags"] | G.GS_FLAG_RADIX_SORT)
+    rplan.ensure_capacity(mean, chol)
+    rws = rplan.new_workspace(dev)
+    rgraph = G.StepGraph(rplan, mean, chol, color, opacity, rws, out, target, grads, loss_acc)
+    for _ in range(args.warmup):
+        rgraph.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rgraph.launch()
+    torch.cuda.synchronize()
+    radix_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    rgraph.close()
+    del rws
+    binning = {"default": "pairs counted into their tiles, each tile's list sorted",
+               "ms_per_step": round(ms_step, 5), "radix_sort_ms_per_step": round(radix_ms, 5)}
+    log(f"radix-sort binning: {radix_ms:.4f} ms/step (counting: {ms_step:.4f})")
     pruned = None
     if not args.no_pruned:
         pruned = pruned_comparison(args, G, synth, torch, np)
@@ -410,7 +430,7 @@ def main():
                    "support_pairs": n_support,
                    "launch": "whole step captured in one HIP graph, replayed"},
         "roofline": roofline, "cpu_baseline": cpu, "surrogate_pruned": pruned,
-        "batched_uneven": batched,
+        "batched_uneven": batched, "binning": binning,
     }
     print(json.dumps(rec), flush=True)
     if args.calibration_copy > 0:

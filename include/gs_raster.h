@@ -96,6 +96,12 @@ typedef struct {
 #define GS_FLAG_ATOMIC_GRADS 0x2 /* backward: one FP32 global atomic per (tile,
                                     Gaussian, sum) instead of per-pair partial
                                     sums reduced in a fixed order (default)    */
+#define GS_FLAG_RADIX_SORT 0x4   /* binning: emit every (tile id, Gaussian id)
+                                    pair and sort them with the device LSD
+                                    radix sort (8-bit digits over the tile-id
+                                    bits) instead of counting each pair into
+                                    its tile and sorting every tile's list
+                                    (default).  Same lists, bitwise.           */
 
 /* ABI version of the loaded library (GS_ABI_VERSION). */
 int32_t gs_abi_version(void);

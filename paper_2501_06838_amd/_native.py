@@ -21,6 +21,7 @@ GS_E_WORKSPACE = -5
 
 GS_FLAG_PERSISTENT = 0x1
 GS_FLAG_ATOMIC_GRADS = 0x2
+GS_FLAG_RADIX_SORT = 0x4
 
 EXPORTED = (
     "gs_abi_version", "gs_status_string", "gs_output_size", "gs_workspace_size",

@@ -49,7 +49,8 @@ gs_status make_layout(const gs_config* cfg, const gs_image* images, int32_t n_im
                           (l.tile == 32 && (l.lds_batch == 32 || l.lds_batch == 64));
     if (!ok_batch) return GS_E_UNSUPPORTED;
     l.flags = cfg ? cfg->flags : 0;
-    if (l.flags & ~(GS_FLAG_PERSISTENT | GS_FLAG_ATOMIC_GRADS)) return GS_E_INVALID;
+    if (l.flags & ~(GS_FLAG_PERSISTENT | GS_FLAG_ATOMIC_GRADS | GS_FLAG_RADIX_SORT))
+        return GS_E_INVALID;
     l.n_img = n_img;
     l.n_gauss = n_gauss;
 
@@ -90,6 +91,12 @@ gs_status make_layout(const gs_config* cfg, const gs_image* images, int32_t n_im
     l.cap = cap;
     l.nblk_g = (int32_t)std::max<int64_t>(1, (n_gauss + kBlockG - 1) / kBlockG);
     l.nblk_scan = (int32_t)std::max<int64_t>(1, (tiles + kScanTile - 1) / kScanTile);
+    if (l.flags & GS_FLAG_RADIX_SORT) {
+        int bits = 0;
+        while (bits < 32 && ((int64_t)1 << bits) < tiles) ++bits;
+        l.n_passes = (bits + kRadixBits - 1) / kRadixBits;
+        l.nblk_sort = (int32_t)std::max<int64_t>(1, (cap + kSortTile - 1) / kSortTile);
+    }
     l.nblk_order = (int32_t)std::max<int64_t>(1, (tiles + kSortTile - 1) / kSortTile);
 
     // Capacity-independent sections first, so a small workspace can run the
@@ -116,6 +123,11 @@ gs_status make_layout(const gs_config* cfg, const gs_image* images, int32_t n_im
     l.off_slots = off; off = align_up(off + sizeof(uint32_t) * (size_t)cap);
     l.off_lists = off; off = align_up(off + sizeof(uint32_t) * (size_t)cap);
     l.off_spare = off; off = align_up(off + sizeof(uint32_t) * (size_t)cap);
+    if (l.flags & GS_FLAG_RADIX_SORT) {
+        l.off_keys1 = off; off = align_up(off + sizeof(uint32_t) * (size_t)cap);
+        l.off_hist = off;
+        off = align_up(off + sizeof(int32_t) * ((size_t)kRadix * l.nblk_sort + kRadix));
+    }
     l.off_partials = off; off = align_up(off + sizeof(float) * 8 * (size_t)cap);
     l.total = off;
     l.host_imgs = table->data();

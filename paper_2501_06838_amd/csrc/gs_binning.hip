@@ -103,7 +103,8 @@ __global__ __launch_bounds__(kBlockG) void k_support(
     const float* __restrict__ mean, const float* __restrict__ chol,
     const float* __restrict__ color, const float* __restrict__ opacity,
     const float* __restrict__ radius, GRec* __restrict__ recs, int32_t* __restrict__ counts,
-    BlockSums* __restrict__ blocksums, int32_t* __restrict__ tile_cnt, int64_t n_tiles,
+    BlockSums* __restrict__ blocksums, int32_t* __restrict__ tile_cnt,
+    int2* __restrict__ ranges_clear, int64_t n_tiles,
     float4* __restrict__ moments, uint32_t* __restrict__ sched) {
     __shared__ int64_t tmp[3][kBlockG / 64];
     const int64_t i = (int64_t)blockIdx.x * kBlockG + threadIdx.x;
@@ -113,7 +114,10 @@ __global__ __launch_bounds__(kBlockG) void k_support(
 
     if (kArgTable && blockIdx.x == 0 && threadIdx.x < n_img)
         imgs[threadIdx.x] = arg_imgs.img[threadIdx.x];
-    for (int64_t t = i; t < n_tiles; t += (int64_t)gridDim.x * kBlockG) tile_cnt[t] = 0;
+    for (int64_t t = i; t < n_tiles; t += (int64_t)gridDim.x * kBlockG) {
+        tile_cnt[t] = 0;
+        if (ranges_clear) ranges_clear[t] = make_int2(0, 0);  // radix-sort binning
+    }
 
     int cnt = 0;
     int64_t area = 0;
@@ -233,6 +237,39 @@ __global__ __launch_bounds__(kBlockG) void k_scan_blocks(BlockSums* __restrict__
     }
 }
 
+// First emission index of this block's Gaussians.  With kFold the block sums
+// the unscanned block sums below it itself, and the last block writes the
+// header totals; otherwise k_scan_blocks has done both.
+template <bool kFold>
+__device__ __forceinline__ int64_t emission_base(const BlockSums* __restrict__ bs, int nblk,
+                                                 int64_t cap, WsHeader* __restrict__ hdr) {
+    if (!kFold) return bs[blockIdx.x].pairs;
+    __shared__ int64_t t3[3][kBlockG / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int b = blockIdx.x;
+    const bool last_block = b == nblk - 1;
+    int64_t lower = 0, sup = 0, inv = 0;
+    for (int j = threadIdx.x; j < nblk; j += kBlockG) {
+        if (j < b) lower += bs[j].pairs;
+        if (last_block) { sup += bs[j].support; inv += bs[j].invalid; }
+    }
+    lower = wave_sum_i64(lower);
+    if (last_block) { sup = wave_sum_i64(sup); inv = wave_sum_i64(inv); }
+    if (lane == 0) { t3[0][wave] = lower; t3[1][wave] = sup; t3[2][wave] = inv; }
+    __syncthreads();
+    int64_t base = 0, sa = 0, sb = 0;
+    for (int k = 0; k < kBlockG / 64; ++k) { base += t3[0][k]; sa += t3[1][k]; sb += t3[2][k]; }
+    if (last_block && threadIdx.x == 0) {
+        const int64_t total = base + bs[b].pairs;
+        hdr->n_pairs = total;
+        hdr->overflow = total > cap ? 1 : 0;
+        hdr->n_support = sa;
+        hdr->n_invalid = sb;
+        hdr->ordered = 0;
+    }
+    return base;
+}
+
 // One thread per Gaussian: local exclusive scan + block offset (the
 // Gaussian's first emission index), then the Gaussian's tiles in row-major
 // order: each pair is counted into its tile (tile_cnt, cleared by the support
@@ -241,9 +278,7 @@ __global__ __launch_bounds__(kBlockG) void k_scan_blocks(BlockSums* __restrict__
 // pairs are counted in LDS first and the block adds one total per tile to the
 // global count (its place = the block's base + the LDS rank); otherwise each
 // pair takes a global atomic.  Pairs past the capacity are neither counted
-// nor placed (the overflow flag says so).  With kFold the block computes its
-// offset from the unscanned block sums itself, and the last block writes the
-// header totals (k_scan_blocks does both otherwise).
+// nor placed (the overflow flag says so).
 template <bool kFold, typename Table>
 __global__ __launch_bounds__(kBlockG) void k_emit(
     Table imgs, const GRec* __restrict__ recs, const int32_t* __restrict__ counts,
@@ -254,34 +289,7 @@ __global__ __launch_bounds__(kBlockG) void k_emit(
     __shared__ int64_t win[2][kBlockG / 64];
     __shared__ int32_t bins[kEmitBins];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int64_t base;
-    if (kFold) {
-        const int b = blockIdx.x;
-        const bool last_block = b == nblk - 1;
-        int64_t lower = 0, sup = 0, inv = 0;
-        for (int j = threadIdx.x; j < nblk; j += kBlockG) {
-            if (j < b) lower += bs[j].pairs;
-            if (last_block) { sup += bs[j].support; inv += bs[j].invalid; }
-        }
-        lower = wave_sum_i64(lower);
-        __shared__ int64_t t3[3][kBlockG / 64];
-        if (last_block) { sup = wave_sum_i64(sup); inv = wave_sum_i64(inv); }
-        if (lane == 0) { t3[0][wave] = lower; t3[1][wave] = sup; t3[2][wave] = inv; }
-        __syncthreads();
-        base = 0;
-        int64_t sa = 0, sb = 0;
-        for (int k = 0; k < kBlockG / 64; ++k) { base += t3[0][k]; sa += t3[1][k]; sb += t3[2][k]; }
-        if (last_block && threadIdx.x == 0) {
-            const int64_t total = base + bs[b].pairs;
-            hdr->n_pairs = total;
-            hdr->overflow = total > cap ? 1 : 0;
-            hdr->n_support = sa;
-            hdr->n_invalid = sb;
-            hdr->ordered = 0;
-        }
-    } else {
-        base = bs[blockIdx.x].pairs;  // scanned by k_scan_blocks
-    }
+    const int64_t base = emission_base<kFold>(bs, nblk, cap, hdr);
     const int64_t i = (int64_t)blockIdx.x * kBlockG + threadIdx.x;
     const int cnt = i < n_gauss ? counts[i] : 0;
     const int64_t inc = block_inclusive_scan((int64_t)cnt, tmp);
@@ -370,6 +378,84 @@ __global__ __launch_bounds__(kBlockG) void k_emit(
         for (int u = 0; u < 4; ++u)
             if (k0 + u < n) slots[off + k0 + u] = slot[u];
     }
+}
+
+// Radix-sort binning (GS_FLAG_RADIX_SORT).  One thread per Gaussian: the
+// Gaussian's (tile id, Gaussian id) pairs in tile row-major order at its
+// emission indices, Gaussian-major overall, so a stable sort by tile id leaves
+// every tile's Gaussians in ascending id.
+template <bool kFold, typename Table>
+__global__ __launch_bounds__(kBlockG) void k_emit_pairs(
+    Table imgs, const GRec* __restrict__ recs, const int32_t* __restrict__ counts,
+    const BlockSums* __restrict__ bs, int nblk, int64_t n_gauss, int tile, int64_t cap,
+    uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, int32_t* __restrict__ offsets,
+    WsHeader* __restrict__ hdr) {
+    __shared__ int64_t tmp[kBlockG / 64];
+    const int64_t base = emission_base<kFold>(bs, nblk, cap, hdr);
+    const int64_t i = (int64_t)blockIdx.x * kBlockG + threadIdx.x;
+    const int cnt = i < n_gauss ? counts[i] : 0;
+    const int64_t inc = block_inclusive_scan((int64_t)cnt, tmp);
+    int64_t off = base + inc - cnt;
+    if (i < n_gauss) offsets[i] = (int32_t)(off < cap ? off : cap);
+    if (cnt == 0) return;
+    const GRec r = recs[i];
+    const ImgDev& im = imgs[r.img];
+    const int tx0 = r.x0 / tile, tx1 = r.x1 / tile;
+    const int ty0 = r.y0 / tile, ty1 = r.y1 / tile;
+    for (int ty = ty0; ty <= ty1; ++ty) {
+        for (int tx = tx0; tx <= tx1; ++tx) {
+            if (off < cap) {
+                keys[off] = (uint32_t)(im.tile_base + (int64_t)ty * im.tiles_x + tx);
+                vals[off] = (uint32_t)i;
+            }
+            ++off;
+        }
+    }
+}
+
+__device__ __forceinline__ int64_t pairs_in_use(const WsHeader* hdr, int64_t cap) {
+    const int64_t p = hdr->n_pairs;
+    return p < cap ? p : cap;
+}
+
+// Sort source of the radix-sort binning: the (tile, Gaussian) pairs, keyed by
+// the 8-bit digit of the tile id at `shift`.
+struct PairDigits {
+    const uint32_t* keys;
+    const uint32_t* vals;
+    const WsHeader* hdr;
+    int64_t cap;
+    int shift;
+    __device__ __forceinline__ int64_t count() const { return pairs_in_use(hdr, cap); }
+    __device__ __forceinline__ int digit(int64_t i) const {
+        return (int)((keys[i] >> shift) & (kRadix - 1));
+    }
+    __device__ __forceinline__ void load(int64_t i, int* d, uint32_t* a, uint32_t* b) const {
+        *a = keys[i];
+        *b = vals[i];
+        *d = (int)((*a >> shift) & (kRadix - 1));
+    }
+};
+struct PairSink {
+    uint32_t* keys;
+    uint32_t* vals;
+    __device__ __forceinline__ void store(int64_t pos, uint32_t a, uint32_t b) const {
+        keys[pos] = a;
+        vals[pos] = b;
+    }
+};
+
+// One thread per sorted pair: the tile range boundaries (the ranges were
+// cleared to [0, 0) by the support kernel).
+__global__ __launch_bounds__(kBlockG) void k_ranges(const uint32_t* __restrict__ keys,
+                                                    const WsHeader* __restrict__ hdr,
+                                                    int64_t cap, int2* __restrict__ ranges) {
+    const int64_t p = (int64_t)blockIdx.x * kBlockG + threadIdx.x;
+    const int64_t P = pairs_in_use(hdr, cap);
+    if (p >= P) return;
+    const uint32_t k = keys[p];
+    if (p == 0 || keys[p - 1] != k) ranges[k].x = (int)p;
+    if (p == P - 1 || keys[p + 1] != k) ranges[k].y = (int)(p + 1);
 }
 
 // Inclusive scan of one int64 value per thread across a workgroup of
@@ -853,14 +939,17 @@ hipError_t launch_support(const Layout& L, const Ws& w, const ImgDev* host_imgs,
         }
     }
     float4* mom = reinterpret_cast<float4*>(w.moments);
+    const bool radix = (L.flags & GS_FLAG_RADIX_SORT) != 0;
     if (by_value)
         hipLaunchKernelGGL(k_support<true>, dim3(L.nblk_g), dim3(kBlockG), 0, st, chunk, w.imgs,
                            L.n_img, L.n_gauss, L.tile, mean, chol, color, opacity, radius,
-                           w.recs, w.counts, w.blocksums, w.tile_cnt, L.n_tiles, mom, w.sched);
+                           w.recs, w.counts, w.blocksums, w.tile_cnt, radix ? w.ranges : nullptr, L.n_tiles, mom,
+                           w.sched);
     else
         hipLaunchKernelGGL(k_support<false>, dim3(L.nblk_g), dim3(kBlockG), 0, st, chunk, w.imgs,
                            L.n_img, L.n_gauss, L.tile, mean, chol, color, opacity, radius,
-                           w.recs, w.counts, w.blocksums, w.tile_cnt, L.n_tiles, mom, w.sched);
+                           w.recs, w.counts, w.blocksums, w.tile_cnt, radix ? w.ranges : nullptr, L.n_tiles, mom,
+                           w.sched);
     if (count_only || L.nblk_g > kFoldScanBlocks)
         hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kBlockG), 0, st, w.blocksums, L.nblk_g,
                            L.cap, w.hdr);
@@ -869,6 +958,19 @@ hipError_t launch_support(const Layout& L, const Ws& w, const ImgDev* host_imgs,
 
 template <typename Table>
 void launch_emit_t(const Layout& L, const Ws& w, Table tab, hipStream_t st) {
+    if (L.flags & GS_FLAG_RADIX_SORT) {
+        uint32_t* keys = w.keys[0];
+        uint32_t* vals = w.vals[0];
+        if (L.nblk_g > kFoldScanBlocks)
+            hipLaunchKernelGGL((k_emit_pairs<false, Table>), dim3(L.nblk_g), dim3(kBlockG), 0, st,
+                               tab, w.recs, w.counts, w.blocksums, L.nblk_g, L.n_gauss, L.tile,
+                               L.cap, keys, vals, w.offsets, w.hdr);
+        else
+            hipLaunchKernelGGL((k_emit_pairs<true, Table>), dim3(L.nblk_g), dim3(kBlockG), 0, st,
+                               tab, w.recs, w.counts, w.blocksums, L.nblk_g, L.n_gauss, L.tile,
+                               L.cap, keys, vals, w.offsets, w.hdr);
+        return;
+    }
     if (L.nblk_g > kFoldScanBlocks)
         hipLaunchKernelGGL((k_emit<false, Table>), dim3(L.nblk_g), dim3(kBlockG), 0, st, tab,
                            w.recs, w.counts, w.blocksums, L.nblk_g, L.n_gauss, L.tile, L.cap,
@@ -902,8 +1004,30 @@ void launch_place_t(const Layout& L, const Ws& w, Table tab, bool local_scan, hi
                            L.n_tiles, w.ranges, w.slots, w.lists);
 }
 
+// Radix-sort binning: LSD passes of 8-bit digits over the tile-id bits
+// (ping-pong between the two key and value buffers; the layout puts the last
+// pass's values into the lists), then the ranges from the sorted keys.
+hipError_t launch_radix_lists(const Layout& L, const Ws& w, hipStream_t st) {
+    int32_t* totals = w.hist + (int64_t)kRadix * L.nblk_sort;
+    for (int pass = 0; pass < L.n_passes; ++pass) {
+        const int src = pass & 1, dst = src ^ 1;
+        const PairDigits in{w.keys[src], w.vals[src], w.hdr, L.cap, pass * kRadixBits};
+        const PairSink out{w.keys[dst], w.vals[dst]};
+        hipLaunchKernelGGL(k_sort_hist<PairDigits>, dim3(L.nblk_sort), dim3(kSortThreads), 0, st,
+                           in, L.nblk_sort, w.hist);
+        hipLaunchKernelGGL(k_sort_rowscan, dim3(kRadix), dim3(kBlockG), 0, st, w.hist,
+                           L.nblk_sort, totals);
+        hipLaunchKernelGGL((k_sort_scatter<PairDigits, PairSink>), dim3(L.nblk_sort),
+                           dim3(kSortThreads), 0, st, in, out, w.hist, totals, L.nblk_sort);
+    }
+    hipLaunchKernelGGL(k_ranges, dim3(blocks_for(L.cap, kBlockG)), dim3(kBlockG), 0, st,
+                       w.keys[L.n_passes & 1], w.hdr, L.cap, w.ranges);
+    return hipGetLastError();
+}
+
 hipError_t launch_lists(const Layout& L, const Ws& w, hipStream_t st) {
     if (L.n_tiles == 0) return hipSuccess;
+    if (L.flags & GS_FLAG_RADIX_SORT) return launch_radix_lists(L, w, st);
     // small batches: the placement blocks scan the counts themselves (each
     // reads all of them, so only while that stays a few MB)
     const bool local_scan = L.n_tiles <= kPlaceScanTiles &&

@@ -102,11 +102,14 @@ struct Layout {
     int64_t cap = 0;          // pair capacity
     int32_t nblk_g = 0;       // blocks of per-Gaussian kernels
     int32_t nblk_scan = 0;    // blocks of the tile-count scan
+    int32_t nblk_sort = 0;    // radix-sort binning: blocks of a pass at full capacity
+    int32_t n_passes = 0;     // radix-sort binning: passes over the tile-id bits
     int32_t nblk_order = 0;   // blocks of the tile-order sort
     size_t off_order = 0, off_order_hist = 0, off_sched = 0;
     size_t off_header = 0, off_imgs = 0, off_recs = 0, off_counts = 0, off_offsets = 0,
            off_blocksums = 0, off_tile_cnt = 0, off_loss_parts = 0, off_scan_sums = 0, off_slots = 0, off_lists = 0, off_spare = 0,
-           off_ranges = 0, off_moments = 0, off_tile_loss = 0, off_partials = 0, total = 0;
+           off_ranges = 0, off_moments = 0, off_tile_loss = 0, off_partials = 0,
+           off_keys1 = 0, off_hist = 0, total = 0;
     const ImgDev* host_imgs = nullptr;  // host copy of the table (valid during a call)
 };
 
@@ -123,6 +126,11 @@ struct Ws {
     uint32_t* slots;     // per emitted pair (emission order): its place in its tile's list
     uint32_t* lists;     // per tile, its Gaussian ids ascending (tile ranges index it)
     uint32_t* spare;     // merge buffer of the longest lists' sort
+    // radix-sort binning: ping-pong keys and values (keys[0] is slots; the
+    // values of the last pass land in lists, the other buffer is spare)
+    uint32_t* keys[2];
+    uint32_t* vals[2];
+    int32_t* hist;       // per sort block digit counts, then digit totals
     int2* ranges;        // per tile [begin, end) in lists ([0, 0) when empty)
     float* moments;
     double* tile_loss;
@@ -147,6 +155,11 @@ inline Ws bind(const Layout& L, void* base) {
     w.slots = reinterpret_cast<uint32_t*>(b + L.off_slots);
     w.lists = reinterpret_cast<uint32_t*>(b + L.off_lists);
     w.spare = reinterpret_cast<uint32_t*>(b + L.off_spare);
+    w.keys[0] = w.slots;
+    w.keys[1] = L.off_keys1 ? reinterpret_cast<uint32_t*>(b + L.off_keys1) : nullptr;
+    w.vals[L.n_passes & 1] = w.lists;
+    w.vals[(L.n_passes & 1) ^ 1] = w.spare;
+    w.hist = L.off_hist ? reinterpret_cast<int32_t*>(b + L.off_hist) : nullptr;
     w.ranges = reinterpret_cast<int2*>(b + L.off_ranges);
     w.moments = reinterpret_cast<float*>(b + L.off_moments);
     w.tile_loss = reinterpret_cast<double*>(b + L.off_tile_loss);

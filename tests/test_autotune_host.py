@@ -25,7 +25,8 @@ def test_every_candidate_is_accepted_and_others_are_not():
             ok = (tile, batch) in TILE_BATCHES
             assert (_ws(tile, batch) == N.GS_OK) == ok, (tile, batch)
         assert _ws(tile, 0) == N.GS_OK   # default batch
-    assert _ws(16, 0, 0x4) == N.GS_E_INVALID  # unknown flag bit
+    assert _ws(16, 0, 0x4) == N.GS_OK  # radix-sort binning
+    assert _ws(16, 0, 0x8) == N.GS_E_INVALID  # unknown flag bit
 
 
 def test_layout_key_depends_on_layout_and_device():

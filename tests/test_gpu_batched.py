@@ -3,9 +3,10 @@ tile order, the forward's LDS batch, graph replays of a persistent step, the
 autotuner, and the full serving-style batch (64 uneven images) against the
 FP64 oracle.
 
-The persistent flag and the LDS batch are launch choices only: the image must
-be bitwise the default launch's, and so must the gradients (the per-pair
-sums are reduced in a fixed order)."""
+The persistent flag, the LDS batch and the binning's sort (counting or
+radix) are launch choices only: the image must be bitwise the default
+launch's, and so must the gradients (the per-pair sums are reduced in a
+fixed order)."""
 import numpy as np
 import pytest
 import torch
@@ -17,6 +18,7 @@ from tests._gpu import assert_forward_close, assert_grad_close, plan_for, render
 pytestmark = pytest.mark.gpu
 
 PERSISTENT = 0x1
+RADIX = 0x4
 
 
 def _small_uneven(seed=21):
@@ -43,7 +45,7 @@ def test_persistent_and_lds_batch_are_bitwise_launch_choices(tile, batches):
     say("bitwise launch choices", tile, batches, wl.n_gauss)
     _, _, out0, g0, l0 = _step(wl, tile)
     for b in batches:
-        for flags in (0, PERSISTENT):
+        for flags in (0, PERSISTENT, RADIX, PERSISTENT | RADIX):
             say("  batch", b, "flags", flags)
             _, _, out, g, l = _step(wl, tile, b, flags)
             assert torch.equal(out, out0), (b, flags)

@@ -39,11 +39,17 @@ TILE_CASES = [
 ]
 
 
+RADIX = 0x4
+
+
+@pytest.mark.parametrize("flags", [0, RADIX], ids=["counting", "radix"])
 @pytest.mark.parametrize("name,make,tile", TILE_CASES, ids=[c[0] for c in TILE_CASES])
-def test_tile_lists_bit_exact(name, make, tile):
+def test_tile_lists_bit_exact(name, make, tile, flags):
+    """Both binnings (pairs counted into their tiles, then each list sorted;
+    or all pairs radix-sorted by tile id) give the oracle's lists exactly."""
     wl = make()
-    say("tile lists", name, "tile", tile, "n", wl.n_gauss)
-    plan, ws, _ = render(wl, tile)
+    say("tile lists", name, "tile", tile, "flags", flags, "n", wl.n_gauss)
+    plan, ws, _ = render(wl, tile, plan=plan_for(wl, tile, flags=flags))
     ranges, gids = plan.tile_lists(ws)
     r_ref, g_ref = O.tile_lists_batch(wl, tile, tile)
     assert np.array_equal(ranges, r_ref)
@@ -70,14 +76,14 @@ def test_tile_lists_with_empty_tiles(tile):
         assert_forward_close(g, r)
 
 
-@pytest.mark.parametrize("tile", [8, 16, 32])
-def test_crowded_tiles_long_lists(tile):
+@pytest.mark.parametrize("tile,flags", [(8, 0), (16, 0), (32, 0), (16, RADIX)])
+def test_crowded_tiles_long_lists(tile, flags):
     """9,036 Gaussians over a 24 x 24 HR image: tile lists of thousands of
     ids (the list sort's LDS chunks and its pairwise merges), bit-exact
     against the oracle, with the forward and the backward against it too."""
     wl = synth.tiny(H=6, W=6, s=4.0, seed=11, extra_frac=250.0, n_images=1)
-    say("crowded tiles", tile, wl.n_gauss)
-    plan, ws, out = render(wl, tile)
+    say("crowded tiles", tile, flags, wl.n_gauss)
+    plan, ws, out = render(wl, tile, plan=plan_for(wl, tile, flags=flags))
     ranges, gids = plan.tile_lists(ws)
     r_ref, g_ref = O.tile_lists_batch(wl, tile, tile)
     assert (r_ref[:, 1] - r_ref[:, 0]).max() > 4096  # two merge levels
