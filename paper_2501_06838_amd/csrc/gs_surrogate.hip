@@ -36,10 +36,27 @@ constexpr int kOffW1 = 0, kOffB1 = 512, kOffW2 = 576, kOffB2 = 4672, kOffW3 = 47
 constexpr int kMlpThreads = 256;
 
 // FP32 -> BF16 bits, round to nearest even (inputs are finite).
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// FP32 -> BF16, round to nearest even (the hardware conversion)
 __device__ __forceinline__ short bf16_bits(float x) {
-    uint32_t u = __float_as_uint(x);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (short)(u >> 16);
+    const f32x2 v = {x, 0.f};
+    const bf16x2_t b = __builtin_convertvector(v, bf16x2_t);
+    return (short)(__builtin_bit_cast(uint32_t, b) & 0xFFFFu);
+}
+// max(acc + b, 0) of a C tile as the BF16 B operand of the next layer
+__device__ __forceinline__ bf16x4 relu_bf16(f32x4 acc, const float* b) {
+    const f32x2 lo = {fmaxf(acc[0] + b[0], 0.f), fmaxf(acc[1] + b[1], 0.f)};
+    const f32x2 hi = {fmaxf(acc[2] + b[2], 0.f), fmaxf(acc[3] + b[3], 0.f)};
+    const uint32_t l = __builtin_bit_cast(uint32_t, __builtin_convertvector(lo, bf16x2_t));
+    const uint32_t h = __builtin_bit_cast(uint32_t, __builtin_convertvector(hi, bf16x2_t));
+    bf16x4 r;
+    r[0] = (short)(l & 0xFFFFu);
+    r[1] = (short)(l >> 16);
+    r[2] = (short)(h & 0xFFFFu);
+    r[3] = (short)(h >> 16);
+    return r;
 }
 __device__ __forceinline__ float bf16_value(short b) {
     return __uint_as_float(((uint32_t)(uint16_t)b) << 16);
@@ -408,6 +425,17 @@ __global__ __launch_bounds__(kRadiusThreads) void k_mlp_radius(
             b2[p][e] = params[kOffB2 + 16 * p + 4 * g + e];
         }
     const float b3 = params[kOffB3];
+    // this lane's four features' standardisation and range, in registers (an
+    // index into the by-value struct would read it from memory every tile)
+    float nmu[4], nsd[4], nlo[4], nhi[4];
+    for (int e = 0; e < 4; ++e) {
+        const int k = g < 2 ? 4 * g + e : 0;
+        nmu[e] = norm.mu[k];
+        nsd[e] = norm.sd[k];
+        nlo[e] = norm.fmin[k];
+        nhi[e] = norm.fmax[k];
+    }
+    const float margin = norm.margin;
     const int64_t wave = ((int64_t)blockIdx.x * kRadiusThreads + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * kRadiusThreads) >> 6;
     // lanes g = 0 read (l11, l21, l22, scale), lanes g = 1 (alpha, c): the raw
@@ -439,10 +467,10 @@ __global__ __launch_bounds__(kRadiusThreads) void k_mlp_radius(
             float f[4];
             if (g == 0) shape_features(rs, rv[0], rv[1], rv[2], f);
             else { f[0] = rv[0]; f[1] = rv[1]; f[2] = rv[2]; f[3] = rv[3]; }
+#pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int k = 4 * g + e;
-                const float v = standardised(f[e], k, norm);
-                inside = inside && v >= norm.fmin[k] && v <= norm.fmax[k];
+                const float v = (f[e] - nmu[e]) / nsd[e];
+                inside = inside && v >= nlo[e] && v <= nhi[e];
                 x[e] = bf16_bits(v);
             }
         } else {
@@ -452,12 +480,12 @@ __global__ __launch_bounds__(kRadiusThreads) void k_mlp_radius(
         for (int p = 0; p < 4; ++p) {
             f32x4 acc = {0.f, 0.f, 0.f, 0.f};
             acc = mfma(w1[p], x, acc);
-            for (int e = 0; e < 4; ++e) h1[p][e] = bf16_bits(fmaxf(acc[e] + b1[p][e], 0.f));
+            h1[p] = relu_bf16(acc, b1[p]);
         }
         for (int q = 0; q < 4; ++q) {
             f32x4 acc = {0.f, 0.f, 0.f, 0.f};
             for (int p = 0; p < 4; ++p) acc = mfma(w2[4 * q + p], h1[p], acc);
-            for (int e = 0; e < 4; ++e) h2[q][e] = bf16_bits(fmaxf(acc[e] + b2[q][e], 0.f));
+            h2[q] = relu_bf16(acc, b2[q]);
         }
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
         for (int q = 0; q < 4; ++q) acc = mfma(w3[q], h2[q], acc);
@@ -465,7 +493,7 @@ __global__ __launch_bounds__(kRadiusThreads) void k_mlp_radius(
         const bool in_hi = __shfl_xor((int)inside, 16, 64) != 0;  // features 4..7
         if (g == 0 && col < n) {
             float r = pred;
-            r = (inside && in_hi && isfinite(r)) ? fminf(fmaxf(r + norm.margin, 0.f), 3.f) : 3.f;
+            r = (inside && in_hi && isfinite(r)) ? fminf(fmaxf(r + margin, 0.f), 3.f) : 3.f;
             out[col] = r;
         }
     }
