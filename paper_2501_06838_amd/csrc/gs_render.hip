@@ -583,8 +583,23 @@ __device__ __forceinline__ void fused_tile(
     }
 }
 
-// One tile per workgroup (grid of n_tiles), or, with `persistent`, a grid
-// sized to the resident workgroups that walks the longest-first tile order
+// One workgroup per tile: workgroups are dealt round-robin to the 8 XCDs
+// (workgroup b runs on XCD b % 8).  Runs of kXcdRun consecutive tiles go to
+// one XCD, so neighbouring tiles of a row, which gather many of the same
+// render records, share an L2, while the runs still rotate over the XCDs
+// (heavy regions of uneven batches stay spread).  The ragged end keeps its
+// order.
+constexpr int64_t kXcds = 8;
+constexpr int64_t kXcdRun = 16;
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t n) {
+    const int64_t full = n / (kXcds * kXcdRun) * (kXcds * kXcdRun);
+    if (b >= full) return b;
+    const int64_t x = b % kXcds, k = b / kXcds;
+    return (k / kXcdRun) * (kXcds * kXcdRun) + x * kXcdRun + (k % kXcdRun);
+}
+
+// One tile per workgroup (grid of n_tiles, XCD-aware order), or, with
+// `persistent`, a grid sized to the resident workgroups that walks the longest-first tile order
 // (without a tile order from the matching binning, items are tiles).
 template <int T, int B, typename Table>
 __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_fwd(
@@ -595,7 +610,7 @@ __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_fwd(
     int persistent, uint32_t* __restrict__ sched) {
     __shared__ FwdLds<T, B> sm;
     if (!persistent) {
-        fwd_tile<T, B>(sm, imgs, n_img, svals, recs, offsets, ranges, out, (int64_t)blockIdx.x);
+        fwd_tile<T, B>(sm, imgs, n_img, svals, recs, offsets, ranges, out, xcd_tile(blockIdx.x, n_tiles));
         return;
     }
     const bool ordered = hdr->ordered != 0;
@@ -618,7 +633,7 @@ __attribute__((amdgpu_waves_per_eu(BwdOccupancy<T, B>::kMinWaves, 8))) void k_re
     __shared__ BwdLds<T, B> sm;
     if (!persistent) {
         bwd_tile<T, B, kL1>(sm, imgs, n_img, svals, recs, offsets, ranges, grad_out, target, inv_numel,
-                            tile_loss, moments, partials, atomic_grads, (int64_t)blockIdx.x);
+                            tile_loss, moments, partials, atomic_grads, xcd_tile(blockIdx.x, n_tiles));
         return;
     }
     const bool ordered = hdr->ordered != 0;
@@ -643,7 +658,7 @@ __attribute__((amdgpu_waves_per_eu(BwdOccupancy<T, B>::kMinWaves, 8))) void k_re
     __shared__ BwdLds<T, B> sm;
     if (!persistent) {
         fused_tile<T, B>(sm, imgs, n_img, svals, recs, offsets, ranges, out, target, inv_numel, tile_loss,
-                         moments, partials, atomic_grads, (int64_t)blockIdx.x);
+                         moments, partials, atomic_grads, xcd_tile(blockIdx.x, n_tiles));
         return;
     }
     const bool ordered = hdr->ordered != 0;
