@@ -174,15 +174,30 @@ def pruned_comparison(args, G, synth, torch, np):
     train the radius network on labels the exact rasterizer measures on 10k
     seeded images, then time both steps (each captured as one graph) and
     report the PSNR of the pruned render against the exact one."""
-    from paper_2501_06838_amd.surrogate import psnr
     from paper_2501_06838_amd.surrogate_train import train_radius_mlp
-    dev = torch.device("cuda:0")
     tau = 4e-3
     log("surrogate: labels from the exact rasterizer on 10k images, training")
     net, info = train_radius_mlp(lambda k: synth.surrogate_training_batch(11, k), 600, 25, tau,
                                  steps=600, lr=3e-3, quantile=0.9, coverage=0.999)
     log(f"surrogate trained: margin {info['margin']:.3f}, loss {info['losses'][-1]:.4f}")
-    wl = synth.by_name(args.pruned_workload, with_target=True)
+    out_list = []
+    names = [n.strip() for n in args.pruned_workload.split(",") if n.strip()]
+    for name in names:
+        if name not in ("config2a", "config2b"):
+            raise SystemExit(f"--pruned-workload: {name} is not config2a or config2b")
+    for name in names:
+        r = pruned_one(args, G, synth, torch, np, net, info, tau, name)
+        log(f"pruned ({name}): {r['pruned']['mp_s']} vs exact {r['exact']['mp_s']} MP/s "
+            f"({r['speedup']}x) at {r['pruned']['psnr_db']} dB")
+        out_list.append(r)
+    return out_list
+
+
+def pruned_one(args, G, synth, torch, np, net, info, tau, name):
+    """One workload of the pruned comparison with the trained network."""
+    from paper_2501_06838_amd.surrogate import psnr
+    dev = torch.device("cuda:0")
+    wl = synth.by_name(name, with_target=True)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     mean, chol, color, opacity = t(wl.mean), t(wl.chol), t(wl.color), t(wl.opacity)
     imgs = [(im.lr_h, im.lr_w, im.scale, im.g_begin, im.g_count) for im in wl.images]
@@ -221,10 +236,10 @@ def pruned_comparison(args, G, synth, torch, np):
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
             step()
-        for _ in range(3):
+        for _ in range(10):
             g.replay()
         torch.cuda.synchronize()
-        n = max(5, args.steps // 5)
+        n = max(50, args.steps)
         t0 = time.perf_counter()
         for _ in range(n):
             g.replay()
@@ -241,7 +256,7 @@ def pruned_comparison(args, G, synth, torch, np):
     for r in results.values():
         r.pop("image")
     return {
-        "workload": f"{args.pruned_workload}: {WORKLOADS[args.pruned_workload]}",
+        "workload": f"{name}: {WORKLOADS[name]}",
         "tau": tau, "exact": results["exact"], "pruned": results["pruned"],
         "speedup": round(results["exact"]["ms_per_step"] / results["pruned"]["ms_per_step"], 3),
         "closed_form_control": results["closed_form"],
@@ -265,7 +280,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pruned", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--pruned-workload", default="config2a", choices=["config2a", "config2b"])
+    ap.add_argument("--pruned-workload", default="config2a,config2b",
+                    help="comma-separated, from config2a, config2b")
     ap.add_argument("--calibration-copy", type=int, default=0, metavar="MIB",
                     help="finish with 5 plain device-to-device copies of MIB MiB (a known "
                          "byte count for scaling hardware traffic counters)")
@@ -407,8 +423,6 @@ def main():
     pruned = None
     if not args.no_pruned:
         pruned = pruned_comparison(args, G, synth, torch, np)
-        log(f"pruned: {pruned['pruned']['mp_s']} vs exact {pruned['exact']['mp_s']} MP/s "
-            f"({pruned['speedup']}x) at {pruned['pruned']['psnr_db']} dB")
     batched = None
     if not args.no_batched:
         batched = batched_uneven(args, G, synth, torch, np)
