@@ -532,12 +532,6 @@ __global__ __launch_bounds__(256) void k_sqrt_labels(const uint32_t* __restrict_
     if (i < n) R[i] = sqrtf(__uint_as_float(best[i]));
 }
 
-__global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * 256)
-        p[i] = 0u;
-}
-
 __global__ __launch_bounds__(256) void k_sq_error(const float* __restrict__ a,
                                                   const float* __restrict__ b, int64_t n,
                                                   double* __restrict__ sum) {

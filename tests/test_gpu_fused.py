@@ -73,3 +73,30 @@ def test_step_against_oracle():
     assert abs(loss.item() - ref_loss) <= 1e-12 * ref_loss
     for name, a, r in zip(("mean", "chol", "color", "opacity"), g, O.backward_batch(wl, G)):
         assert_grad_close(a.cpu().numpy(), r, name=name)
+
+
+def test_loss_reduction_repeats_bitwise():
+    """The loss value is reduced by several workgroups (36,864 tiles), the
+    last one to finish adding the partial sums and resetting the count: three
+    steps in a row and the stand-alone loss kernel give the same bits."""
+    wl = synth.config2b()
+    say("loss repeats", wl.n_gauss)
+    plan = plan_for(wl, 16)
+    m, c, col, op = to_dev(wl)
+    plan.ensure_capacity(m, c)
+    target = plan.pack([torch.from_numpy(t) for t in wl.target]).cuda()
+    ws, out = plan.new_workspace(), plan.new_output()
+    n = wl.n_gauss
+    g = tuple(torch.empty(s, device="cuda") for s in [(n, 2), (n, 3), (n, 3), (n,)])
+    vals = []
+    for _ in range(3):
+        loss = torch.zeros((), dtype=torch.float64, device="cuda")
+        plan.step_l1(m, c, col, op, ws, out, target, g, loss=loss)
+        torch.cuda.synchronize()
+        vals.append(loss.item())
+    again = torch.zeros((), dtype=torch.float64, device="cuda")
+    plan.l1_loss_value(ws, again)
+    torch.cuda.synchronize()
+    assert vals[0] == vals[1] == vals[2]
+    assert abs(again.item() - vals[0]) <= 1e-12 * vals[0]
+    assert vals[0] > 0
