@@ -88,11 +88,11 @@ typedef struct {
 
 /* flags */
 #define GS_FLAG_PERSISTENT 0x1   /* tile kernels run persistent: a grid of as
-                                    many workgroups as fit on the device takes
-                                    tiles from device work counters, longest
-                                    list first (the binning builds that order).
-                                    Results are bitwise those of the default
-                                    one-workgroup-per-tile launch.            */
+                                    many workgroups as fit on the device walks
+                                    the tiles longest list first (the binning
+                                    builds that order) in a fixed snake
+                                    schedule.  Results are bitwise those of
+                                    the default one-workgroup-per-tile launch.*/
 #define GS_FLAG_ATOMIC_GRADS 0x2 /* backward: one FP32 global atomic per (tile,
                                     Gaussian, sum) instead of per-pair partial
                                     sums reduced in a fixed order (default)    */

@@ -118,7 +118,7 @@ gs_status make_layout(const gs_config* cfg, const gs_image* images, int32_t n_im
     l.off_order = off; off = align_up(off + sizeof(uint32_t) * (size_t)tiles);
     l.off_order_hist = off;
     off = align_up(off + sizeof(int32_t) * ((size_t)kRadix * l.nblk_order + kRadix));
-    l.off_sched = off; off = align_up(off + sizeof(uint32_t) * kSchedWords);
+    l.off_counters = off; off = align_up(off + sizeof(uint32_t) * kCounterWords);
     l.off_scan_sums = off; off = align_up(off + sizeof(int64_t) * (size_t)l.nblk_scan);
     l.off_slots = off; off = align_up(off + sizeof(uint32_t) * (size_t)cap);
     l.off_lists = off; off = align_up(off + sizeof(uint32_t) * (size_t)cap);

@@ -105,12 +105,12 @@ __global__ __launch_bounds__(kBlockG) void k_support(
     const float* __restrict__ radius, GRec* __restrict__ recs, int32_t* __restrict__ counts,
     BlockSums* __restrict__ blocksums, int32_t* __restrict__ tile_cnt,
     int2* __restrict__ ranges_clear, int64_t n_tiles,
-    float4* __restrict__ moments, uint32_t* __restrict__ sched) {
+    float4* __restrict__ moments, uint32_t* __restrict__ counters) {
     __shared__ int64_t tmp[3][kBlockG / 64];
     const int64_t i = (int64_t)blockIdx.x * kBlockG + threadIdx.x;
 
     if (blockIdx.x == 0)
-        for (int k = threadIdx.x; k < kSchedWords; k += kBlockG) sched[k] = 0;
+        for (int k = threadIdx.x; k < kCounterWords; k += kBlockG) counters[k] = 0;
 
     if (kArgTable && blockIdx.x == 0 && threadIdx.x < n_img)
         imgs[threadIdx.x] = arg_imgs.img[threadIdx.x];
@@ -944,12 +944,12 @@ hipError_t launch_support(const Layout& L, const Ws& w, const ImgDev* host_imgs,
         hipLaunchKernelGGL(k_support<true>, dim3(L.nblk_g), dim3(kBlockG), 0, st, chunk, w.imgs,
                            L.n_img, L.n_gauss, L.tile, mean, chol, color, opacity, radius,
                            w.recs, w.counts, w.blocksums, w.tile_cnt, radix ? w.ranges : nullptr, L.n_tiles, mom,
-                           w.sched);
+                           w.counters);
     else
         hipLaunchKernelGGL(k_support<false>, dim3(L.nblk_g), dim3(kBlockG), 0, st, chunk, w.imgs,
                            L.n_img, L.n_gauss, L.tile, mean, chol, color, opacity, radius,
                            w.recs, w.counts, w.blocksums, w.tile_cnt, radix ? w.ranges : nullptr, L.n_tiles, mom,
-                           w.sched);
+                           w.counters);
     if (count_only || L.nblk_g > kFoldScanBlocks)
         hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kBlockG), 0, st, w.blocksums, L.nblk_g,
                            L.cap, w.hdr);

@@ -28,15 +28,11 @@ constexpr int kFinChunk = 1024;        // per-pair sums staged per gradient-kern
 constexpr int kEmitBins = 4096;        // widest tile window counted in LDS by one emission block
 constexpr int kPlaceScanTiles = 4096;  // up to this many tiles each placement block scans the
                                        // tile counts itself
-// Persistent tile kernels: per kernel (forward, backward) kSchedParts work
-// counters and one exit counter, each on a 64-byte line of its own.
-constexpr int kSchedParts = 16;
-constexpr int kSchedStride = 16;  // words
-constexpr int kSchedKernelWords = (kSchedParts + 1) * kSchedStride;  // per tile kernel
-// after the two kernels' counters: one line for the loss reduction's count of
-// finished workgroups
-constexpr int kLossCounterWord = 2 * kSchedKernelWords;
-constexpr int kSchedWords = 2 * kSchedKernelWords + kSchedStride;
+// Device counters (one 64-byte line each), zeroed by every binning: the
+// loss reduction's count of finished workgroups.
+constexpr int kCounterStride = 16;  // words
+constexpr int kLossCounterWord = 0;
+constexpr int kCounterWords = kCounterStride;
 constexpr int kLossSlice = 4096;  // tiles per workgroup of the loss-value kernel
 constexpr int kLossParts = 64;    // workgroups of the gradient kernel that reduce the loss
 constexpr int kRadix = 1 << kRadixBits;
@@ -105,7 +101,7 @@ struct Layout {
     int32_t nblk_sort = 0;    // radix-sort binning: blocks of a pass at full capacity
     int32_t n_passes = 0;     // radix-sort binning: passes over the tile-id bits
     int32_t nblk_order = 0;   // blocks of the tile-order sort
-    size_t off_order = 0, off_order_hist = 0, off_sched = 0;
+    size_t off_order = 0, off_order_hist = 0, off_counters = 0;
     size_t off_header = 0, off_imgs = 0, off_recs = 0, off_counts = 0, off_offsets = 0,
            off_blocksums = 0, off_tile_cnt = 0, off_loss_parts = 0, off_scan_sums = 0, off_slots = 0, off_lists = 0, off_spare = 0,
            off_ranges = 0, off_moments = 0, off_tile_loss = 0, off_partials = 0,
@@ -138,7 +134,7 @@ struct Ws {
     float4* partials;    // per emitted pair (emission order): 8 backward sums (2 x float4)
     uint32_t* order;     // tiles, longest list first (persistent kernels)
     int32_t* order_hist; // histograms of the tile-order sort
-    uint32_t* sched;     // persistent-kernel counters (kSchedWords, zeroed by the binning)
+    uint32_t* counters;  // device counters (kCounterWords, zeroed by the binning)
 };
 
 inline Ws bind(const Layout& L, void* base) {
@@ -167,7 +163,7 @@ inline Ws bind(const Layout& L, void* base) {
     w.partials = reinterpret_cast<float4*>(b + L.off_partials);
     w.order = reinterpret_cast<uint32_t*>(b + L.off_order);
     w.order_hist = reinterpret_cast<int32_t*>(b + L.off_order_hist);
-    w.sched = reinterpret_cast<uint32_t*>(b + L.off_sched);
+    w.counters = reinterpret_cast<uint32_t*>(b + L.off_counters);
     return w;
 }
 

@@ -62,45 +62,21 @@ struct BwdOccupancy {
     static constexpr int kMinWaves = (T == 16 && B == 64) ? 6 : 1;
 };
 
-// Persistent tile kernels.  The items (the longest-first tile order) are
-// dealt round-robin to K = min(16, grid) partitions, item i to partition
-// i % K, whose workgroups are p, p + K, p + 2K, ...  A workgroup's first item
-// in its partition is fixed by its index; later ones come from the
-// partition's own counter (a line of its own, so the atomics of different
-// partitions do not queue on one address), and the ticket for the item after
-// next is taken while the current one is processed, which hides the atomic's
-// latency.  Every workgroup leaves once its partition is exhausted; the last
-// one to leave resets the counters for the next launch.
+// Persistent tile kernels: a grid of the resident workgroups walks the items
+// (the longest-first tile order) in a fixed snake schedule: round r gives
+// item r G + b to workgroup b on even rounds and r G + G - 1 - b on odd ones,
+// so every workgroup's share alternates long and short lists (the static
+// longest-processing-time heuristic).  No counters: work queues taken with
+// same-address atomics serialise across the XCDs (about one atomic per 100 ns
+// per address here), which cost more than the tiles' imbalance.
 template <typename Body>
-__device__ __forceinline__ void run_persistent(uint32_t* ctrs, int64_t n_items, Body body) {
-    __shared__ uint32_t s_n;
-    const int G = (int)gridDim.x;
-    const int K = G < kSchedParts ? G : kSchedParts;
-    const int p = (int)blockIdx.x % K;
-    const int Gp = (G - p + K - 1) / K;  // workgroups of partition p
-    uint32_t* ctr = ctrs + kSchedStride * p;
-    uint32_t ticket = 0;
-    if (threadIdx.x == 0) ticket = atomicAdd(ctr, 1u);  // for the second item
-    int64_t n = (int64_t)blockIdx.x / K;
-    for (;;) {
-        const int64_t item = (int64_t)p + n * K;
+__device__ __forceinline__ void run_persistent(int64_t n_items, Body body) {
+    const int64_t G = gridDim.x, b = blockIdx.x;
+    for (int64_t r = 0;; ++r) {
+        const int64_t item = r * G + ((r & 1) ? G - 1 - b : b);
         if (item >= n_items) break;  // uniform
         body(item);
-        __syncthreads();  // every thread is done with s_n
-        if (threadIdx.x == 0) {
-            s_n = (uint32_t)Gp + ticket;
-            ticket = atomicAdd(ctr, 1u);
-        }
-        __syncthreads();
-        n = (int64_t)s_n;
-    }
-    if (threadIdx.x == 0) {
-        __threadfence();  // this workgroup's tickets are taken
-        uint32_t* exited = ctrs + kSchedStride * kSchedParts;
-        if (atomicAdd(exited, 1u) == (uint32_t)G - 1) {
-            for (int k = 0; k < K; ++k) atomicExch(ctrs + kSchedStride * k, 0u);
-            atomicExch(exited, 0u);
-        }
+        __syncthreads();  // the LDS is reused by the next item
     }
 }
 
@@ -607,14 +583,14 @@ __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_fwd(
     const int32_t* __restrict__ offsets,
     const int2* __restrict__ ranges, float* __restrict__ out,
     const uint32_t* __restrict__ order, const WsHeader* __restrict__ hdr, int64_t n_tiles,
-    int persistent, uint32_t* __restrict__ sched) {
+    int persistent) {
     __shared__ FwdLds<T, B> sm;
     if (!persistent) {
         fwd_tile<T, B>(sm, imgs, n_img, svals, recs, offsets, ranges, out, xcd_tile(blockIdx.x, n_tiles));
         return;
     }
     const bool ordered = hdr->ordered != 0;
-    run_persistent(sched, n_tiles, [&](int64_t item) {
+    run_persistent(n_tiles, [&](int64_t item) {
         const int64_t tile = ordered ? (int64_t)order[item] : item;
         if (tile < n_tiles) fwd_tile<T, B>(sm, imgs, n_img, svals, recs, offsets, ranges, out, tile);
     });
@@ -629,7 +605,7 @@ __attribute__((amdgpu_waves_per_eu(BwdOccupancy<T, B>::kMinWaves, 8))) void k_re
     const float* __restrict__ target, float inv_numel, double* __restrict__ tile_loss,
     float* __restrict__ moments, float4* __restrict__ partials, int atomic_grads,
     const uint32_t* __restrict__ order, const WsHeader* __restrict__ hdr, int64_t n_tiles,
-    int persistent, uint32_t* __restrict__ sched) {
+    int persistent) {
     __shared__ BwdLds<T, B> sm;
     if (!persistent) {
         bwd_tile<T, B, kL1>(sm, imgs, n_img, svals, recs, offsets, ranges, grad_out, target, inv_numel,
@@ -637,7 +613,7 @@ __attribute__((amdgpu_waves_per_eu(BwdOccupancy<T, B>::kMinWaves, 8))) void k_re
         return;
     }
     const bool ordered = hdr->ordered != 0;
-    run_persistent(sched, n_tiles, [&](int64_t item) {
+    run_persistent(n_tiles, [&](int64_t item) {
         const int64_t tile = ordered ? (int64_t)order[item] : item;
         if (tile < n_tiles)
             bwd_tile<T, B, kL1>(sm, imgs, n_img, svals, recs, offsets, ranges, grad_out, target, inv_numel,
@@ -654,7 +630,7 @@ __attribute__((amdgpu_waves_per_eu(BwdOccupancy<T, B>::kMinWaves, 8))) void k_re
     const float* __restrict__ target, float inv_numel, double* __restrict__ tile_loss,
     float* __restrict__ moments, float4* __restrict__ partials, int atomic_grads,
     const uint32_t* __restrict__ order, const WsHeader* __restrict__ hdr, int64_t n_tiles,
-    int persistent, uint32_t* __restrict__ sched) {
+    int persistent) {
     __shared__ BwdLds<T, B> sm;
     if (!persistent) {
         fused_tile<T, B>(sm, imgs, n_img, svals, recs, offsets, ranges, out, target, inv_numel, tile_loss,
@@ -662,7 +638,7 @@ __attribute__((amdgpu_waves_per_eu(BwdOccupancy<T, B>::kMinWaves, 8))) void k_re
         return;
     }
     const bool ordered = hdr->ordered != 0;
-    run_persistent(sched, n_tiles, [&](int64_t item) {
+    run_persistent(n_tiles, [&](int64_t item) {
         const int64_t tile = ordered ? (int64_t)order[item] : item;
         if (tile < n_tiles)
             fused_tile<T, B>(sm, imgs, n_img, svals, recs, offsets, ranges, out, target, inv_numel, tile_loss,
@@ -866,7 +842,7 @@ hipError_t launch_sum_loss(const Layout& L, const Ws& w, int64_t numel, double* 
                            hipStream_t st) {
     const int nb = std::max(1, blocks_for(L.n_tiles, kLossSlice));
     hipLaunchKernelGGL(k_sum_loss, dim3(nb), dim3(kBlockG), 0, st, w.tile_loss, L.n_tiles,
-                       1.0 / (double)numel, loss, w.loss_parts, w.sched + kLossCounterWord);
+                       1.0 / (double)numel, loss, w.loss_parts, w.counters + kLossCounterWord);
     return hipGetLastError();
 }
 
@@ -880,11 +856,10 @@ static hipError_t tile_grid(const Layout& L, const void* kernel, int threads, un
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0);
     if (e != hipSuccess) return e;
-    // at least 8 waves per SIMD (4 SIMDs per CU); workgroups beyond the
-    // resident ones start once others leave and find little or no work
-    const int waves = (threads + 63) / 64;
-    const int64_t per = std::max(per_cu, (32 + waves - 1) / waves);
-    const int64_t resident = (int64_t)std::max(cus, 1) * per;
+    // exactly the resident workgroups: a workgroup's first item is fixed by
+    // its index, so one that could only start once another has left would
+    // hold its item back until the end
+    const int64_t resident = (int64_t)std::max(cus, 1) * std::max(per_cu, 1);
     *grid = (unsigned)std::min<int64_t>(L.n_tiles, resident);
     return hipSuccess;
 }
@@ -899,7 +874,7 @@ static hipError_t launch_fwd_tb(const Layout& L, const Ws& w, const Table& tab, 
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(TileShape<T>::kThreads), 0, st, tab, L.n_img,
                        w.lists, w.recs, w.offsets, w.ranges, out, w.order, w.hdr, L.n_tiles,
-                       (L.flags & GS_FLAG_PERSISTENT) ? 1 : 0, w.sched);
+                       (L.flags & GS_FLAG_PERSISTENT) ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -949,8 +924,7 @@ static hipError_t launch_bwd_tt(const Layout& L, const Ws& w, const Table& tab,
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(TileShape<T>::kThreads), 0, st, tab, L.n_img,
                        w.lists, w.recs, w.offsets, w.ranges, grad_out, target, inv_numel, w.tile_loss, w.moments,
                        w.partials, (L.flags & GS_FLAG_ATOMIC_GRADS) ? 1 : 0, w.order, w.hdr,
-                       L.n_tiles, (L.flags & GS_FLAG_PERSISTENT) ? 1 : 0,
-                       w.sched + kSchedKernelWords);
+                       L.n_tiles, (L.flags & GS_FLAG_PERSISTENT) ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -1014,8 +988,7 @@ static hipError_t launch_fused_tt(const Layout& L, const Ws& w, const Table& tab
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(TileShape<T>::kThreads), 0, st, tab, L.n_img,
                        w.lists, w.recs, w.offsets, w.ranges, out, target, inv_numel, w.tile_loss, w.moments,
                        w.partials, (L.flags & GS_FLAG_ATOMIC_GRADS) ? 1 : 0, w.order, w.hdr,
-                       L.n_tiles, (L.flags & GS_FLAG_PERSISTENT) ? 1 : 0,
-                       w.sched + kSchedKernelWords);
+                       L.n_tiles, (L.flags & GS_FLAG_PERSISTENT) ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -1067,7 +1040,7 @@ hipError_t launch_finalize(const Layout& L, const Ws& w, const float* chol,
                        (L.flags & GS_FLAG_ATOMIC_GRADS) ? 1 : 0, grad_mean, grad_chol,
                        grad_color, grad_opacity, w.tile_loss, L.n_tiles,
                        loss ? 1.0 / (double)numel : 0.0, loss, w.loss_parts,
-                       w.sched + kLossCounterWord);
+                       w.counters + kLossCounterWord);
     return hipGetLastError();
 }
 

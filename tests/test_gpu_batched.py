@@ -96,9 +96,9 @@ def test_tile_order_is_longest_first():
 
 
 def test_persistent_graph_replays_match_default_launch():
-    """The persistent kernels reset their work counters themselves: several
-    replays of a captured persistent step, with eager work in between, each
-    give bitwise the default launch's image and gradients."""
+    """Several replays of a captured persistent step (and of the loss
+    reduction's counter), with eager work in between, each give bitwise the
+    default launch's image and gradients."""
     import paper_2501_06838_amd as P
     wl = synth.config3(n_images=4, with_target=True)
     plan = plan_for(wl, 16, flags=PERSISTENT)
