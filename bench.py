@@ -46,8 +46,8 @@ FLOPEQ_BWD = 48.0
 # reads 131,085 KiB (factor 2.0), WRITE_SIZE 262,144 KiB (factor 1.0).  Valid
 # only while the render sources hash to `sources`; otherwise null.
 TRAFFIC = {"workload": "config1", "launch": {"tile": 16, "lds_batch": 64, "flags": 0},
-           "sources": "4dccf7716309961f",
-           "fetch_kib": 23907.6, "write_kib": 21855.0, "fetch_factor": 2.0, "write_factor": 1.0}
+           "sources": "8943f07203eb089e",
+           "fetch_kib": 12084.7, "write_kib": 20300.4, "fetch_factor": 2.0, "write_factor": 1.0}
 TRAFFIC_SOURCES = ("paper_2501_06838_amd/csrc/gs_render.hip", "paper_2501_06838_amd/csrc/gs_internal.h")
 
 
