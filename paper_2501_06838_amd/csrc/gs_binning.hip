@@ -289,9 +289,12 @@ __global__ __launch_bounds__(kBlockG) void k_emit(
     __shared__ int64_t win[2][kBlockG / 64];
     __shared__ int32_t bins[kEmitBins];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t base = emission_base<kFold>(bs, nblk, cap, hdr);
+    // this Gaussian's count and record, read together with the block sums
     const int64_t i = (int64_t)blockIdx.x * kBlockG + threadIdx.x;
     const int cnt = i < n_gauss ? counts[i] : 0;
+    GRec r;
+    if (cnt > 0) r = recs[i];
+    const int64_t base = emission_base<kFold>(bs, nblk, cap, hdr);
     const int64_t inc = block_inclusive_scan((int64_t)cnt, tmp);
     const int64_t off = base + inc - cnt;
     if (i < n_gauss) offsets[i] = (int32_t)(off < cap ? off : cap);
@@ -300,7 +303,6 @@ __global__ __launch_bounds__(kBlockG) void k_emit(
     int n = 0, tx0 = 0, tx1 = -1, ty0 = 0, tiles_x = 0;
     int64_t tb = 0, lo = INT64_MAX, hi = -1;
     if (cnt > 0 && off < cap) {
-        const GRec r = recs[i];
         const ImgDev& im = imgs[r.img];
         tx0 = r.x0 / tile; tx1 = r.x1 / tile; ty0 = r.y0 / tile;
         const int ty1 = r.y1 / tile;
@@ -594,10 +596,17 @@ __global__ __launch_bounds__(kBlockG) void k_place(
     int cnt = 0;
     int64_t off = cap;
     GRec r;
+    uint32_t sl[4] = {0u, 0u, 0u, 0u};  // the first four slots
     if (i < n_gauss) {
         cnt = counts[i];
         off = offsets[i];
-        if (cnt > 0 && off < cap) r = recs[i];
+        if (cnt > 0 && off < cap) {
+            r = recs[i];
+            const int n4 = (int)min((int64_t)min(cnt, 4), cap - off);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (u < n4) sl[u] = slots[off + u];
+        }
     }
     if (kLocalScan) {
 #pragma unroll
@@ -638,7 +647,8 @@ __global__ __launch_bounds__(kBlockG) void k_place(
             pos[u] = -1;
             if (k0 + u < n) {
                 const int64_t t = tb + (int64_t)ty * im.tiles_x + tx;
-                pos[u] = (kLocalScan ? s_off[lds((int)t)] : ranges[t].x) + (int)slots[off + k0 + u];
+                const uint32_t slot = k0 == 0 ? sl[u] : slots[off + k0 + u];
+                pos[u] = (kLocalScan ? s_off[lds((int)t)] : ranges[t].x) + (int)slot;
                 if (++tx > tx1) { tx = tx0; ++ty; }
             }
         }
