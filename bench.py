@@ -288,8 +288,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build renders on a single MI355X; "
-              "multi-GPU sharding is a design note, not a measured path.", file=sys.stderr)
+        print("bench.py measures one GPU only (--gpus 1): the library renders a batch on "
+              "a single MI355X; sharding over several GPUs is described, not measured.",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
