@@ -45,9 +45,12 @@ FLOPEQ_BWD = 48.0
 # what the same counter reads for a plain 256 MiB device copy: FETCH_SIZE
 # reads 131,085 KiB (factor 2.0), WRITE_SIZE 262,144 KiB (factor 1.0).  Valid
 # only while the render sources hash to `sources`; otherwise null.
+# The same profile's VALU counters: busy = SQ_ACTIVE_INST_VALU x 4 / 1,024
+# SIMDs / (GRBM_GUI_ACTIVE / 8 XCDs), per dispatch.
 TRAFFIC = {"workload": "config1", "launch": {"tile": 16, "lds_batch": 64, "flags": 0},
            "sources": "8943f07203eb089e",
-           "fetch_kib": 12084.7, "write_kib": 20300.4, "fetch_factor": 2.0, "write_factor": 1.0}
+           "fetch_kib": 12084.7, "write_kib": 20300.4, "fetch_factor": 2.0, "write_factor": 1.0,
+           "sq_active_inst_valu": 22768769, "grbm_gui_active": 1343075}
 TRAFFIC_SOURCES = ("paper_2501_06838_amd/csrc/gs_render.hip", "paper_2501_06838_amd/csrc/gs_internal.h")
 
 
@@ -60,12 +63,26 @@ def render_sources_hash():
     return h.hexdigest()[:16]
 
 
+def profile_valid(workload, launch):
+    T = TRAFFIC
+    return (workload == T["workload"] and launch == T["launch"]
+            and render_sources_hash() == T["sources"])
+
+
 def traffic_bytes(workload, launch):
     T = TRAFFIC
-    if (workload != T["workload"] or launch != T["launch"]
-            or render_sources_hash() != T["sources"]):
+    if not profile_valid(workload, launch):
         return None
     return round(T["fetch_kib"] * 1024 * T["fetch_factor"] + T["write_kib"] * 1024 * T["write_factor"])
+
+
+def valu_busy(workload, launch):
+    """Fraction of the SIMDs' cycles issuing VALU work in the profiled fused
+    kernel (profiles/config1_k_render_fused_valu.md), or None."""
+    T = TRAFFIC
+    if not profile_valid(workload, launch):
+        return None
+    return round(T["sq_active_inst_valu"] * 4 / 1024 / (T["grbm_gui_active"] / 8), 3)
 
 
 WORKLOADS = {
@@ -393,6 +410,7 @@ def main():
         "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
         "frac": round(fused_tflops / PEAK_FP32_VECTOR_TFLOPS, 4),
         "traffic": traffic_bytes(args.workload, launch),
+        "valu_busy": valu_busy(args.workload, launch),
         "per_launch_flopeq": n_support * (FLOPEQ_FWD + FLOPEQ_BWD),
         "avg_launch_us": round(fused_ms * 1e3, 2),
         "other": {name: {"achieved": round(tf(fe, ms), 3),
