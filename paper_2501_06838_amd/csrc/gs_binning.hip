@@ -11,6 +11,9 @@
 //              Gaussian id written to its place, then each tile's list sorted
 //              ascending (the atomics' order is arbitrary; the sorted lists
 //              are unique)
+// With GS_FLAG_RADIX_SORT the emission writes (tile id, Gaussian id) pairs
+// instead, a stable LSD radix sort orders them by tile id and the ranges are
+// read off the sorted keys: the same lists.
 //
 // The support box follows Algorithm 1's strict window test with the window
 // replaced by R standard deviations per axis, evaluated in HR pixels:
@@ -94,8 +97,8 @@ __device__ bool support_box(double s, int out_w, int out_h, double mx, double my
 
 // One thread per Gaussian: box, record, tile count; per-block sums of the
 // pair counts, in-support areas and invalid flags.  Also clears the per-tile
-// pair counts and the backward accumulators (grid-stride / per Gaussian).  With a
-// by-value image table (kArgTable, batches of at most kSetupChunk images) the
+// pair counts (and, for the radix path, the ranges), the backward
+// accumulators and the device counters.  With a by-value image table (kArgTable, batches of at most kSetupChunk images) the
 // first block also writes the table into the workspace for later kernels.
 template <bool kArgTable>
 __global__ __launch_bounds__(kBlockG) void k_support(
