@@ -98,8 +98,9 @@ __device__ bool support_box(double s, int out_w, int out_h, double mx, double my
 // One thread per Gaussian: box, record, tile count; per-block sums of the
 // pair counts, in-support areas and invalid flags.  Also clears the per-tile
 // pair counts (and, for the radix path, the ranges), the backward
-// accumulators and the device counters.  With a by-value image table (kArgTable, batches of at most kSetupChunk images) the
-// first block also writes the table into the workspace for later kernels.
+// accumulators and the device counters.  With a by-value image table
+// (kArgTable, batches of at most kSetupChunk images) the first block also
+// writes the table into the workspace for later kernels.
 template <bool kArgTable>
 __global__ __launch_bounds__(kBlockG) void k_support(
     ImgChunk arg_imgs, ImgDev* __restrict__ imgs, int n_img, int64_t n_gauss, int tile,
