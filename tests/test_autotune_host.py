@@ -57,3 +57,24 @@ def test_cache_round_trip_and_rejects_bad_entries(tmp_path):
     assert TuneCache(str(p)).get("k") is None
     p.write_text(json.dumps([1, 2]))
     assert TuneCache(str(p)).entries == {}
+
+
+def test_tile_count_limit_and_workspace_growth():
+    """2^24 tiles or more is refused (one workgroup of up to 256 threads per
+    tile must keep a dispatch under 2^32 work-items); just below is accepted;
+    the radix-sort binning needs a larger workspace than the default."""
+    from paper_2501_06838_amd import _native as N
+
+    def ws(lr, s, tile, flags=0):
+        arr = (N.gs_image * 1)(N.gs_image(lr, lr, s, 0, 1, 0))
+        cfg = N.gs_config(tile, 0, flags, 1 << 20, 0)
+        b = ctypes.c_size_t()
+        st = N.lib().gs_workspace_size(ctypes.byref(cfg), arr, 1, 1, ctypes.byref(b))
+        return st, b.value
+    # 4096 x 4096 LR at x8 -> 32768^2 HR: 4096^2 = 2^24 tiles of 8 x 8
+    assert ws(4096, 8.0, 8)[0] == N.GS_E_UNSUPPORTED
+    # the same at 16 x 16 tiles: 2^22 tiles
+    st, b0 = ws(4096, 8.0, 16)
+    assert st == N.GS_OK
+    st, b1 = ws(4096, 8.0, 16, 0x4)
+    assert st == N.GS_OK and b1 > b0
