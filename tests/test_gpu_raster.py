@@ -151,11 +151,23 @@ def test_single_isotropic_gaussian_closed_form():
 
 @pytest.mark.parametrize("which", ["config2a", "config2b"])
 def test_full_size_sampled(which):
-    """DIV2K-sized renders at full size: tile lists bit-exact, pair count
-    exact, and 3000 sampled pixels against the oracle's per-pixel sums."""
+    """DIV2K-sized training steps at full size, in the benchmark's launch
+    (gs_raster_step_l1, tile 16, default batch): tile lists bit-exact, 3000
+    sampled pixels against the oracle's per-pixel sums, the L1 loss, and the
+    gradients of 800 sampled Gaussians against the oracle (a Gaussian's
+    gradient depends only on its own parameters and the upstream gradient)."""
     wl = synth.by_name(which)
     say("full size", which, "n", wl.n_gauss)
-    plan, ws, out = render(wl, 16)
+    plan = plan_for(wl, 16)
+    m, c, col, op = to_dev(wl)
+    plan.ensure_capacity(m, c)
+    ws, out = plan.new_workspace(), plan.new_output()
+    target = plan.pack([torch.from_numpy(t) for t in wl.target]).cuda()
+    n = wl.n_gauss
+    g = tuple(torch.empty(sh, device="cuda") for sh in [(n, 2), (n, 3), (n, 3), (n,)])
+    loss = torch.zeros((), dtype=torch.float64, device="cuda")
+    plan.step_l1(m, c, col, op, ws, out, target, g, loss=loss)
+    torch.cuda.synchronize()
     im = wl.images[0]
     ranges, gids = plan.tile_lists(ws)
     r_ref, g_ref = O.tile_lists_batch(wl, 16, 16)
@@ -168,6 +180,13 @@ def test_full_size_sampled(which):
                          xs, ys)
     assert_forward_close(img[:, ys, xs], ref)
     assert np.isfinite(img).all()
+    ref_loss, G = O.l1_loss_and_grad([img], wl.target)
+    assert abs(loss.item() - ref_loss) <= 1e-12 * ref_loss
+    idx = np.sort(rng.choice(n, size=800, replace=False))
+    r = O.backward(im.lr_h, im.lr_w, im.scale, wl.mean[idx], wl.chol[idx], wl.color[idx],
+                   wl.opacity[idx], G[0])
+    for name, a, rr in zip(("mean", "chol", "color", "opacity"), g, r):
+        assert_grad_close(a.cpu().numpy()[idx], rr, name=name)
 
 
 def test_forward_deterministic_and_permutation():
