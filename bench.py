@@ -147,7 +147,7 @@ def batched_uneven(args, G, synth, torch, np):
     target = plan0.pack([t(x) for x in wl.target])
     wl.target = None
     t0 = time.perf_counter()
-    res = tune(imgs, mean, chol, color, opacity, target, reps=3, warmup=1)
+    res = tune(imgs, mean, chol, color, opacity, target, reps=5, warmup=2)
     t_tune = time.perf_counter() - t0
     best = res["config"]
     log(f"batched: autotuner picked {best} in {t_tune:.1f} s")
@@ -331,7 +331,7 @@ def main():
         tuned = None
     else:
         from paper_2501_06838_amd.autotune import tune
-        res = tune(imgs, mean, chol, color, opacity, target, reps=3, warmup=1)
+        res = tune(imgs, mean, chol, color, opacity, target, reps=5, warmup=2)
         launch = res["config"]
         tuned = [[c["config"]["tile"], c["config"]["lds_batch"], c["config"]["flags"], c["ms"]]
                  for c in res["timings"]]

@@ -26,8 +26,8 @@ from typing import Dict, List, Optional, Sequence, Tuple
 from . import _native as N
 
 # (tile, lds_batch) pairs the library accepts
-TILE_BATCHES: Tuple[Tuple[int, int], ...] = ((8, 32), (8, 64), (16, 64), (16, 128), (16, 256),
-                                             (32, 32), (32, 64))
+TILE_BATCHES: Tuple[Tuple[int, int], ...] = ((8, 32), (8, 64), (16, 56), (16, 64), (16, 128),
+                                             (16, 256), (32, 32), (32, 64))
 
 
 def candidates(persistent: Sequence[bool] = (False, True)) -> List[Dict[str, int]]:

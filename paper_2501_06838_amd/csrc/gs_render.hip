@@ -55,11 +55,13 @@ struct TileShape {
 };
 
 // Waves per SIMD the backward and fused kernels are compiled for: at 16 x 16
-// with 64 Gaussians per round the LDS fits six workgroups per CU, so the
-// register budget is held to 80 VGPRs (elsewhere the LDS limits occupancy).
+// the LDS fits six workgroups per CU with 64 Gaussians per round and seven
+// with 56, so the register budget is held to 80 or 72 VGPRs (a few values
+// spill; elsewhere the LDS limits occupancy).  Seven waves pay on long tile
+// lists, six on short ones.
 template <int T, int B>
 struct BwdOccupancy {
-    static constexpr int kMinWaves = (T == 16 && B == 64) ? 6 : 1;
+    static constexpr int kMinWaves = (T == 16 && B == 64) ? 6 : (T == 16 && B == 56) ? 7 : 1;
 };
 
 // Persistent tile kernels: a grid of the resident workgroups walks the items
@@ -888,6 +890,7 @@ static hipError_t launch_fwd_t(const Layout& L, const Ws& w, const Table& tab, f
             if (b == 64) return launch_fwd_tb<8, 64>(L, w, tab, out, st);
             break;
         case 16:
+            if (b == 56) return launch_fwd_tb<16, 56>(L, w, tab, out, st);
             if (b == 64) return launch_fwd_tb<16, 64>(L, w, tab, out, st);
             if (b == 128) return launch_fwd_tb<16, 128>(L, w, tab, out, st);
             if (b == 256) return launch_fwd_tb<16, 256>(L, w, tab, out, st);
@@ -939,6 +942,7 @@ static hipError_t launch_bwd_t(const Layout& L, const Ws& w, const Table& tab,
             if (b == 64) return launch_bwd_tt<8, 64, kL1>(L, w, tab, grad_out, target, inv_numel, st);
             break;
         case 16:
+            if (b == 56) return launch_bwd_tt<16, 56, kL1>(L, w, tab, grad_out, target, inv_numel, st);
             if (b == 64) return launch_bwd_tt<16, 64, kL1>(L, w, tab, grad_out, target, inv_numel, st);
             if (b == 128)
                 return launch_bwd_tt<16, 128, kL1>(L, w, tab, grad_out, target, inv_numel, st);
@@ -1002,6 +1006,7 @@ static hipError_t launch_fused_t(const Layout& L, const Ws& w, const Table& tab,
             if (b == 64) return launch_fused_tt<8, 64>(L, w, tab, out, target, inv_numel, st);
             break;
         case 16:
+            if (b == 56) return launch_fused_tt<16, 56>(L, w, tab, out, target, inv_numel, st);
             if (b == 64) return launch_fused_tt<16, 64>(L, w, tab, out, target, inv_numel, st);
             if (b == 128) return launch_fused_tt<16, 128>(L, w, tab, out, target, inv_numel, st);
             if (b == 256) return launch_fused_tt<16, 256>(L, w, tab, out, target, inv_numel, st);
