@@ -26,7 +26,7 @@ from typing import Dict, List, Optional, Sequence, Tuple
 from . import _native as N
 
 # (tile, lds_batch) pairs the library accepts
-TILE_BATCHES: Tuple[Tuple[int, int], ...] = ((8, 32), (8, 64), (16, 56), (16, 64), (16, 128),
+TILE_BATCHES: Tuple[Tuple[int, int], ...] = ((8, 32), (8, 64), (16, 64), (16, 96), (16, 128),
                                              (16, 256), (32, 32), (32, 64))
 
 

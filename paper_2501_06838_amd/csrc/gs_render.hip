@@ -54,14 +54,14 @@ struct TileShape {
     static constexpr int kBatch = kThreads;
 };
 
-// Waves per SIMD the backward and fused kernels are compiled for: at 16 x 16
-// the LDS fits six workgroups per CU with 64 Gaussians per round and seven
-// with 56, so the register budget is held to 80 or 72 VGPRs (a few values
-// spill; elsewhere the LDS limits occupancy).  Seven waves pay on long tile
-// lists, six on short ones.
+// Waves per SIMD the backward and fused kernels are compiled for.  They are
+// latency bound, so at 16 x 16 the register budget follows what the LDS
+// allows: eight workgroups per CU with 64 Gaussians per round (64 VGPRs),
+// seven with 96 (72 VGPRs); a few values spill, outside the pixel loops.
+// Elsewhere the compiler's own register count decides.
 template <int T, int B>
 struct BwdOccupancy {
-    static constexpr int kMinWaves = (T == 16 && B == 64) ? 6 : (T == 16 && B == 56) ? 7 : 1;
+    static constexpr int kMinWaves = (T == 16 && B == 64) ? 8 : (T == 16 && B == 96) ? 7 : 1;
 };
 
 // Persistent tile kernels: a grid of the resident workgroups walks the items
@@ -99,6 +99,7 @@ struct StageLds {
     uint4 l2[NB][B];
     int scount[NB];
     int wcount[TileShape<T>::kWaves][NB];
+    uint8_t slot[NB][B];  // staged Gaussian t's position in block j's list
 };
 
 template <int T, int B>
@@ -106,13 +107,14 @@ struct FwdLds {
     StageLds<T, B> st;
 };
 
-// Backward and fused kernels: the records, the tile's upstream gradient and
-// the per (block, staged Gaussian) sums.
+// Backward and fused kernels: the records and the tile's upstream gradient.
+// The eight sums of a (block, staged Gaussian) record overwrite its l0 and
+// l1 entries once the backward has read them (only the lane that owns a
+// record reads it), so the sums need no LDS of their own.
 template <int T, int B>
 struct BwdLds {
     StageLds<T, B> st;
     float4 gt[T * T];       // upstream gradient of the tile, {g0, g1, g2, 0}
-    float4 acc[TileShape<T>::kBlocks][B][2];
     double lpart[TileShape<T>::kWaves];
 };
 
@@ -194,6 +196,7 @@ __device__ __forceinline__ StagedMine stage_round(StageLds<T, B>& st,
             st.l1[j][pos] = make_float4(r.g, r.A[0], r.A[1], r.A[2]);
             st.l2[j][pos] = make_uint4((uint32_t)my_mask[j], (uint32_t)(my_mask[j] >> 32),
                                        (uint32_t)t, 0u);
+            st.slot[j][t] = (uint8_t)pos;
             mine.touch |= 1u << j;
         }
     }
@@ -259,8 +262,10 @@ __device__ __forceinline__ void fwd_round(const StageLds<T, B>& st,
 // loop is uniform and each lane accumulates the eight sums of its own
 // Gaussian in registers (no cross-lane reduction, no atomics).  A lane's
 // values depend only on its own record, never on which records share its
-// pass.  Each (block, staged Gaussian) writes its sums once.  Ends with a
-// barrier.
+// pass.  Each (block, staged Gaussian) writes its sums once, over the l0 and
+// l1 entries of the record it came from.  Idle lanes of the last pass read
+// entry (0, 0), which may already hold sums; their masks are zero and they
+// write nothing.  Ends with a barrier.
 template <int T, int B>
 __device__ __forceinline__ void bwd_round(BwdLds<T, B>& sm) {
     using S = TileShape<T>;
@@ -333,8 +338,9 @@ __device__ __forceinline__ void bwd_round(BwdLds<T, B>& sm) {
             }
         }
         if (active) {
-            sm.acc[j][c2.z][0] = make_float4(m0, m1, m2, m3);
-            sm.acc[j][c2.z][1] = make_float4(m4, m5, m6, m7);
+            // in place of the record this lane read (no other lane reads it)
+            sm.st.l0[j][pos] = make_float4(m0, m1, m2, m3);
+            sm.st.l1[j][pos] = make_float4(m4, m5, m6, m7);
         }
     }
     __syncthreads();
@@ -354,7 +360,8 @@ __device__ __forceinline__ void bwd_round_store(BwdLds<T, B>& sm, StagedMine min
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
             if (mine.touch & (1u << j)) {
-                const float4 a0 = sm.acc[j][t][0], a1 = sm.acc[j][t][1];
+                const int p = sm.st.slot[j][t];
+                const float4 a0 = sm.st.l0[j][p], a1 = sm.st.l1[j][p];
                 u.x += a0.x; u.y += a0.y; u.z += a0.z; u.w += a0.w;
                 v.x += a1.x; v.y += a1.y; v.z += a1.z; v.w += a1.w;
             }
@@ -890,8 +897,8 @@ static hipError_t launch_fwd_t(const Layout& L, const Ws& w, const Table& tab, f
             if (b == 64) return launch_fwd_tb<8, 64>(L, w, tab, out, st);
             break;
         case 16:
-            if (b == 56) return launch_fwd_tb<16, 56>(L, w, tab, out, st);
             if (b == 64) return launch_fwd_tb<16, 64>(L, w, tab, out, st);
+            if (b == 96) return launch_fwd_tb<16, 96>(L, w, tab, out, st);
             if (b == 128) return launch_fwd_tb<16, 128>(L, w, tab, out, st);
             if (b == 256) return launch_fwd_tb<16, 256>(L, w, tab, out, st);
             break;
@@ -942,8 +949,8 @@ static hipError_t launch_bwd_t(const Layout& L, const Ws& w, const Table& tab,
             if (b == 64) return launch_bwd_tt<8, 64, kL1>(L, w, tab, grad_out, target, inv_numel, st);
             break;
         case 16:
-            if (b == 56) return launch_bwd_tt<16, 56, kL1>(L, w, tab, grad_out, target, inv_numel, st);
             if (b == 64) return launch_bwd_tt<16, 64, kL1>(L, w, tab, grad_out, target, inv_numel, st);
+            if (b == 96) return launch_bwd_tt<16, 96, kL1>(L, w, tab, grad_out, target, inv_numel, st);
             if (b == 128)
                 return launch_bwd_tt<16, 128, kL1>(L, w, tab, grad_out, target, inv_numel, st);
             if (b == 256)
@@ -1006,8 +1013,8 @@ static hipError_t launch_fused_t(const Layout& L, const Ws& w, const Table& tab,
             if (b == 64) return launch_fused_tt<8, 64>(L, w, tab, out, target, inv_numel, st);
             break;
         case 16:
-            if (b == 56) return launch_fused_tt<16, 56>(L, w, tab, out, target, inv_numel, st);
             if (b == 64) return launch_fused_tt<16, 64>(L, w, tab, out, target, inv_numel, st);
+            if (b == 96) return launch_fused_tt<16, 96>(L, w, tab, out, target, inv_numel, st);
             if (b == 128) return launch_fused_tt<16, 128>(L, w, tab, out, target, inv_numel, st);
             if (b == 256) return launch_fused_tt<16, 256>(L, w, tab, out, target, inv_numel, st);
             break;

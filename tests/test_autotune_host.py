@@ -21,7 +21,7 @@ def test_every_candidate_is_accepted_and_others_are_not():
         assert _ws(c["tile"], c["lds_batch"], c["flags"]) == N.GS_OK, c
     assert len(candidates()) == 2 * len(TILE_BATCHES)
     for tile in (8, 16, 32):
-        for batch in (16, 32, 48, 56, 64, 128, 256, 512):
+        for batch in (16, 32, 48, 64, 96, 128, 256, 512):
             ok = (tile, batch) in TILE_BATCHES
             assert (_ws(tile, batch) == N.GS_OK) == ok, (tile, batch)
         assert _ws(tile, 0) == N.GS_OK   # default batch

@@ -21,7 +21,6 @@ CASES = [("config1x3", lambda: synth.config1(n_images=3), 16, 0),
          ("config1x3_T8", lambda: synth.config1(n_images=3), 8, 0),
          ("config1x2_T32", lambda: synth.config1(n_images=2), 32, 0),
          ("uneven_T16_B64", _uneven, 16, 64),
-         ("uneven_T16_B56", _uneven, 16, 56),
          ("uneven_T16_B256_persistent", _uneven, 16, 256),
          ("config2b_T16", lambda: synth.config2b(), 16, 0)]
 
