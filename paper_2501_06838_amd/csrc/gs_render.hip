@@ -55,13 +55,13 @@ struct TileShape {
 };
 
 // Waves per SIMD the backward and fused kernels are compiled for.  They are
-// latency bound, so at 16 x 16 the register budget follows what the LDS
-// allows: eight workgroups per CU with 64 Gaussians per round (64 VGPRs),
-// seven with 96 (72 VGPRs); a few values spill, outside the pixel loops.
-// Elsewhere the compiler's own register count decides.
+// latency bound, so at 16 x 16 with 64 or 96 Gaussians per round, where the
+// LDS fits eight workgroups per CU, the register budget is held to 64 VGPRs
+// (a few values spill, outside the pixel loops).  Elsewhere the compiler's
+// own register count decides.
 template <int T, int B>
 struct BwdOccupancy {
-    static constexpr int kMinWaves = (T == 16 && B == 64) ? 8 : (T == 16 && B == 96) ? 7 : 1;
+    static constexpr int kMinWaves = (T == 16 && (B == 64 || B == 96)) ? 8 : 1;
 };
 
 // Persistent tile kernels: a grid of the resident workgroups walks the items
@@ -84,19 +84,18 @@ __device__ __forceinline__ void run_persistent(int64_t n_items, Body body) {
 
 // Gaussians staged per round (lds_batch).  Per 8x8 block of the tile the
 // staged Gaussians touching it are compacted, in staged (ascending Gaussian)
-// order, into a list of 48-byte records:
+// order, into a list of 40-byte records:
 //   l0 = {z1, z2 at the block's first pixel, a, e}
 //   l1 = {g, A0, A1, A2}
-//   l2 = {pixel mask lo, pixel mask hi, staged index, -}
-// (equal strides: one address register walks all three).  For the block's
-// pixel (dx, dy): z1 = z1_0 + a dx, z2 = z2_0 + e dy - g dx, and the
+//   l2 = {pixel mask lo, pixel mask hi}.
+// For the block's pixel (dx, dy): z1 = z1_0 + a dx, z2 = z2_0 + e dy - g dx, and the
 // Gaussian's contribution is A_c exp2(-(z1^2 + z2^2)) where the mask is set.
 template <int T, int B>
 struct StageLds {
     static constexpr int NB = TileShape<T>::kBlocks;
     float4 l0[NB][B];
     float4 l1[NB][B];
-    uint4 l2[NB][B];
+    uint2 l2[NB][B];
     int scount[NB];
     int wcount[TileShape<T>::kWaves][NB];
     uint8_t slot[NB][B];  // staged Gaussian t's position in block j's list
@@ -194,8 +193,7 @@ __device__ __forceinline__ StagedMine stage_round(StageLds<T, B>& st,
             const float Yb = (kyr + (float)by) - r.fy;
             st.l0[j][pos] = make_float4(r.a * Xb, r.e * Yb - r.g * Xb, r.a, r.e);
             st.l1[j][pos] = make_float4(r.g, r.A[0], r.A[1], r.A[2]);
-            st.l2[j][pos] = make_uint4((uint32_t)my_mask[j], (uint32_t)(my_mask[j] >> 32),
-                                       (uint32_t)t, 0u);
+            st.l2[j][pos] = make_uint2((uint32_t)my_mask[j], (uint32_t)(my_mask[j] >> 32));
             st.slot[j][t] = (uint8_t)pos;
             mine.touch |= 1u << j;
         }
@@ -285,7 +283,7 @@ __device__ __forceinline__ void bwd_round(BwdLds<T, B>& sm) {
         }
         if (!active) { j = 0; pos = 0; }
         const float4 c0 = sm.st.l0[j][pos], c1 = sm.st.l1[j][pos];
-        const uint4 c2 = sm.st.l2[j][pos];
+        const uint2 c2 = sm.st.l2[j][pos];
         const uint32_t mlo = active ? c2.x : 0u, mhi = active ? c2.y : 0u;
         const int bx = (j % S::kBlocksX) * 8, by = (j / S::kBlocksX) * 8;
         // block-local rows and columns the wave's boxes cover
