@@ -43,14 +43,14 @@ FLOPEQ_BWD = 48.0
 # tile 16, LDS batch 96, from two rocprofv3 --pmc passes (FETCH_SIZE,
 # WRITE_SIZE; KiB per dispatch, averaged over the dispatches), each scaled by
 # what the same counter reads for a plain 256 MiB device copy: FETCH_SIZE
-# reads 131,084.5 KiB (factor 2.0), WRITE_SIZE 262,144 KiB (factor 1.0).  Valid
+# reads 131,084.6 KiB (factor 2.0), WRITE_SIZE 262,144 KiB (factor 1.0).  Valid
 # only while the render sources hash to `sources`; otherwise null.
 # The same profile's VALU counters: busy = SQ_ACTIVE_INST_VALU x 4 / 1,024
 # SIMDs / (GRBM_GUI_ACTIVE / 8 XCDs), per dispatch.
 TRAFFIC = {"workload": "config1", "launch": {"tile": 16, "lds_batch": 96, "flags": 0},
-           "sources": "dfaccd751816ba71",
-           "fetch_kib": 11259.6, "write_kib": 17599.7, "fetch_factor": 2.0, "write_factor": 1.0,
-           "sq_active_inst_valu": 22810120, "grbm_gui_active": 1133871}
+           "sources": "3b348b0d821e0322",
+           "fetch_kib": 11269.8, "write_kib": 17600.0, "fetch_factor": 2.0, "write_factor": 1.0,
+           "sq_active_inst_valu": 22810120, "grbm_gui_active": 1133433}
 TRAFFIC_SOURCES = ("paper_2501_06838_amd/csrc/gs_render.hip", "paper_2501_06838_amd/csrc/gs_internal.h")
 
 

@@ -77,7 +77,7 @@ typedef struct {
     int32_t tile;          /* square HR tile side: 8, 16 (default) or 32     */
     int32_t lds_batch;     /* Gaussians the tile kernels stage in LDS per
                               round: tile 8: 32 or 64 (default 64); tile 16:
-                              64, 96 (default), 128 or 256; tile 32: 32
+                              64, 96 (default), 112, 128 or 256; tile 32: 32
                               (default) or 64.  Neither the image nor the
                               gradients depend on it.                        */
     int32_t flags;         /* GS_FLAG_* (other bits: GS_E_INVALID)           */

@@ -26,8 +26,24 @@ from typing import Dict, List, Optional, Sequence, Tuple
 from . import _native as N
 
 # (tile, lds_batch) pairs the library accepts
-TILE_BATCHES: Tuple[Tuple[int, int], ...] = ((8, 32), (8, 64), (16, 64), (16, 96), (16, 128),
-                                             (16, 256), (32, 32), (32, 64))
+TILE_BATCHES: Tuple[Tuple[int, int], ...] = ((8, 32), (8, 64), (16, 64), (16, 96), (16, 112),
+                                             (16, 128), (16, 256), (32, 32), (32, 64))
+
+
+# the library's own default launch (tile 16, its default LDS batch, one
+# workgroup per tile), kept unless a candidate is clearly faster
+DEFAULT_LAUNCH: Dict[str, int] = {"tile": 16, "lds_batch": 96, "flags": 0}
+
+
+def pick(timings: List[dict], margin: float = 0.02) -> dict:
+    """The fastest timing entry, except that the default launch stays when
+    no candidate beats it by more than `margin` (a fraction of its time):
+    candidates within timing noise of each other do not flip the choice."""
+    best = min(timings, key=lambda t: t["ms"])
+    dflt = next((t for t in timings if t["config"] == DEFAULT_LAUNCH), None)
+    if dflt is not None and best["ms"] > dflt["ms"] * (1.0 - margin):
+        return dflt
+    return best
 
 
 def candidates(persistent: Sequence[bool] = (False, True)) -> List[Dict[str, int]]:
@@ -126,9 +142,9 @@ def time_step(plan, mean, chol, color, opacity, target, reps: int = 3, warmup: i
 def tune(images: Sequence[Tuple[int, int, float, int, int]], mean, chol, color, opacity,
          target, reps: int = 3, warmup: int = 1,
          cands: Optional[List[Dict[str, int]]] = None, cache: Optional[TuneCache] = None,
-         force: bool = False, log=None) -> dict:
-    """Fastest configuration for this batch: {"config": {tile, lds_batch,
-    flags}, "ms": ..., "timings": [...], "cached": bool}."""
+         force: bool = False, log=None, margin: float = 0.02) -> dict:
+    """Fastest configuration for this batch (see `pick`): {"config": {tile,
+    lds_batch, flags}, "ms": ..., "timings": [...], "cached": bool}."""
     import torch
     from .raster import RasterPlan
     name = torch.cuda.get_device_name(mean.device)
@@ -145,7 +161,7 @@ def tune(images: Sequence[Tuple[int, int, float, int, int]], mean, chol, color, 
         timings.append({"config": dict(c), "ms": round(ms, 5), "pairs": pairs})
         if log:
             log(f"autotune {c}: {ms:.4f} ms, {pairs} pairs")
-    best = min(timings, key=lambda t: t["ms"])
+    best = pick(timings, margin)
     entry = {"config": best["config"], "ms": best["ms"], "timings": timings, "device": name}
     if cache is not None:
         cache.put(key, entry)

@@ -44,7 +44,7 @@ gs_status make_layout(const gs_config* cfg, const gs_image* images, int32_t n_im
     const int dflt = l.tile == 8 ? 64 : (l.tile == 16 ? 96 : 32);
     l.lds_batch = (cfg && cfg->lds_batch) ? cfg->lds_batch : dflt;
     const bool ok_batch = (l.tile == 8 && (l.lds_batch == 32 || l.lds_batch == 64)) ||
-                          (l.tile == 16 && (l.lds_batch == 64 || l.lds_batch == 96 || l.lds_batch == 128 ||
+                          (l.tile == 16 && (l.lds_batch == 64 || l.lds_batch == 96 || l.lds_batch == 112 || l.lds_batch == 128 ||
                                             l.lds_batch == 256)) ||
                           (l.tile == 32 && (l.lds_batch == 32 || l.lds_batch == 64));
     if (!ok_batch) return GS_E_UNSUPPORTED;

@@ -55,13 +55,17 @@ struct TileShape {
 };
 
 // Waves per SIMD the backward and fused kernels are compiled for.  They are
-// latency bound, so at 16 x 16 with 64 or 96 Gaussians per round, where the
-// LDS fits eight workgroups per CU, the register budget is held to 64 VGPRs
-// (a few values spill, outside the pixel loops).  Elsewhere the compiler's
-// own register count decides.
+// latency bound, so at 16 x 16 the register budget follows the workgroups
+// the LDS fits per CU: eight with 64 or 96 Gaussians per round (64 VGPRs),
+// seven with 112 (72), six with 128 (80); a few values spill, outside the
+// pixel loops.  Elsewhere the compiler's own register count decides.
 template <int T, int B>
 struct BwdOccupancy {
-    static constexpr int kMinWaves = (T == 16 && (B == 64 || B == 96)) ? 8 : 1;
+    static constexpr int kMinWaves = T != 16 ? 1
+                                   : (B == 64 || B == 96) ? 8
+                                   : B == 112             ? 7
+                                   : B == 128             ? 6
+                                                          : 1;
 };
 
 // Persistent tile kernels: a grid of the resident workgroups walks the items
@@ -897,6 +901,7 @@ static hipError_t launch_fwd_t(const Layout& L, const Ws& w, const Table& tab, f
         case 16:
             if (b == 64) return launch_fwd_tb<16, 64>(L, w, tab, out, st);
             if (b == 96) return launch_fwd_tb<16, 96>(L, w, tab, out, st);
+            if (b == 112) return launch_fwd_tb<16, 112>(L, w, tab, out, st);
             if (b == 128) return launch_fwd_tb<16, 128>(L, w, tab, out, st);
             if (b == 256) return launch_fwd_tb<16, 256>(L, w, tab, out, st);
             break;
@@ -949,6 +954,7 @@ static hipError_t launch_bwd_t(const Layout& L, const Ws& w, const Table& tab,
         case 16:
             if (b == 64) return launch_bwd_tt<16, 64, kL1>(L, w, tab, grad_out, target, inv_numel, st);
             if (b == 96) return launch_bwd_tt<16, 96, kL1>(L, w, tab, grad_out, target, inv_numel, st);
+            if (b == 112) return launch_bwd_tt<16, 112, kL1>(L, w, tab, grad_out, target, inv_numel, st);
             if (b == 128)
                 return launch_bwd_tt<16, 128, kL1>(L, w, tab, grad_out, target, inv_numel, st);
             if (b == 256)
@@ -1013,6 +1019,7 @@ static hipError_t launch_fused_t(const Layout& L, const Ws& w, const Table& tab,
         case 16:
             if (b == 64) return launch_fused_tt<16, 64>(L, w, tab, out, target, inv_numel, st);
             if (b == 96) return launch_fused_tt<16, 96>(L, w, tab, out, target, inv_numel, st);
+            if (b == 112) return launch_fused_tt<16, 112>(L, w, tab, out, target, inv_numel, st);
             if (b == 128) return launch_fused_tt<16, 128>(L, w, tab, out, target, inv_numel, st);
             if (b == 256) return launch_fused_tt<16, 256>(L, w, tab, out, target, inv_numel, st);
             break;

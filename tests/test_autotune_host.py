@@ -21,7 +21,7 @@ def test_every_candidate_is_accepted_and_others_are_not():
         assert _ws(c["tile"], c["lds_batch"], c["flags"]) == N.GS_OK, c
     assert len(candidates()) == 2 * len(TILE_BATCHES)
     for tile in (8, 16, 32):
-        for batch in (16, 32, 48, 64, 96, 128, 256, 512):
+        for batch in (16, 32, 48, 64, 96, 112, 128, 256, 512):
             ok = (tile, batch) in TILE_BATCHES
             assert (_ws(tile, batch) == N.GS_OK) == ok, (tile, batch)
         assert _ws(tile, 0) == N.GS_OK   # default batch
@@ -78,3 +78,18 @@ def test_tile_count_limit_and_workspace_growth():
     assert st == N.GS_OK
     st, b1 = ws(4096, 8.0, 16, 0x4)
     assert st == N.GS_OK and b1 > b0
+
+
+def test_pick_keeps_the_default_within_the_margin():
+    from paper_2501_06838_amd.autotune import DEFAULT_LAUNCH, pick
+    other = {"tile": 16, "lds_batch": 112, "flags": 0}
+    t = [{"config": dict(DEFAULT_LAUNCH), "ms": 1.00}, {"config": other, "ms": 0.99}]
+    assert pick(t)["config"] == DEFAULT_LAUNCH          # 1% faster: noise
+    t[1]["ms"] = 0.97
+    assert pick(t)["config"] == other                   # 3% faster: taken
+    assert pick(t, margin=0.05)["config"] == DEFAULT_LAUNCH
+    # without the default among the timings the fastest wins
+    assert pick(t[1:] + [{"config": {"tile": 8, "lds_batch": 64, "flags": 0}, "ms": 0.5}])["ms"] == 0.5
+    # the default is what the library uses for a zero batch at tile 16
+    from paper_2501_06838_amd import _native as N
+    assert _ws(16, DEFAULT_LAUNCH["lds_batch"]) == N.GS_OK

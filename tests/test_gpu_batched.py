@@ -39,7 +39,7 @@ def _step(wl, tile, lds_batch=0, flags=0):
     return plan, ws, out, grads, loss
 
 
-@pytest.mark.parametrize("tile,batches", [(8, (32, 64)), (16, (64, 96, 128, 256)), (32, (32, 64))])
+@pytest.mark.parametrize("tile,batches", [(8, (32, 64)), (16, (64, 96, 112, 128, 256)), (32, (32, 64))])
 def test_persistent_and_lds_batch_are_bitwise_launch_choices(tile, batches):
     wl = synth.config3(n_images=6, with_target=True)
     say("bitwise launch choices", tile, batches, wl.n_gauss)
