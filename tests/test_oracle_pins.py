@@ -354,3 +354,36 @@ def test_radius_support_shrinks_box():
         ref += part
     np.testing.assert_allclose(c, ref, rtol=1e-12, atol=1e-300)
     assert (c <= a + 1e-15).all()
+
+
+@pytest.mark.parametrize("s", [1.0, 2.25, 3.7])
+def test_support_pair_count_equals_brute_force_masks(s):
+    """The in-support pair count (the work figure of the roofline and the
+    n_support the GPU reports) equals the number of (pixel, Gaussian) pairs
+    that pass the per-pixel strict box test, counted over brute-force masks,
+    with Gaussians partly and wholly off the image and a per-Gaussian radius."""
+    H, W = 6, 7
+    wl = synth.tiny(H=H, W=W, s=s, seed=41, extra_frac=0.4, sigma=(0.8, 0.5))
+    mean = np.float64(wl.mean).copy()
+    chol = np.float64(wl.chol).copy()
+    chol[:2] = (1.0, 0.3, 0.9)
+    mean[0] = (-2.0, 2.0)      # box clipped at the left edge
+    mean[1] = (3.0, H + 1.0)   # box clipped at the bottom
+    mean[2] = (500.0, 3.0)     # no pixel at all
+    _, masks = brute_force(H, W, s, mean, chol, wl.color, wl.opacity)
+    rects, total = O.support_rects(H, W, s, mean, chol)
+    assert total == sum(int(m.sum()) for m in masks)
+    assert masks[2].sum() == 0 and masks[0].sum() > 0 and masks[1].sum() > 0
+    for i, m in enumerate(masks):
+        x0, x1, y0, y1 = rects[i]
+        area = max(0, x1 - x0 + 1) * max(0, y1 - y0 + 1)
+        assert area == int(m.sum()), i
+    R = np.random.default_rng(3).uniform(0.4, 3.0, wl.n_gauss)
+    _, total_r = O.support_rects(H, W, s, mean, chol, R)
+    count_r = 0
+    for i in range(wl.n_gauss):
+        _, mk = brute_force(H, W, s, mean[i:i + 1], chol[i:i + 1], wl.color[i:i + 1],
+                            wl.opacity[i:i + 1], R=R[i])
+        count_r += int(mk[0].sum())
+    assert total_r == count_r
+    assert O.support_pairs_batch(wl) == O.support_rects(H, W, s, wl.mean, wl.chol)[1]

@@ -125,3 +125,137 @@ def test_prune_radius_rules():
     R = S.prune_radius(np.array([1.0, 1.0, 3.5]), 0.2, F, np.array([-1.0, -1.0]),
                        np.array([1.0, 1.0]))
     np.testing.assert_allclose(R, [1.2, 3.0, 3.0])
+
+
+def test_features_from_constructed_covariance():
+    """The features follow from the covariance itself, not from the Cholesky
+    factor's entries: build Sigma = R(theta) diag(s1^2, s2^2) R(theta)^T in
+    FP64, read sigma_x = sqrt(Sxx), sigma_y = sqrt(Syy), rho = Sxy / (sigma_x
+    sigma_y) off it, factor it with numpy's Cholesky and feed the factor to
+    the oracle.  Includes strongly anisotropic, rotated Gaussians whose l21 is
+    far larger than l22 (where sigma_y and l22 differ most)."""
+    rng = np.random.default_rng(12)
+    n = 400
+    s1 = np.exp(rng.normal(np.log(0.8), 0.7, n))
+    s2 = np.exp(rng.normal(np.log(0.8), 0.7, n))
+    th = rng.uniform(0.0, np.pi, n)
+    s1[:40], s2[:40], th[:40] = 3.0, 0.05, np.pi / 4 + rng.uniform(-0.1, 0.1, 40)
+    scale = rng.uniform(1.5, 12.0, n)
+    color = rng.uniform(0.0, 1.0, (n, 3))
+    alpha = rng.uniform(0.5, 1.0, n)
+    chol = np.zeros((n, 3))
+    expect = np.zeros((n, 8))
+    for i in range(n):
+        c, s = math.cos(th[i]), math.sin(th[i])
+        Rm = np.array([[c, -s], [s, c]])
+        Sig = Rm @ np.diag([s1[i] ** 2, s2[i] ** 2]) @ Rm.T
+        L = np.linalg.cholesky(Sig)
+        chol[i] = (L[0, 0], L[1, 0], L[1, 1])
+        sx, sy = math.sqrt(Sig[0, 0]), math.sqrt(Sig[1, 1])
+        expect[i] = (math.log(scale[i]), math.log(sx), math.log(sy), Sig[0, 1] / (sx * sy),
+                     alpha[i], *color[i])
+    assert (np.abs(chol[:40, 1]) > 5 * chol[:40, 2]).all()
+    got = S.features(scale, chol, color, alpha)
+    np.testing.assert_allclose(got, expect, rtol=1e-12, atol=1e-12)
+
+
+# ---- BF16 rounding points of the MLP, pinned by the BF16 format itself ----
+#
+# BF16 keeps 8 significant bits: on [1, 2) its spacing is 2^-7, so 1 + 2^-9
+# (a quarter of a spacing above 1) rounds to 1, 1 + 2^-8 (a tie) rounds to
+# the even neighbour 1, and 1 + 2^-8 + 2^-9 rounds up to 1 + 2^-7.  Each case
+# below is a chain network (one live unit per layer) that puts a
+# non-representable value at exactly one rounding point.  Where a later
+# rounding follows, the next layer's bias adds 2^-8, so that the value there
+# is a tie when the earlier rounding happened (result 1) and lies above the
+# tie when it did not (result 1 + 2^-7): a missing rounding cannot be hidden
+# by the next one.  Expected results are worked out by hand from the spacing.
+
+def _chain(w1=1.0, b1=0.0, w2=1.0, b2=0.0, w3=1.0, b3=0.0):
+    d = {"W1": np.zeros((64, 8)), "b1": np.zeros(64), "W2": np.zeros((64, 64)),
+         "b2": np.zeros(64), "W3": np.zeros((1, 64)), "b3": np.zeros(1)}
+    d["W1"][0, 0], d["b1"][0], d["W2"][0, 0] = w1, b1, w2
+    d["b2"][0], d["W3"][0, 0], d["b3"][0] = b2, w3, b3
+    return S.pack(d)
+
+
+def _x(v):
+    X = np.zeros((1, 8))
+    X[0, 0] = v
+    return X
+
+
+Q = 2.0 ** -9
+T = 2.0 ** -8
+
+
+@pytest.mark.parametrize("point,params,x,rounded,exact", [
+    ("input x", _chain(b1=T), 1 + Q, 1.0, 1 + Q + T),
+    ("weight W1", _chain(w1=1 + Q, b1=T), 1.0, 1.0, 1 + Q + T),
+    ("hidden H1", _chain(b1=Q, b2=T), 1.0, 1.0, 1 + Q + T),
+    ("weight W2", _chain(w2=1 + Q, b2=T), 1.0, 1.0, 1 + Q + T),
+    ("hidden H2", _chain(b2=Q), 1.0, 1.0, 1 + Q),
+    ("weight W3", _chain(w3=1 + Q), 1.0, 1.0, 1 + Q),
+    ("output bias (not rounded)", _chain(b3=Q), 1.0, 1 + Q, 1 + Q),
+    ("tie above the midpoint", _chain(b1=T + Q), 1.0, 1 + 2 * T, 1 + T + Q),
+])
+def test_forward_rounding_points(point, params, x, rounded, exact):
+    out_r, _ = S.mlp_forward(params, _x(x), rounding=True)
+    out_e, _ = S.mlp_forward(params, _x(x), rounding=False)
+    assert out_r[0] == rounded, point
+    assert out_e[0] == exact, point
+
+
+def test_backward_rounding_points():
+    """d3 (the upstream gradient fed to the matrix cores), dZ2 and dZ1 are
+    rounded before they multiply; the bias gradients use the unrounded
+    values."""
+    P7 = 2.0 ** -7
+    # d3: dout = 1 + 2^-9 -> 1 for dW3 (H2 = 1), while db3 sums dout itself
+    params = _chain()
+    _, cache = S.mlp_forward(params, _x(1.0))
+    g = S.unpack(S.mlp_backward(cache, np.array([1 + Q])))
+    assert g["W3"][0, 0] == 1.0 and g["b3"][0] == 1 + Q
+    # dZ2 = d3b * W3b = (1 + 2^-7)^2 = 1 + 2^-6 + 2^-14 -> 1 + 2^-6 for dW2
+    # (H1 = 1); db2 keeps 2^-14; dZ1 = dZ2b * W2b = 1 + 2^-6 -> exact, so
+    # dW1 = 1 + 2^-6
+    params = _chain(w3=1 + P7)
+    _, cache = S.mlp_forward(params, _x(1.0))
+    g = S.unpack(S.mlp_backward(cache, np.array([1 + P7])))
+    assert g["W2"][0, 0] == 1 + 2 * P7
+    assert g["b2"][0] == 1 + 2 * P7 + 2.0 ** -14
+    assert g["W1"][0, 0] == 1 + 2 * P7
+    # dZ1 = dZ2b * W2b = (1 + 2^-6)(1 + 2^-7) = 1 + 3 * 2^-7 + 2^-13 -> 1 + 3 * 2^-7
+    # for dW1 (x = 1); db1 keeps 2^-13
+    params = _chain(w2=1 + P7, w3=1 + P7)
+    _, cache = S.mlp_forward(params, _x(1.0))
+    g = S.unpack(S.mlp_backward(cache, np.array([1 + P7])))
+    assert g["W1"][0, 0] == 1 + 3 * P7
+    assert g["b1"][0] == 1 + 3 * P7 + 2.0 ** -13
+    # without rounding every product keeps its low bits
+    g = S.unpack(S.mlp_backward(cache, np.array([1 + P7]), rounding=False))
+    assert g["W1"][0, 0] == (1 + P7) ** 3
+
+
+def test_rounding_is_identity_on_representable_values():
+    """Inputs, weights and every intermediate value representable in BF16
+    (small integers and powers of two): the rounded MLP equals the exact one
+    bit for bit, forward and backward."""
+    rng = np.random.default_rng(21)
+    d = {"W1": rng.integers(-1, 2, (64, 8)).astype(np.float64),
+         "b1": rng.integers(0, 3, 64).astype(np.float64),
+         "W2": np.zeros((64, 64)), "b2": rng.integers(0, 3, 64).astype(np.float64),
+         "W3": rng.integers(-1, 2, (1, 64)).astype(np.float64), "b3": np.array([0.5])}
+    for k in range(64):  # four entries per row keep |Z2| < 256
+        d["W2"][k, rng.choice(64, 4, replace=False)] = rng.choice([-1.0, 1.0], 4)
+    params = S.pack(d)
+    X = rng.integers(-2, 3, (50, 8)).astype(np.float64)
+    dout = 2.0 ** rng.integers(-12, -4, 50) * rng.choice([-1.0, 1.0], 50)
+    a, ca = S.mlp_forward(params, X, rounding=True)
+    b, cb = S.mlp_forward(params, X, rounding=False)
+    assert np.array_equal(a, b)
+    assert (np.abs(ca[2]).max() > 2) and np.array_equal(ca[2], cb[2])  # H1 nontrivial
+    ga = S.mlp_backward(ca, dout, rounding=True)
+    gb = S.mlp_backward(cb, dout, rounding=False)
+    assert np.array_equal(ga, gb)
+    assert np.abs(ga).max() > 0
