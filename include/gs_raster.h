@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define GS_ABI_VERSION 1
+#define GS_ABI_VERSION 2
 
 typedef int32_t gs_status;
 enum {
@@ -241,10 +241,10 @@ gs_status gs_raster_backward_l1(const gs_config* cfg, const gs_image* images, in
 
 /* L1 training loss (Sec. 3.2, "Rendering": rendered SR image against the HR target)
  * and its gradient: grad = sign(img - target) / numel with sign(0) = 0.
- * img, target, grad: device [numel]; loss_sum: device double, the sum of
- * |img - target| is atomically ADDED to it (zero it first to get one batch). */
+ * img, target, grad: device [numel]; loss: device double, overwritten with
+ * the mean of |img - target| (0 when numel is 0). */
 gs_status gs_l1_loss_grad(const float* img, const float* target, int64_t numel,
-                          float* grad, double* loss_sum, void* stream);
+                          float* grad, double* loss, void* stream);
 
 /* Synchronising.  Counts of the last forward in this workspace: total
  * (tile, Gaussian) pairs, overflow flag (pairs > capacity: the output of
@@ -353,10 +353,24 @@ gs_status gs_mlp_adam(float* params, float* m, float* v, const float* grad, int3
 /* Training labels from the exact rasterizer: per Gaussian, the largest
  * Mahalanobis distance over the HR pixels of its 3-sigma box whose own
  * contribution alpha max(c) f is at least tau (0 if none).  Uses the
- * workspace of a gs_raster_forward with radius NULL; radius: device [n_gauss]. */
+ * workspace of a gs_raster_bin / gs_raster_forward with radius NULL;
+ * radius: device [n_gauss].  With interior_only != 0, a Gaussian whose
+ * support box the image border cuts gets -1 instead (its label would be cut
+ * by the border too: training takes the Gaussians with labels >= 0). */
 gs_status gs_radius_stats(const gs_config* cfg, const gs_image* images, int32_t n_img,
                           int64_t n_gauss, const void* workspace, size_t ws_bytes, float tau,
-                          float* radius, void* stream);
+                          int32_t interior_only, float* radius, void* stream);
+
+/* The support radius of the method without the learned part (the control
+ * the learned radius is compared with): the Mahalanobis distance at which a
+ * Gaussian's own peak contribution alpha max(c) f (Eq. 1, 2) falls to tau,
+ *     R = min(max(sqrt(2 ln(max(alpha max(c) K / tau, 1))) + margin, 0), 3),
+ * K = 1 / (2 pi sigma_x sigma_y sqrt(1 - rho^2)) = 1 / (2 pi l11 l22), in FP64;
+ * 3 (the exact box) for l11 <= 0, l22 <= 0 or non-finite values.
+ * chol [n][3], color [n][3], opacity [n], radius [n]: device.  tau > 0. */
+gs_status gs_closed_form_radius(const float* chol, const float* color, const float* opacity,
+                                int64_t n_gauss, double tau, double margin, float* radius,
+                                void* stream);
 
 /* sum (a_i - b_i)^2 over n elements, ADDED to *sum (device double): the
  * squared error behind the PSNR of a pruned render against the exact one. */

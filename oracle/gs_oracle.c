@@ -37,9 +37,10 @@
  *   - A Gaussian with a non-finite value, l11 <= 0 or l22 <= 0 has no support.
  *
  * Build (done by the repository's build step):
- *   gcc -O2 -ffp-contract=off -fPIC -shared gs_oracle.c -o libgsoracle.so -lm
+ *   gcc -O2 -ffp-contract=off -fopenmp -fPIC -shared gs_oracle.c -o libgsoracle.so -lm
  * -ffp-contract=off matters: the support box is defined by an exact FP64
- * operation sequence with no fused multiply-add.
+ * operation sequence with no fused multiply-add.  OpenMP is used only by the
+ * *_mt variants, which time the oracle on several cores.
  */
 #include <math.h>
 #include <stdint.h>
@@ -96,6 +97,24 @@ int or_support_rect(double s, int32_t out_w, int32_t out_h,
     return 1;
 }
 
+/* 1 if the image border cuts the support box of a valid Gaussian (some
+ * integer x or y passing the strict window test lies outside the image),
+ * 0 if the box lies inside the image, -1 if the Gaussian is invalid.  Used to
+ * select the Gaussians whose support-radius labels the border does not cut. */
+int or_box_cut(double s, int32_t out_w, int32_t out_h,
+               double mx, double my, double l11, double l21, double l22, double R)
+{
+    if (!isfinite(mx) || !isfinite(my) || !isfinite(l11) || !isfinite(l21) ||
+        !isfinite(l22) || !isfinite(R))
+        return -1;
+    if (!(l11 > 0.0) || !(l22 > 0.0) || !(R > 0.0)) return -1;
+    double sx = l11;
+    double sy = sqrt(l21 * l21 + l22 * l22);
+    double x0 = floor(s * (mx - R * sx)) + 1.0, x1 = ceil(s * (mx + R * sx)) - 1.0;
+    double y0 = floor(s * (my - R * sy)) + 1.0, y1 = ceil(s * (my + R * sy)) - 1.0;
+    return (x0 < 0.0 || y0 < 0.0 || x1 > (double)(out_w - 1) || y1 > (double)(out_h - 1)) ? 1 : 0;
+}
+
 /* Eq. 2 in its printed (sigma_x, sigma_y, rho) form, at offset (dx, dy). */
 static double eq2_density(double dx, double dy, double sx, double sy, double rho)
 {
@@ -116,6 +135,38 @@ static double radius_of(const double* radius, int64_t i)
     return radius ? radius[i] : 3.0;
 }
 
+/* Adds every Gaussian's contribution to the HR rows [y_lo, y_hi) of one image
+ * (Algorithm 1's loops with Eq. 1, 2, 4, restricted to those rows): for each
+ * Gaussian in ascending order, for each pixel of its support box in the rows,
+ * out += alpha c f(x/s, y/s).  out is the whole [3][out_h][out_w] image. */
+static void forward_rows(int32_t oh, int32_t ow, double s, int64_t n,
+                         const double* mean, const double* chol, const double* color,
+                         const double* opacity, const double* radius,
+                         int32_t y_lo, int32_t y_hi, double* out)
+{
+    int64_t plane = (int64_t)oh * ow;
+    for (int64_t i = 0; i < n; ++i) {
+        const double mx = mean[2 * i], my = mean[2 * i + 1];
+        const double l11 = chol[3 * i], l21 = chol[3 * i + 1], l22 = chol[3 * i + 2];
+        int32_t r[4];
+        if (!or_support_rect(s, ow, oh, mx, my, l11, l21, l22, radius_of(radius, i), r)) continue;
+        if (!isfinite(opacity[i]) || !isfinite(color[3 * i]) || !isfinite(color[3 * i + 1]) ||
+            !isfinite(color[3 * i + 2]))
+            continue;
+        const int32_t ya = r[2] > y_lo ? r[2] : y_lo;
+        const int32_t yb = r[3] < y_hi - 1 ? r[3] : y_hi - 1;
+        double sx, sy, rho;
+        chol_to_eq2(l11, l21, l22, &sx, &sy, &rho);
+        for (int32_t y = ya; y <= yb; ++y) {
+            for (int32_t x = r[0]; x <= r[1]; ++x) {
+                double f = eq2_density((double)x / s - mx, (double)y / s - my, sx, sy, rho);
+                for (int c = 0; c < 3; ++c)
+                    out[c * plane + (int64_t)y * ow + x] += opacity[i] * color[3 * i + c] * f; /* Eq. 1 */
+            }
+        }
+    }
+}
+
 /* Forward render of one image (Algorithm 1 with Eq. 1, 2, 4).
  * mean [n][2] (mu_x, mu_y); chol [n][3] (l11, l21, l22); color [n][3];
  * opacity [n]; radius [n] or NULL (NULL = 3 standard deviations).
@@ -126,26 +177,28 @@ void or_forward(int32_t H, int32_t W, double s, int64_t n,
 {
     int32_t oh, ow;
     if (or_output_size(H, W, s, &oh, &ow) != 0) return;
-    int64_t plane = (int64_t)oh * ow;
-    memset(out, 0, sizeof(double) * 3 * (size_t)plane);
+    memset(out, 0, sizeof(double) * 3 * (size_t)oh * (size_t)ow);
+    forward_rows(oh, ow, s, n, mean, chol, color, opacity, radius, 0, oh, out);
+}
 
-    for (int64_t i = 0; i < n; ++i) {
-        const double mx = mean[2 * i], my = mean[2 * i + 1];
-        const double l11 = chol[3 * i], l21 = chol[3 * i + 1], l22 = chol[3 * i + 2];
-        int32_t r[4];
-        if (!or_support_rect(s, ow, oh, mx, my, l11, l21, l22, radius_of(radius, i), r)) continue;
-        if (!isfinite(opacity[i]) || !isfinite(color[3 * i]) || !isfinite(color[3 * i + 1]) ||
-            !isfinite(color[3 * i + 2]))
-            continue;
-        double sx, sy, rho;
-        chol_to_eq2(l11, l21, l22, &sx, &sy, &rho);
-        for (int32_t y = r[2]; y <= r[3]; ++y) {
-            for (int32_t x = r[0]; x <= r[1]; ++x) {
-                double f = eq2_density((double)x / s - mx, (double)y / s - my, sx, sy, rho);
-                for (int c = 0; c < 3; ++c)
-                    out[c * plane + (int64_t)y * ow + x] += opacity[i] * color[3 * i + c] * f; /* Eq. 1 */
-            }
-        }
+/* or_forward on up to nthreads host threads (OpenMP), for timing the oracle
+ * on all cores: bands of HR rows are rendered independently, each pixel
+ * still summing its Gaussians in ascending order, so the result is bitwise
+ * that of or_forward. */
+void or_forward_mt(int32_t H, int32_t W, double s, int64_t n,
+                   const double* mean, const double* chol, const double* color,
+                   const double* opacity, const double* radius, double* out, int32_t nthreads)
+{
+    int32_t oh, ow;
+    if (or_output_size(H, W, s, &oh, &ow) != 0) return;
+    memset(out, 0, sizeof(double) * 3 * (size_t)oh * (size_t)ow);
+    const int32_t band = 32;
+    const int32_t nb = (oh + band - 1) / band;
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+    for (int32_t b = 0; b < nb; ++b) {
+        const int32_t y1 = (b + 1) * band < oh ? (b + 1) * band : oh;
+        forward_rows(oh, ow, s, n, mean, chol, color, opacity, radius, b * band, y1, out);
     }
 }
 
@@ -166,6 +219,58 @@ void or_forward(int32_t H, int32_t W, double s, int64_t n,
  *   d rho/d l21 = l22^2/sy^3, d rho/d l22 = -l21 l22/sy^3.
  * Outputs are overwritten: grad_mean [n][2], grad_chol [n][3],
  * grad_color [n][3], grad_opacity [n]. */
+/* The gradients of Gaussian i (see or_backward). */
+static void backward_one(int64_t i, int32_t oh, int32_t ow, double s,
+                         const double* mean, const double* chol, const double* color,
+                         const double* opacity, const double* radius, const double* grad_out,
+                         double* grad_mean, double* grad_chol, double* grad_color,
+                         double* grad_opacity)
+{
+    int64_t plane = (int64_t)oh * ow;
+    const double mx = mean[2 * i], my = mean[2 * i + 1];
+    const double l11 = chol[3 * i], l21 = chol[3 * i + 1], l22 = chol[3 * i + 2];
+    const double al = opacity[i];
+    const double* c = color + 3 * i;
+    int32_t r[4];
+    if (!or_support_rect(s, ow, oh, mx, my, l11, l21, l22, radius_of(radius, i), r)) return;
+    if (!isfinite(al) || !isfinite(c[0]) || !isfinite(c[1]) || !isfinite(c[2])) return;
+    double sx, sy, rho;
+    chol_to_eq2(l11, l21, l22, &sx, &sy, &rho);
+    const double D = 1.0 - rho * rho;
+
+    double g_mx = 0, g_my = 0, g_sx = 0, g_sy = 0, g_rho = 0, g_al = 0;
+    double g_c[3] = {0, 0, 0};
+    for (int32_t y = r[2]; y <= r[3]; ++y) {
+        for (int32_t x = r[0]; x <= r[1]; ++x) {
+            const double dx = (double)x / s - mx, dy = (double)y / s - my;
+            const double f = eq2_density(dx, dy, sx, sy, rho);
+            const int64_t p = (int64_t)y * ow + x;
+            double gc_dot = 0.0; /* sum_c dL/dI_c * c_c */
+            for (int k = 0; k < 3; ++k) {
+                const double g = grad_out[k * plane + p];
+                g_c[k] += g * al * f;          /* dI_c/dc_c = alpha f      */
+                gc_dot += g * c[k];
+            }
+            g_al += gc_dot * f;                /* dI_c/dalpha = c_c f      */
+            const double wf = gc_dot * al * f; /* dL/dlog f                 */
+            const double a = dx / sx, b = dy / sy;
+            g_mx += wf * (a - rho * b) / (D * sx);
+            g_my += wf * (b - rho * a) / (D * sy);
+            g_sx += wf * ((a * a - rho * a * b) / (D * sx) - 1.0 / sx);
+            g_sy += wf * ((b * b - rho * a * b) / (D * sy) - 1.0 / sy);
+            g_rho += wf * ((a * b * D - rho * (a * a - 2.0 * rho * a * b + b * b)) / (D * D) + rho / D);
+        }
+    }
+    const double sy3 = sy * sy * sy;
+    grad_mean[2 * i] = g_mx;
+    grad_mean[2 * i + 1] = g_my;
+    grad_chol[3 * i] = g_sx;
+    grad_chol[3 * i + 1] = g_sy * (l21 / sy) + g_rho * (l22 * l22 / sy3);
+    grad_chol[3 * i + 2] = g_sy * (l22 / sy) + g_rho * (-l21 * l22 / sy3);
+    for (int k = 0; k < 3; ++k) grad_color[3 * i + k] = g_c[k];
+    grad_opacity[i] = g_al;
+}
+
 void or_backward(int32_t H, int32_t W, double s, int64_t n,
                  const double* mean, const double* chol, const double* color,
                  const double* opacity, const double* radius, const double* grad_out,
@@ -177,52 +282,31 @@ void or_backward(int32_t H, int32_t W, double s, int64_t n,
     memset(grad_color, 0, sizeof(double) * 3 * (size_t)n);
     memset(grad_opacity, 0, sizeof(double) * (size_t)n);
     if (or_output_size(H, W, s, &oh, &ow) != 0) return;
-    int64_t plane = (int64_t)oh * ow;
+    for (int64_t i = 0; i < n; ++i)
+        backward_one(i, oh, ow, s, mean, chol, color, opacity, radius, grad_out, grad_mean,
+                     grad_chol, grad_color, grad_opacity);
+}
 
-    for (int64_t i = 0; i < n; ++i) {
-        const double mx = mean[2 * i], my = mean[2 * i + 1];
-        const double l11 = chol[3 * i], l21 = chol[3 * i + 1], l22 = chol[3 * i + 2];
-        const double al = opacity[i];
-        const double* c = color + 3 * i;
-        int32_t r[4];
-        if (!or_support_rect(s, ow, oh, mx, my, l11, l21, l22, radius_of(radius, i), r)) continue;
-        if (!isfinite(al) || !isfinite(c[0]) || !isfinite(c[1]) || !isfinite(c[2])) continue;
-        double sx, sy, rho;
-        chol_to_eq2(l11, l21, l22, &sx, &sy, &rho);
-        const double D = 1.0 - rho * rho;
-
-        double g_mx = 0, g_my = 0, g_sx = 0, g_sy = 0, g_rho = 0, g_al = 0;
-        double g_c[3] = {0, 0, 0};
-        for (int32_t y = r[2]; y <= r[3]; ++y) {
-            for (int32_t x = r[0]; x <= r[1]; ++x) {
-                const double dx = (double)x / s - mx, dy = (double)y / s - my;
-                const double f = eq2_density(dx, dy, sx, sy, rho);
-                const int64_t p = (int64_t)y * ow + x;
-                double gc_dot = 0.0; /* sum_c dL/dI_c * c_c */
-                for (int k = 0; k < 3; ++k) {
-                    const double g = grad_out[k * plane + p];
-                    g_c[k] += g * al * f;          /* dI_c/dc_c = alpha f      */
-                    gc_dot += g * c[k];
-                }
-                g_al += gc_dot * f;                /* dI_c/dalpha = c_c f      */
-                const double wf = gc_dot * al * f; /* dL/dlog f                 */
-                const double a = dx / sx, b = dy / sy;
-                g_mx += wf * (a - rho * b) / (D * sx);
-                g_my += wf * (b - rho * a) / (D * sy);
-                g_sx += wf * ((a * a - rho * a * b) / (D * sx) - 1.0 / sx);
-                g_sy += wf * ((b * b - rho * a * b) / (D * sy) - 1.0 / sy);
-                g_rho += wf * ((a * b * D - rho * (a * a - 2.0 * rho * a * b + b * b)) / (D * D) + rho / D);
-            }
-        }
-        const double sy3 = sy * sy * sy;
-        grad_mean[2 * i] = g_mx;
-        grad_mean[2 * i + 1] = g_my;
-        grad_chol[3 * i] = g_sx;
-        grad_chol[3 * i + 1] = g_sy * (l21 / sy) + g_rho * (l22 * l22 / sy3);
-        grad_chol[3 * i + 2] = g_sy * (l22 / sy) + g_rho * (-l21 * l22 / sy3);
-        for (int k = 0; k < 3; ++k) grad_color[3 * i + k] = g_c[k];
-        grad_opacity[i] = g_al;
-    }
+/* or_backward on up to nthreads host threads (OpenMP), for timing the
+ * oracle on all cores: Gaussians are independent, so the result is bitwise
+ * that of or_backward. */
+void or_backward_mt(int32_t H, int32_t W, double s, int64_t n,
+                    const double* mean, const double* chol, const double* color,
+                    const double* opacity, const double* radius, const double* grad_out,
+                    double* grad_mean, double* grad_chol, double* grad_color,
+                    double* grad_opacity, int32_t nthreads)
+{
+    int32_t oh, ow;
+    memset(grad_mean, 0, sizeof(double) * 2 * (size_t)n);
+    memset(grad_chol, 0, sizeof(double) * 3 * (size_t)n);
+    memset(grad_color, 0, sizeof(double) * 3 * (size_t)n);
+    memset(grad_opacity, 0, sizeof(double) * (size_t)n);
+    if (or_output_size(H, W, s, &oh, &ow) != 0) return;
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for schedule(dynamic, 256) num_threads(nthreads)
+    for (int64_t i = 0; i < n; ++i)
+        backward_one(i, oh, ow, s, mean, chol, color, opacity, radius, grad_out, grad_mean,
+                     grad_chol, grad_color, grad_opacity);
 }
 
 /* Tile lists of one image: tiles are tw x th HR pixels, numbered row-major

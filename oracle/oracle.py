@@ -28,11 +28,12 @@ _I32 = ctypes.POINTER(ctypes.c_int32)
 
 
 def build(force: bool = False) -> str:
-    """Compile the C oracle with gcc (plain -O2, no FMA contraction)."""
+    """Compile the C oracle with gcc (plain -O2, no FMA contraction; OpenMP
+    for the multi-threaded timing variants only)."""
     if force or not os.path.exists(_LIB_PATH) or \
             os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
                                _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -49,12 +50,18 @@ def lib():
         L.or_support_rect.argtypes = [ctypes.c_double, ctypes.c_int32, ctypes.c_int32] + \
             [ctypes.c_double] * 6 + [_I32]
         L.or_support_rect.restype = ctypes.c_int
+        L.or_box_cut.argtypes = L.or_support_rect.argtypes[:-1]
+        L.or_box_cut.restype = ctypes.c_int
         L.or_forward.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                  ctypes.c_int64, _D, _D, _D, _D, _D, _D]
         L.or_forward.restype = None
         L.or_backward.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                   ctypes.c_int64, _D, _D, _D, _D, _D, _D, _D, _D, _D, _D]
         L.or_backward.restype = None
+        L.or_forward_mt.argtypes = L.or_forward.argtypes + [ctypes.c_int32]
+        L.or_forward_mt.restype = None
+        L.or_backward_mt.argtypes = L.or_backward.argtypes + [ctypes.c_int32]
+        L.or_backward_mt.restype = None
         L.or_tile_lists.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                     ctypes.c_int64, _D, _D, _D, ctypes.c_int32,
                                     ctypes.c_int32, _I32, _I32, ctypes.c_int64]
@@ -98,6 +105,15 @@ def support_rect(s, out_w, out_h, mx, my, l11, l21, l22, R=3.0):
     return bool(ok), tuple(r)
 
 
+def box_cut(H, W, s, mean, chol, R=3.0):
+    """Per Gaussian: 1 if the image border cuts its support box, 0 if not,
+    -1 if it is invalid."""
+    oh, ow = output_size(H, W, s)
+    mean, chol = _d(mean), _d(chol)
+    return np.array([lib().or_box_cut(float(s), ow, oh, *mean[i], *chol[i], float(R))
+                     for i in range(mean.shape[0])], dtype=np.int32)
+
+
 def support_rects(H, W, s, mean, chol, radius=None):
     """Support boxes [n][4] (x0, x1, y0, y1; empty = x1 < x0) and the number of
     in-support (pixel, Gaussian) pairs."""
@@ -110,27 +126,37 @@ def support_rects(H, W, s, mean, chol, radius=None):
     return rects, int(total)
 
 
-def forward(H, W, s, mean, chol, color, opacity, radius=None):
-    """HR image [3, out_h, out_w] (FP64) of one image."""
+def forward(H, W, s, mean, chol, color, opacity, radius=None, threads=1):
+    """HR image [3, out_h, out_w] (FP64) of one image.  threads > 1 runs the
+    OpenMP variant (row bands; bitwise the same image)."""
     oh, ow = output_size(H, W, s)
     mean, chol, color, opacity = _d(mean), _d(chol), _d(color), _d(opacity)
     rad = None if radius is None else _d(radius)
     out = np.zeros((3, oh, ow), dtype=np.float64)
-    lib().or_forward(H, W, float(s), mean.shape[0], _p(mean), _p(chol), _p(color),
-                     _p(opacity), _p(rad), _p(out))
+    args = (H, W, float(s), mean.shape[0], _p(mean), _p(chol), _p(color), _p(opacity),
+            _p(rad), _p(out))
+    if threads > 1:
+        lib().or_forward_mt(*args, int(threads))
+    else:
+        lib().or_forward(*args)
     return out
 
 
-def backward(H, W, s, mean, chol, color, opacity, grad_out, radius=None):
-    """Gradients (mean, chol, color, opacity) for upstream dL/dI grad_out."""
+def backward(H, W, s, mean, chol, color, opacity, grad_out, radius=None, threads=1):
+    """Gradients (mean, chol, color, opacity) for upstream dL/dI grad_out.
+    threads > 1 runs the OpenMP variant (bitwise the same result)."""
     mean, chol, color, opacity = _d(mean), _d(chol), _d(color), _d(opacity)
     rad = None if radius is None else _d(radius)
     g = _d(grad_out)
     n = mean.shape[0]
     gm, gc = np.zeros((n, 2)), np.zeros((n, 3))
     gcol, gop = np.zeros((n, 3)), np.zeros(n)
-    lib().or_backward(H, W, float(s), n, _p(mean), _p(chol), _p(color), _p(opacity),
-                      _p(rad), _p(g), _p(gm), _p(gc), _p(gcol), _p(gop))
+    args = (H, W, float(s), n, _p(mean), _p(chol), _p(color), _p(opacity), _p(rad), _p(g),
+            _p(gm), _p(gc), _p(gcol), _p(gop))
+    if threads > 1:
+        lib().or_backward_mt(*args, int(threads))
+    else:
+        lib().or_backward(*args)
     return gm, gc, gcol, gop
 
 
@@ -153,6 +179,17 @@ def radius_labels(H, W, s, mean, chol, color, opacity, tau):
     lib().or_radius_labels(H, W, float(s), mean.shape[0], _p(mean), _p(chol), _p(color),
                            _p(opacity), float(tau), _p(R))
     return R
+
+
+def interior_labels_batch(wl, tau):
+    """radius_labels_batch with -1 for the Gaussians whose support box the
+    image border cuts (or that are invalid)."""
+    out = radius_labels_batch(wl, tau)
+    for k, im in enumerate(wl.images):
+        sl = wl.image_slice(k)
+        cut = box_cut(im.lr_h, im.lr_w, im.scale, wl.mean[sl], wl.chol[sl])
+        out[sl] = np.where(cut != 0, -1.0, out[sl])
+    return out
 
 
 def radius_labels_batch(wl, tau):
@@ -186,17 +223,17 @@ def _radius_slice(radius, sl):
     return None if radius is None else np.asarray(radius)[sl]
 
 
-def forward_batch(wl, radius=None):
+def forward_batch(wl, radius=None, threads=1):
     """List of FP64 images [3, oh, ow], one per image of the workload."""
     out = []
     for k, im in enumerate(wl.images):
         sl = wl.image_slice(k)
         out.append(forward(im.lr_h, im.lr_w, im.scale, wl.mean[sl], wl.chol[sl],
-                           wl.color[sl], wl.opacity[sl], _radius_slice(radius, sl)))
+                           wl.color[sl], wl.opacity[sl], _radius_slice(radius, sl), threads))
     return out
 
 
-def backward_batch(wl, grads_out, radius=None):
+def backward_batch(wl, grads_out, radius=None, threads=1):
     """Packed gradients over the whole batch for per-image upstream gradients."""
     n = wl.n_gauss
     gm, gc = np.zeros((n, 2)), np.zeros((n, 3))
@@ -205,7 +242,7 @@ def backward_batch(wl, grads_out, radius=None):
         sl = wl.image_slice(k)
         a, b, c, d = backward(im.lr_h, im.lr_w, im.scale, wl.mean[sl], wl.chol[sl],
                               wl.color[sl], wl.opacity[sl], grads_out[k],
-                              _radius_slice(radius, sl))
+                              _radius_slice(radius, sl), threads)
         gm[sl], gc[sl], gcol[sl], gop[sl] = a, b, c, d
     return gm, gc, gcol, gop
 

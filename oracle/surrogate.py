@@ -96,8 +96,10 @@ def mlp_forward(params, X, rounding=True):
     return out, (Xb, Z1, H1, Z2, H2, W1, W2, W3)
 
 
-def mlp_backward(cache, dout, rounding=True):
-    """Flat gradient (PARAM_SHAPES order) for upstream dout [N]."""
+def mlp_backward(cache, dout, rounding=True, parts=None):
+    """Flat gradient (PARAM_SHAPES order) for upstream dout [N].  When parts
+    is a dict it receives the backward's intermediate values (d3b, dZ2, dZ2b,
+    dH1, dZ1, dZ1b), for tests that bound the GPU's rounding against them."""
     r = bf16 if rounding else (lambda v: np.asarray(v, np.float64))
     Xb, Z1, H1, Z2, H2, W1, W2, W3 = cache
     d3 = np.asarray(dout, np.float64)
@@ -112,6 +114,8 @@ def mlp_backward(cache, dout, rounding=True):
     dZ1b = r(dZ1)
     dW1 = dZ1b.T @ Xb
     db1 = dZ1.sum(axis=0)
+    if parts is not None:
+        parts.update(d3=d3, d3b=d3b, dZ2=dZ2, dZ2b=dZ2b, dH1=dZ2b @ W2, dZ1=dZ1, dZ1b=dZ1b)
     return pack({"W1": dW1, "b1": db1, "W2": dW2, "b2": db2, "W3": dW3, "b3": db3})
 
 
@@ -134,6 +138,24 @@ def adam(params, grad, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
     vh = v / (1 - b2 ** t)
     p = np.asarray(params, np.float64) - lr * mh / (np.sqrt(vh) + eps)
     return p.astype(np.float32), m.astype(np.float32), v.astype(np.float32)
+
+
+def closed_form_radius(chol, color, opacity, tau, margin=0.0):
+    """The support radius without the learned part: the Mahalanobis distance d
+    at which alpha max(c) f (Eq. 1, 2) at distance d, alpha max(c) K
+    exp(-d^2/2) with K = 1 / (2 pi sigma_x sigma_y sqrt(1 - rho^2)), falls to
+    tau; plus margin, clamped to [0, 3]; 3 for invalid values."""
+    chol = np.asarray(chol, np.float64)
+    sx = chol[:, 0]
+    sy = np.sqrt(chol[:, 1] ** 2 + chol[:, 2] ** 2)
+    rho = chol[:, 1] / sy
+    K = 1.0 / (2.0 * math.pi * sx * sy * np.sqrt(1.0 - rho * rho))
+    peak = np.asarray(opacity, np.float64) * np.asarray(color, np.float64).max(axis=1) * K
+    with np.errstate(invalid="ignore", divide="ignore"):
+        d = np.sqrt(2.0 * np.log(np.maximum(peak / tau, 1.0)))
+    R = np.clip(d + margin, 0.0, 3.0)
+    ok = (chol[:, 0] > 0) & (chol[:, 2] > 0) & np.isfinite(peak)
+    return np.where(ok, R, 3.0)
 
 
 def prune_radius(pred, margin, F, fmin, fmax):

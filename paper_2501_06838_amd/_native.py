@@ -19,6 +19,8 @@ GS_E_DEVICE = -3
 GS_E_UNSUPPORTED = -4
 GS_E_WORKSPACE = -5
 
+ABI_VERSION = 2  # GS_ABI_VERSION of include/gs_raster.h
+
 GS_FLAG_PERSISTENT = 0x1
 GS_FLAG_ATOMIC_GRADS = 0x2
 GS_FLAG_RADIX_SORT = 0x4
@@ -31,7 +33,7 @@ EXPORTED = (
     "gs_l1_loss_value", "gs_raster_backward_l1", "gs_graph_create", "gs_graph_launch",
     "gs_graph_destroy", "gs_mlp_features", "gs_mlp_forward", "gs_mlp_workspace_size",
     "gs_mlp_grad", "gs_mlp_adam", "gs_radius_stats", "gs_sq_error", "gs_tile_order",
-    "gs_raster_render_fused_l1", "gs_raster_step_l1", "gs_mlp_radius",
+    "gs_raster_render_fused_l1", "gs_raster_step_l1", "gs_mlp_radius", "gs_closed_form_radius",
 )
 
 
@@ -130,7 +132,7 @@ def lib():
         L.gs_graph_launch.restype = _i32
         L.gs_graph_destroy.argtypes = [_vp]
         L.gs_graph_destroy.restype = _i32
-        if L.gs_abi_version() != 1:
+        if L.gs_abi_version() != ABI_VERSION:
             raise ImportError("libgsraster ABI version mismatch")
         _lib = L
     return _lib

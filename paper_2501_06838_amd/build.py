@@ -29,25 +29,51 @@ FLAGS = [
 
 
 def command(out=LIB):
+    """One hipcc line that compiles and links every source (for reference;
+    build() compiles the sources in parallel and links them)."""
     return [HIPCC, *FLAGS, "-I", INCLUDE, "-I", CSRC,
             *[os.path.join(CSRC, s) for s in SOURCES], "-o", out]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source into one shared library (always recompiles)."""
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = command(tmp)
-    if verbose:
-        print(" ".join(cmd), flush=True)
+def _run(cmd):
     res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     # hipcc's host pass does not know the packed-FP32 feature name: harmless
     noise = "'-packed-fp32-ops' is not a recognized feature"
     text = "\n".join(l for l in res.stdout.splitlines() if noise not in l)
-    if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + text)
-    if verbose and text.strip():
-        print(text)
-    os.replace(tmp, LIB)
+    return res.returncode, text
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every HIP source (in parallel, one hipcc per file) and link
+    them into one shared library.  Always recompiles."""
+    from concurrent.futures import ThreadPoolExecutor
+    tag = "%d" % os.getpid()
+    objs = [os.path.join(CSRC, os.path.splitext(s)[0] + ".%s.o" % tag) for s in SOURCES]
+    compile_flags = [f for f in FLAGS if f != "-shared"]
+    cmds = [[HIPCC, *compile_flags, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, s),
+             "-o", o] for s, o in zip(SOURCES, objs)]
+    tmp = LIB + ".tmp" + tag
+    try:
+        with ThreadPoolExecutor(max_workers=len(cmds)) as ex:
+            results = list(ex.map(_run, cmds))
+        for cmd, (rc, text) in zip(cmds, results):
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            if rc != 0:
+                raise RuntimeError("hipcc failed:\n" + text)
+            if verbose and text.strip():
+                print(text)
+        link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+        rc, text = _run(link)
+        if verbose:
+            print(" ".join(link), flush=True)
+        if rc != 0:
+            raise RuntimeError("hipcc link failed:\n" + text)
+        os.replace(tmp, LIB)
+    finally:
+        for o in objs + [tmp]:
+            if os.path.exists(o):
+                os.remove(o)
     return LIB
 
 

@@ -361,10 +361,10 @@ gs_status gs_raster_backward_l1(const gs_config* cfg, const gs_image* images, in
 }
 
 gs_status gs_l1_loss_grad(const float* img, const float* target, int64_t numel,
-                          float* grad, double* loss_sum, void* stream) {
-    if (numel < 0) return GS_E_INVALID;
-    if (numel > 0 && (!img || !target || !grad || !loss_sum)) return GS_E_INVALID;
-    return dev(launch_l1(img, target, numel, grad, loss_sum, static_cast<hipStream_t>(stream)));
+                          float* grad, double* loss, void* stream) {
+    if (numel < 0 || !loss) return GS_E_INVALID;
+    if (numel > 0 && (!img || !target || !grad)) return GS_E_INVALID;
+    return dev(launch_l1(img, target, numel, grad, loss, static_cast<hipStream_t>(stream)));
 }
 
 gs_status gs_diagnostics(const gs_config* cfg, const gs_image* images, int32_t n_img,
@@ -521,15 +521,26 @@ gs_status gs_mlp_adam(float* params, float* m, float* v, const float* grad, int3
 
 gs_status gs_radius_stats(const gs_config* cfg, const gs_image* images, int32_t n_img,
                           int64_t n_gauss, const void* workspace, size_t ws_bytes, float tau,
-                          float* radius, void* stream) {
+                          int32_t interior_only, float* radius, void* stream) {
     Layout L;
     std::vector<ImgDev> table;
     GS_TRY(make_layout(cfg, images, n_img, n_gauss, &L, &table));
     if (n_gauss > 0 && !radius) return GS_E_INVALID;
     if (!(tau > 0.f)) return GS_E_INVALID;
     if (!workspace || ws_bytes < L.total) return GS_E_WORKSPACE;
-    return dev(launch_radius_stats(L, bind(L, const_cast<void*>(workspace)), tau, radius,
+    return dev(launch_radius_stats(L, bind(L, const_cast<void*>(workspace)), tau,
+                                   interior_only ? 1 : 0, radius,
                                    static_cast<hipStream_t>(stream)));
+}
+
+gs_status gs_closed_form_radius(const float* chol, const float* color, const float* opacity,
+                                int64_t n_gauss, double tau, double margin, float* radius,
+                                void* stream) {
+    if (n_gauss < 0 || !(tau > 0.0) || !std::isfinite(tau) || !std::isfinite(margin))
+        return GS_E_INVALID;
+    if (n_gauss > 0 && (!chol || !color || !opacity || !radius)) return GS_E_INVALID;
+    return dev(launch_closed_form_radius(chol, color, opacity, n_gauss, tau, margin, radius,
+                                         static_cast<hipStream_t>(stream)));
 }
 
 gs_status gs_sq_error(const float* a, const float* b, int64_t n, double* sum, void* stream) {

@@ -70,9 +70,11 @@ __device__ __forceinline__ int find_image(const Table& imgs, int n_img, int64_t 
 __device__ __forceinline__ bool finite_d(double v) { return __builtin_isfinite(v); }
 
 // Support box in HR pixels, clipped to the image (see the file comment).
-// Returns false when the box is empty or the parameters are invalid.
+// Returns false when the box is empty or the parameters are invalid;
+// *clipped tells whether the image border cut the box.
 __device__ bool support_box(double s, int out_w, int out_h, double mx, double my,
-                            double l11, double l21, double l22, double R, int* box) {
+                            double l11, double l21, double l22, double R, int* box,
+                            bool* clipped) {
 #pragma clang fp contract(off)
     if (!finite_d(mx) || !finite_d(my) || !finite_d(l11) || !finite_d(l21) ||
         !finite_d(l22) || !finite_d(R))
@@ -86,6 +88,7 @@ __device__ bool support_box(double s, int out_w, int out_h, double mx, double my
     const double hi_y = s * (my + R * sy);
     double x0 = __builtin_floor(lo_x) + 1.0, x1 = __builtin_ceil(hi_x) - 1.0;
     double y0 = __builtin_floor(lo_y) + 1.0, y1 = __builtin_ceil(hi_y) - 1.0;
+    *clipped = x0 < 0.0 || y0 < 0.0 || x1 > (double)(out_w - 1) || y1 > (double)(out_h - 1);
     if (x0 < 0.0) x0 = 0.0;
     if (y0 < 0.0) y0 = 0.0;
     if (x1 > (double)(out_w - 1)) x1 = (double)(out_w - 1);
@@ -132,7 +135,7 @@ __global__ __launch_bounds__(kBlockG) void k_support(
         r.fx = r.fy = 0.f; r.kx = r.ky = 0;
         r.a = r.e = r.g = 0.f;
         r.A[0] = r.A[1] = r.A[2] = 0.f;
-        r.pad = 0;
+        r.flags = 0;
         const int k = kArgTable ? find_image(arg_imgs.img, n_img, i) : find_image(imgs, n_img, i);
         r.img = k;
         if (k >= 0) {
@@ -142,10 +145,11 @@ __global__ __launch_bounds__(kBlockG) void k_support(
             const double l11 = chol[3 * i], l21 = chol[3 * i + 1], l22 = chol[3 * i + 2];
             const double R = radius ? (double)radius[i] : 3.0;
             int box[4];
+            bool clipped = false;
             const bool shape_ok = finite_d(mx) && finite_d(my) && finite_d(l11) &&
                                   finite_d(l21) && finite_d(l22) && l11 > 0.0 && l22 > 0.0;
             bad = shape_ok ? 0 : 1;
-            if (support_box(s, im.out_w, im.out_h, mx, my, l11, l21, l22, R, box)) {
+            if (support_box(s, im.out_w, im.out_h, mx, my, l11, l21, l22, R, box, &clipped)) {
                 // colour / opacity may be NULL when only the pairs are counted
                 const double al = opacity ? (double)opacity[i] : 0.0;
                 const double c0 = color ? (double)color[3 * i] : 0.0;
@@ -170,8 +174,9 @@ __global__ __launch_bounds__(kBlockG) void k_support(
                     r.A[1] = (float)(al * c1 * K);
                     r.A[2] = (float)(al * c2 * K);
                 } else {
-                    r.pad = 1;  // listed in tiles but contributes and receives nothing
+                    r.flags |= kRecNoAmp;  // listed in tiles but adds and receives nothing
                 }
+                if (clipped) r.flags |= kRecClipped;
                 const int tx0 = r.x0 / tile, tx1 = r.x1 / tile;
                 const int ty0 = r.y0 / tile, ty1 = r.y1 / tile;
                 cnt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);

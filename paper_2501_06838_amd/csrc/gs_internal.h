@@ -64,8 +64,12 @@ struct GRec {
     float A[3];
     int32_t x0, x1, y0, y1;  // support box, inclusive; x0 > x1 means none
     int32_t img;
-    int32_t pad;
+    int32_t flags;           // kRecNoAmp | kRecClipped
 };
+// GRec::flags: a non-finite opacity or colour (listed in its tiles, adds and
+// receives nothing); the support box was cut by the image border.
+constexpr int32_t kRecNoAmp = 1;
+constexpr int32_t kRecClipped = 2;
 static_assert(sizeof(GRec) == 64, "GRec layout");
 
 
@@ -217,8 +221,9 @@ hipError_t launch_finalize(const Layout& L, const Ws& w, const float* chol,
                            const float* color, const float* opacity, float* grad_mean,
                            float* grad_chol, float* grad_color, float* grad_opacity,
                            hipStream_t st, int64_t numel = 0, double* loss = nullptr);
+// grad = sign(img - target) / numel; *loss = mean |img - target| (overwritten)
 hipError_t launch_l1(const float* img, const float* target, int64_t numel, float* grad,
-                     double* loss_sum, hipStream_t st);
+                     double* loss, hipStream_t st);
 
 // ---- launchers (gs_surrogate.hip) ----------------------------------------
 int64_t mlp_grad_waves(int64_t n);
@@ -237,8 +242,11 @@ hipError_t launch_mlp_grad(const float* params, const float* X, const float* lab
                            float* grad, double* loss_sum, hipStream_t st);
 hipError_t launch_adam(float* p, float* m, float* v, const float* grad, int t, float lr,
                        float b1, float b2, float eps, hipStream_t st);
-hipError_t launch_radius_stats(const Layout& L, const Ws& w, float tau, float* R,
-                               hipStream_t st);
+hipError_t launch_radius_stats(const Layout& L, const Ws& w, float tau, int interior_only,
+                               float* R, hipStream_t st);
+hipError_t launch_closed_form_radius(const float* chol, const float* color,
+                                    const float* opacity, int64_t n, double tau, double margin,
+                                    float* R, hipStream_t st);
 hipError_t launch_sq_error(const float* a, const float* b, int64_t n, double* sum,
                            hipStream_t st);
 

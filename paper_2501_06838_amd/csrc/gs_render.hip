@@ -779,7 +779,7 @@ __global__ __launch_bounds__(kBlockG) void k_finalize(
         mp[0] = make_float4(0.f, 0.f, 0.f, 0.f);  // ready for the next backward
         mp[1] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
-    if (r.x0 <= r.x1 && r.pad == 0) {
+    if (r.x0 <= r.x1 && !(r.flags & kRecNoAmp)) {
         const double l11 = chol[3 * i], l21 = chol[3 * i + 1], l22 = chol[3 * i + 2];
         const double al = opacity[i];
         const double c0 = color[3 * i], c1 = color[3 * i + 1], c2 = color[3 * i + 2];
@@ -811,10 +811,14 @@ __global__ __launch_bounds__(kBlockG) void k_finalize(
     grad_opacity[i] = (float)ga;
 }
 
+__global__ void k_zero_double(double* __restrict__ p) { *p = 0.0; }
+
+// L1 gradient sign(img - tgt) / numel per element; each workgroup adds its
+// share of the mean |img - tgt| to *loss (zeroed by k_zero_double first).
 __global__ __launch_bounds__(kBlockG) void k_l1(const float* __restrict__ img,
                                                 const float* __restrict__ tgt, int64_t numel,
                                                 float* __restrict__ grad,
-                                                double* __restrict__ loss_sum) {
+                                                double* __restrict__ loss) {
     __shared__ double tmp[kBlockG / 64];
     const float inv = (float)(1.0 / (double)numel);
     double s = 0.0;
@@ -830,7 +834,7 @@ __global__ __launch_bounds__(kBlockG) void k_l1(const float* __restrict__ img,
     if (threadIdx.x == 0) {
         double b = 0.0;
         for (int k = 0; k < kBlockG / 64; ++k) b += tmp[k];
-        atomicAdd(loss_sum, b);
+        atomicAdd(loss, b / (double)numel);
     }
 }
 
@@ -1062,14 +1066,14 @@ hipError_t launch_finalize(const Layout& L, const Ws& w, const float* chol,
 }
 
 hipError_t launch_l1(const float* img, const float* target, int64_t numel, float* grad,
-                     double* loss_sum, hipStream_t st) {
-    if (numel == 0) return hipSuccess;
-    // at most 256 workgroups: each adds one double to *loss_sum, and atomics
+                     double* loss, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_double, dim3(1), dim3(1), 0, st, loss);
+    if (numel == 0) return hipGetLastError();
+    // at most 256 workgroups: each adds one double to *loss, and atomics
     // on a single address serialise
     int nb = blocks_for(numel, kBlockG * 4);
     if (nb > 256) nb = 256;
-    hipLaunchKernelGGL(k_l1, dim3(nb), dim3(kBlockG), 0, st, img, target, numel, grad,
-                       loss_sum);
+    hipLaunchKernelGGL(k_l1, dim3(nb), dim3(kBlockG), 0, st, img, target, numel, grad, loss);
     return hipGetLastError();
 }
 

@@ -502,15 +502,17 @@ __global__ __launch_bounds__(kRadiusThreads) void k_mlp_radius(
 // Labels from the exact rasterizer's render records (workspace of a forward
 // with the exact 3-sigma boxes): per Gaussian, walk its box and keep the
 // largest z1^2 + z2^2 among pixels with max_c(A_c) * w >= tau (A_c =
-// alpha c_c K, w = exp(-(z1^2 + z2^2) / 2)); FP32 bits in best.
+// alpha c_c K, w = exp(-(z1^2 + z2^2) / 2)); FP32 bits in best.  With
+// interior_only, a Gaussian whose box the image border cut gets -1 (its
+// label would be cut too).
 __global__ __launch_bounds__(256) void k_radius_stats(const GRec* __restrict__ recs,
-                                                      int64_t n, float tau,
+                                                      int64_t n, float tau, int interior_only,
                                                       uint32_t* __restrict__ best) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     const GRec r = recs[i];
     float m = 0.f;
-    if (r.x0 <= r.x1 && r.y0 <= r.y1 && r.pad == 0) {
+    if (r.x0 <= r.x1 && r.y0 <= r.y1 && !(r.flags & kRecNoAmp)) {
         const float amax = fmaxf(r.A[0], fmaxf(r.A[1], r.A[2]));
         const float inv_kc2 = (float)(1.0 / (kZScale * kZScale));
         for (int y = r.y0; y <= r.y1; ++y) {
@@ -523,13 +525,42 @@ __global__ __launch_bounds__(256) void k_radius_stats(const GRec* __restrict__ r
             }
         }
     }
+    if (interior_only && (r.flags & kRecClipped)) m = -1.f;
     best[i] = __float_as_uint(m);
 }
 
 __global__ __launch_bounds__(256) void k_sqrt_labels(const uint32_t* __restrict__ best,
                                                      int64_t n, float* __restrict__ R) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < n) R[i] = sqrtf(__uint_as_float(best[i]));
+    if (i >= n) return;
+    const float v = __uint_as_float(best[i]);
+    R[i] = v < 0.f ? -1.f : sqrtf(v);
+}
+
+// The closed-form support radius of the method without the learned part:
+// the Mahalanobis distance d at which a Gaussian's own peak contribution
+// alpha max(c) K exp(-d^2 / 2) (Eq. 1, 2; K = 1 / (2 pi sigma_x sigma_y
+// sqrt(1 - rho^2)) = 1 / (2 pi l11 l22)) falls to tau, plus a margin, capped
+// at 3: R = min(sqrt(2 ln(max(alpha max(c) K / tau, 1))) + margin, 3).
+// Invalid values give 3 (the exact box decides).
+__global__ __launch_bounds__(256) void k_closed_form_radius(
+    const float* __restrict__ chol, const float* __restrict__ color,
+    const float* __restrict__ opacity, int64_t n, double tau, double margin,
+    float* __restrict__ R) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const double l11 = chol[3 * i], l22 = chol[3 * i + 2];
+    const double al = opacity[i];
+    const double cm = fmax((double)color[3 * i], fmax((double)color[3 * i + 1],
+                                                      (double)color[3 * i + 2]));
+    const double K = 1.0 / (2.0 * 3.14159265358979323846 * l11 * l22);
+    const double ratio = al * cm * K / tau;
+    double r = 3.0;
+    if (l11 > 0.0 && l22 > 0.0 && __builtin_isfinite(ratio)) {
+        r = sqrt(2.0 * log(fmax(ratio, 1.0))) + margin;
+        r = fmin(fmax(r, 0.0), 3.0);
+    }
+    R[i] = (float)r;
 }
 
 __global__ __launch_bounds__(256) void k_sq_error(const float* __restrict__ a,
@@ -628,14 +659,23 @@ hipError_t launch_adam(float* p, float* m, float* v, const float* grad, int t, f
     return hipGetLastError();
 }
 
-hipError_t launch_radius_stats(const Layout& L, const Ws& w, float tau, float* R,
-                               hipStream_t st) {
+hipError_t launch_radius_stats(const Layout& L, const Ws& w, float tau, int interior_only,
+                               float* R, hipStream_t st) {
     uint32_t* best = reinterpret_cast<uint32_t*>(R);  // FP32 bits, then sqrt in place
     if (L.n_gauss == 0) return hipSuccess;
     hipLaunchKernelGGL(k_radius_stats, dim3(blocks_for(L.n_gauss, 256)), dim3(256), 0, st,
-                       w.recs, L.n_gauss, tau, best);
+                       w.recs, L.n_gauss, tau, interior_only, best);
     hipLaunchKernelGGL(k_sqrt_labels, dim3(blocks_for(L.n_gauss, 256)), dim3(256), 0, st,
                        best, L.n_gauss, R);
+    return hipGetLastError();
+}
+
+hipError_t launch_closed_form_radius(const float* chol, const float* color,
+                                    const float* opacity, int64_t n, double tau, double margin,
+                                    float* R, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_closed_form_radius, dim3(blocks_for(n, 256)), dim3(256), 0, st, chol,
+                       color, opacity, n, tau, margin, R);
     return hipGetLastError();
 }
 

@@ -393,7 +393,7 @@ def l1_loss_grad(img: torch.Tensor, target: torch.Tensor, stream=None):
     _check_param(img, "img", tuple(img.shape))
     _check_param(target, "target", tuple(img.shape))
     grad = torch.empty_like(img)
-    acc = torch.zeros((), dtype=torch.float64, device=img.device)
+    loss = torch.empty((), dtype=torch.float64, device=img.device)
     N.check(N.lib().gs_l1_loss_grad(_ptr(img), _ptr(target), img.numel(), _ptr(grad),
-                                    _ptr(acc), _stream(stream)), "l1 loss")
-    return acc / img.numel(), grad
+                                    _ptr(loss), _stream(stream)), "l1 loss")
+    return loss, grad

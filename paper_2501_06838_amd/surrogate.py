@@ -51,10 +51,13 @@ def _bind():
     L.gs_mlp_adam.argtypes = [vp, vp, vp, vp, i32, f32, vp]
     L.gs_mlp_adam.restype = i32
     L.gs_radius_stats.argtypes = [ctypes.POINTER(N.gs_config), ctypes.POINTER(N.gs_image), i32,
-                                  i64, vp, ctypes.c_size_t, f32, vp, vp]
+                                  i64, vp, ctypes.c_size_t, f32, i32, vp, vp]
     L.gs_radius_stats.restype = i32
     L.gs_sq_error.argtypes = [vp, vp, i64, vp, vp]
     L.gs_sq_error.restype = i32
+    L.gs_closed_form_radius.argtypes = [vp, vp, vp, i64, ctypes.c_double, ctypes.c_double, vp,
+                                        vp]
+    L.gs_closed_form_radius.restype = i32
     L._gs_mlp_bound = True
     return L
 
@@ -84,14 +87,30 @@ def features(plan: RasterPlan, chol, color, opacity, norm: Optional[gs_mlp_norm]
 
 
 def radius_labels(plan: RasterPlan, workspace, tau: float, capacity=None,
-                  stream=None) -> torch.Tensor:
-    """Training labels from the exact render's workspace (radius=None)."""
+                  stream=None, interior_only: bool = False) -> torch.Tensor:
+    """Training labels from the exact render's workspace (radius=None); with
+    interior_only, -1 for Gaussians whose support box the border cuts."""
     L = _bind()
     out = torch.empty(plan.n_gauss, dtype=torch.float32, device=workspace.device)
     cfg = plan.config(capacity)
     N.check(L.gs_radius_stats(ctypes.byref(cfg), plan._arr, len(plan.images), plan.n_gauss,
-                              _ptr(workspace), workspace.numel(), float(tau), _ptr(out),
-                              _stream(stream)), "radius stats")
+                              _ptr(workspace), workspace.numel(), float(tau),
+                              1 if interior_only else 0, _ptr(out), _stream(stream)),
+            "radius stats")
+    return out
+
+
+def closed_form_radius(chol, color, opacity, tau: float, margin: float = 0.0, out=None,
+                       stream=None) -> torch.Tensor:
+    """The support radius without the learned part (the control): where the
+    Gaussian's own peak contribution falls to tau, plus margin, capped at 3."""
+    L = _bind()
+    n = chol.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=chol.device)
+    N.check(L.gs_closed_form_radius(_ptr(chol), _ptr(color), _ptr(opacity), n, float(tau),
+                                    float(margin), _ptr(out), _stream(stream)),
+            "closed-form radius")
     return out
 
 

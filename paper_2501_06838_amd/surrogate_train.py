@@ -31,24 +31,11 @@ class Batch:
     labels: torch.Tensor   # [n]
 
 
-def _interior(images, mean, chol):
-    """Gaussians whose whole 3-sigma box lies inside their LR image: their
-    labels are not cut by the image border (host-side data selection)."""
-    keep = np.zeros(mean.shape[0], dtype=bool)
-    sy = np.sqrt(np.float64(chol[:, 1]) ** 2 + np.float64(chol[:, 2]) ** 2)
-    sx = np.float64(chol[:, 0])
-    for (h, w, s, gb, gc) in images:
-        sl = slice(gb, gb + gc)
-        mx, my = np.float64(mean[sl, 0]), np.float64(mean[sl, 1])
-        keep[sl] = ((mx - 3 * sx[sl] >= 0) & (mx + 3 * sx[sl] <= w - 1) &
-                    (my - 3 * sy[sl] >= 0) & (my + 3 * sy[sl] <= h - 1))
-    return keep
-
-
 def make_batches(make_batch: Callable, ks, tau: float, norm=None, device="cuda",
                  tile: int = 16, with_labels=True) -> List[Batch]:
     """Features (standardised with norm, raw without) and, optionally, labels
-    measured by the exact rasterizer, for the interior Gaussians of batches ks."""
+    measured by the exact rasterizer, for the Gaussians of batches ks whose
+    support box the image border does not cut (their labels are whole)."""
     out = []
     for k in ks:
         images, mean, chol, color, opacity = make_batch(k)
@@ -56,15 +43,13 @@ def make_batches(make_batch: Callable, ks, tau: float, norm=None, device="cuda",
         m, c, col, op = t(mean), t(chol), t(color), t(opacity)
         plan = RasterPlan(images, mean.shape[0], tile=tile)
         F = features(plan, c, col, op, norm)
-        lab = None
-        if with_labels:
-            plan.ensure_capacity(m, c)
-            ws = plan.new_workspace(device)
-            plan.bin(m, c, col, op, ws)
-            lab = radius_labels(plan, ws, tau)
-        idx = torch.from_numpy(np.nonzero(_interior(images, mean, chol))[0]).to(device)
+        plan.ensure_capacity(m, c)
+        ws = plan.new_workspace(device)
+        plan.bin(m, c, col, op, ws)
+        lab = radius_labels(plan, ws, tau, interior_only=True)
+        idx = torch.nonzero(lab >= 0).flatten()
         out.append(Batch(F.index_select(0, idx).contiguous(),
-                         None if lab is None else lab.index_select(0, idx).contiguous()))
+                         lab.index_select(0, idx).contiguous() if with_labels else None))
     return out
 
 

@@ -26,7 +26,7 @@ def test_library_exports_every_declared_symbol():
     for name in names:
         assert hasattr(lib, name), name
     assert set(names) == set(N.EXPORTED)
-    assert lib.gs_abi_version() == 1
+    assert lib.gs_abi_version() == 2
     assert N.status_string(-2) == "pair capacity exceeded"
 
 

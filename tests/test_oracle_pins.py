@@ -387,3 +387,37 @@ def test_support_pair_count_equals_brute_force_masks(s):
         count_r += int(mk[0].sum())
     assert total_r == count_r
     assert O.support_pairs_batch(wl) == O.support_rects(H, W, s, wl.mean, wl.chol)[1]
+
+
+def test_multithreaded_oracle_is_bitwise_serial():
+    """The OpenMP variants (row bands forward, Gaussians backward) give the
+    single-threaded oracle's values bit for bit."""
+    wl = synth.tiny(H=40, W=23, s=3.3, seed=5, extra_frac=0.3, sigma=(0.8, 0.5))
+    a = O.forward(40, 23, 3.3, wl.mean, wl.chol, wl.color, wl.opacity)
+    b = O.forward(40, 23, 3.3, wl.mean, wl.chol, wl.color, wl.opacity, threads=4)
+    assert np.array_equal(a, b)
+    G = np.random.default_rng(1).normal(size=a.shape)
+    ga = O.backward(40, 23, 3.3, wl.mean, wl.chol, wl.color, wl.opacity, G)
+    gb = O.backward(40, 23, 3.3, wl.mean, wl.chol, wl.color, wl.opacity, G, threads=4)
+    for x, y in zip(ga, gb):
+        assert np.array_equal(x, y)
+
+
+def test_box_cut_by_border_brute_force():
+    """The border cuts a support box iff some integer x (or y) passing the
+    strict window test s(mu - 3 sd) < x < s(mu + 3 sd) lies outside the
+    image; enumerated integer by integer over a wide range."""
+    H, W, s = 6, 7, 2.6
+    wl = synth.tiny(H=H, W=W, s=s, seed=13, extra_frac=0.5, sigma=(0.8, 0.5))
+    oh, ow = _out_size(H, W, s)
+    cut = O.box_cut(H, W, s, wl.mean, wl.chol)
+    ints = np.arange(-200, 400)
+    for i in range(wl.n_gauss):
+        l11, l21, l22 = np.float64(wl.chol[i])
+        sx, sy = l11, math.sqrt(l21 * l21 + l22 * l22)
+        mx, my = np.float64(wl.mean[i])
+        xs = ints[(s * (mx - 3 * sx) < ints) & (ints < s * (mx + 3 * sx))]
+        ys = ints[(s * (my - 3 * sy) < ints) & (ints < s * (my + 3 * sy))]
+        out = (xs < 0).any() or (xs > ow - 1).any() or (ys < 0).any() or (ys > oh - 1).any()
+        assert cut[i] == (1 if out else 0), i
+    assert 0 < (cut == 1).sum() < wl.n_gauss

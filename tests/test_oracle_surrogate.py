@@ -259,3 +259,34 @@ def test_rounding_is_identity_on_representable_values():
     gb = S.mlp_backward(cb, dout, rounding=False)
     assert np.array_equal(ga, gb)
     assert np.abs(ga).max() > 0
+
+
+def test_closed_form_radius_is_where_the_density_reaches_tau():
+    """At the closed-form distance R (below the cap), the Gaussian's own
+    contribution alpha max(c) f, with f from scipy's bivariate normal density
+    at mu + L (R u) for unit vectors u (Mahalanobis distance R), equals tau."""
+    rng = np.random.default_rng(3)
+    wl = synth.tiny(H=6, W=6, s=2.0, seed=9, sigma=(0.8, 0.5))
+    tau = 2e-3
+    R = S.closed_form_radius(wl.chol, wl.color, wl.opacity, tau)
+    hit = 0
+    for i in range(wl.n_gauss):
+        if not (0.0 < R[i] < 3.0):
+            continue
+        l11, l21, l22 = np.float64(wl.chol[i])
+        L = np.array([[l11, 0.0], [l21, l22]])
+        for th in rng.uniform(0, 2 * np.pi, 3):
+            u = np.array([np.cos(th), np.sin(th)])
+            p = np.float64(wl.mean[i]) + L @ (R[i] * u)
+            f = multivariate_normal(mean=np.float64(wl.mean[i]), cov=L @ L.T).pdf(p)
+            val = np.float64(wl.opacity[i]) * np.float64(wl.color[i]).max() * f
+            assert abs(val - tau) < 1e-9 * tau
+        hit += 1
+    assert hit > 10
+    assert (S.closed_form_radius(wl.chol, wl.color, wl.opacity, tau, margin=0.3) ==
+            np.clip(R + 0.3, 0, 3)).all()
+    big = S.closed_form_radius(wl.chol, wl.color, wl.opacity, 1e-30)
+    assert (big == 3.0).all()
+    bad = np.float64(wl.chol[:2]).copy()
+    bad[0, 0] = -1.0
+    assert S.closed_form_radius(bad, wl.color[:2], wl.opacity[:2], tau)[0] == 3.0
