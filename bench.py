@@ -315,7 +315,7 @@ def batched_uneven(G, synth, torch, np, reps):
         if key in done:  # the same launch is timed once
             out[name] = {"same_as": done[key]}
             continue
-        out[name] = step_record(B, cfg, reps, kernels=(name == "default_launch"))
+        out[name] = step_record(B, cfg, reps, kernels=True)
         done[key] = name
     out["launch"] = "each step captured as one HIP graph, replayed"
     return out
@@ -572,6 +572,7 @@ def main():
     if not args.no_batched:
         batched = batched_uneven(G, synth, torch, np, max(20, args.steps))
         d = batched["default_launch"]
+        d = batched[d["same_as"]] if "same_as" in d else d
         log(f"batched: default launch {d['mp_s']} MP/s")
     cpu = None
     if not args.no_cpu_baseline:

@@ -129,14 +129,17 @@ def pinball(pred, label, q):
     return loss, grad
 
 
-def adam(params, grad, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
-    """One Adam step (t counts from 1); returns FP32 (params, m, v)."""
+def adam(params, grad, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8, exact=False):
+    """One Adam step (t counts from 1); returns (params, m, v) in FP32, or
+    unrounded in FP64 with exact=True."""
     g = np.asarray(grad, np.float64)
     m = b1 * np.asarray(m, np.float64) + (1 - b1) * g
     v = b2 * np.asarray(v, np.float64) + (1 - b2) * g * g
     mh = m / (1 - b1 ** t)
     vh = v / (1 - b2 ** t)
     p = np.asarray(params, np.float64) - lr * mh / (np.sqrt(vh) + eps)
+    if exact:
+        return p, m, v
     return p.astype(np.float32), m.astype(np.float32), v.astype(np.float32)
 
 

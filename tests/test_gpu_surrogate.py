@@ -74,7 +74,7 @@ def test_mlp_gradient_parity(n):
     g = net.gradient(torch.from_numpy(X).cuda(), dout=torch.from_numpy(dout).cuda())
     g = g.cpu().numpy().astype(np.float64)
     _, _, st = B.forward_bound(params, X)
-    ref, err = B.backward_bound(st, np.float64(dout), np.zeros(n))
+    ref, err = B.backward_bound(st, np.asarray(dout, np.float64), np.zeros(n))
     for name, sl in NAMES:
         _check_bound(g[sl], ref[sl], err[sl], name)
 
@@ -105,9 +105,40 @@ def test_mlp_pinball_gradient():
         _check_bound(g[sl], ref[sl], err[sl], name)
 
 
+def _adam_bounds(p, m, v, g, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """Per-element radii of the kernel's FP32 Adam step (same FP32 inputs)
+    around the oracle's FP64 step.  The kernel holds b1, b2 and lr as FP32
+    numbers (their distance to the FP64 constants counts in full), rounds each
+    product and sum once (u = 2^-24), and takes powf and sqrtf within a few
+    ulps (4u is allowed for each)."""
+    u = 2.0 ** -24
+    p, m, v, g = (np.asarray(a, np.float64) for a in (p, m, v, g))
+    b1f, b2f, lrf = float(np.float32(b1)), float(np.float32(b2)), float(np.float32(lr))
+    m1 = b1 * m + (1 - b1) * g
+    v1 = b2 * v + (1 - b2) * g * g
+    e_m = abs(b1f - b1) * (np.abs(m) + np.abs(g)) + 2 * u * (np.abs(b1 * m) + np.abs((1 - b1) * g))
+    e_v = abs(b2f - b2) * (v + g * g) + 3 * u * (b2 * v + (1 - b2) * g * g)
+    d1, d2 = 1 - b1 ** t, 1 - b2 ** t
+    rel_d1 = (4 * u * b1 ** t + t * abs(b1f - b1)) / d1 + u
+    rel_d2 = (4 * u * b2 ** t + t * abs(b2f - b2)) / d2 + u
+    mh, vh = m1 / d1, v1 / d2
+    e_mh = e_m / d1 * (1 + rel_d1) + np.abs(mh) * (rel_d1 + u)
+    e_vh = e_v / d2 * (1 + rel_d2) + vh * (rel_d2 + u)
+    sq = np.sqrt(vh)
+    e_sq = e_vh / (2 * np.maximum(sq, 1e-300)) + 4 * u * sq
+    den = sq + eps
+    e_den = e_sq + u * den
+    upd = lr * mh / den
+    e_upd = abs(lrf - lr) * np.abs(mh) / den + lr * (
+        e_mh / den + np.abs(mh) * e_den / (den * (den - e_den))) + 3 * u * np.abs(upd)
+    p1 = p - upd
+    e_p = e_upd + u * np.abs(p1)
+    return e_p, e_m, e_v
+
+
 def test_mlp_adam_step():
-    """One Adam step of the kernel against the oracle's, both on the same
-    seeded gradient and moments."""
+    """Adam steps of the kernel against the oracle's, each from the same FP32
+    weights, moments and gradient, within the radii of the FP32 arithmetic."""
     from paper_2501_06838_amd.surrogate import RadiusMLP
     import ctypes
     from paper_2501_06838_amd import _native as N
@@ -120,17 +151,26 @@ def test_mlp_adam_step():
     v0 = (rng.uniform(0, 1e-4, 4801)).astype(np.float32)
     say("adam")
     net = RadiusMLP(params)
-    net.m.copy_(torch.from_numpy(m0))
-    net.v.copy_(torch.from_numpy(v0))
     gd = torch.from_numpy(g).cuda()
     L = _bind()
-    for t, lr in ((1, 1e-3), (7, 3e-3)):
+    for t, lr in ((1, 1e-3), (7, 3e-3), (1000, 1e-2)):
+        net.params.copy_(torch.from_numpy(np.asarray(params, np.float32)))
+        net.m.copy_(torch.from_numpy(m0))
+        net.v.copy_(torch.from_numpy(v0))
         N.check(L.gs_mlp_adam(_ptr(net.params), _ptr(net.m), _ptr(net.v), _ptr(gd), t,
                               ctypes.c_float(lr), _stream()), "adam")
+        e_p, e_m, e_v = _adam_bounds(params, m0, v0, g, t, lr)
+        p1, m1, v1 = S.adam(params, g, m0, v0, t, lr, exact=True)
+        for name, got, ref, err in (("params", net.params, p1, e_p), ("m", net.m, m1, e_m),
+                                    ("v", net.v, v1, e_v)):
+            got = got.cpu().numpy().astype(np.float64)
+            bad = np.abs(got - ref) > err
+            assert not bad.any(), f"t={t} {name}: {bad.sum()} outside the bound"
+            # the bound is tight: the FP32 step moves the weights by far more
+            if name == "params":
+                assert np.median(err / np.maximum(np.abs(p1 - params), 1e-30)) < 1e-3
+        # the next step starts from the oracle's FP32 state
         params, m0, v0 = S.adam(params, g, m0, v0, t, lr)
-        np.testing.assert_allclose(net.params.cpu().numpy(), params, rtol=1e-6, atol=1e-8)
-        np.testing.assert_allclose(net.m.cpu().numpy(), m0, rtol=1e-6, atol=1e-12)
-        np.testing.assert_allclose(net.v.cpu().numpy(), v0, rtol=1e-6, atol=1e-14)
 
 
 def test_features_parity():
