@@ -97,6 +97,36 @@ int or_support_rect(double s, int32_t out_w, int32_t out_h,
     return 1;
 }
 
+/* Support of one Gaussian under Algorithm 1's own window, the rasterization
+ * ratio r of Sec. 3.1 "Fast Rasterization": the strict test |x - mu_x| < r s H,
+ * |y - mu_y| < r s W, read with both sides in HR pixels (the HR centre is
+ * s mu) and each axis paired with its own image extent (x with W, y with H):
+ *     { x integer : s mx - r (s W) < x < s mx + r (s W) }, same for y with H,
+ * clipped to the image.  The Gaussian must still be valid (finite, l11 > 0,
+ * l22 > 0).  rect = {x0, x1, y0, y1}; returns 1 if non-empty, else 0. */
+int or_window_rect(double s, int32_t out_w, int32_t out_h, int32_t H, int32_t W, double r,
+                   double mx, double my, double l11, double l21, double l22, int32_t rect[4])
+{
+    rect[0] = 0; rect[1] = -1; rect[2] = 0; rect[3] = -1;
+    if (!isfinite(mx) || !isfinite(my) || !isfinite(l11) || !isfinite(l21) ||
+        !isfinite(l22) || !isfinite(r))
+        return 0;
+    if (!(l11 > 0.0) || !(l22 > 0.0) || !(r > 0.0)) return 0;
+    double hx = r * (s * (double)W);
+    double hy = r * (s * (double)H);
+    double cx = s * mx, cy = s * my;
+    double x0 = floor(cx - hx) + 1.0, x1 = ceil(cx + hx) - 1.0;
+    double y0 = floor(cy - hy) + 1.0, y1 = ceil(cy + hy) - 1.0;
+    if (x0 < 0.0) x0 = 0.0;
+    if (y0 < 0.0) y0 = 0.0;
+    if (x1 > (double)(out_w - 1)) x1 = (double)(out_w - 1);
+    if (y1 > (double)(out_h - 1)) y1 = (double)(out_h - 1);
+    if (x0 > x1 || y0 > y1) return 0;
+    rect[0] = (int32_t)x0; rect[1] = (int32_t)x1;
+    rect[2] = (int32_t)y0; rect[3] = (int32_t)y1;
+    return 1;
+}
+
 /* 1 if the image border cuts the support box of a valid Gaussian (some
  * integer x or y passing the strict window test lies outside the image),
  * 0 if the box lies inside the image, -1 if the Gaussian is invalid.  Used to
@@ -135,13 +165,26 @@ static double radius_of(const double* radius, int64_t i)
     return radius ? radius[i] : 3.0;
 }
 
+/* The support rect of Gaussian i: Algorithm 1's r-window when window_r > 0,
+ * else the box of radius[i] (NULL: 3) standard deviations per axis. */
+static int rect_of(int64_t i, int32_t H, int32_t W, double s, int32_t oh, int32_t ow,
+                   const double* mean, const double* chol, const double* radius,
+                   double window_r, int32_t r[4])
+{
+    if (window_r > 0.0)
+        return or_window_rect(s, ow, oh, H, W, window_r, mean[2 * i], mean[2 * i + 1],
+                              chol[3 * i], chol[3 * i + 1], chol[3 * i + 2], r);
+    return or_support_rect(s, ow, oh, mean[2 * i], mean[2 * i + 1], chol[3 * i],
+                           chol[3 * i + 1], chol[3 * i + 2], radius_of(radius, i), r);
+}
+
 /* Adds every Gaussian's contribution to the HR rows [y_lo, y_hi) of one image
  * (Algorithm 1's loops with Eq. 1, 2, 4, restricted to those rows): for each
  * Gaussian in ascending order, for each pixel of its support box in the rows,
  * out += alpha c f(x/s, y/s).  out is the whole [3][out_h][out_w] image. */
-static void forward_rows(int32_t oh, int32_t ow, double s, int64_t n,
+static void forward_rows(int32_t H, int32_t W, int32_t oh, int32_t ow, double s, int64_t n,
                          const double* mean, const double* chol, const double* color,
-                         const double* opacity, const double* radius,
+                         const double* opacity, const double* radius, double window_r,
                          int32_t y_lo, int32_t y_hi, double* out)
 {
     int64_t plane = (int64_t)oh * ow;
@@ -149,7 +192,7 @@ static void forward_rows(int32_t oh, int32_t ow, double s, int64_t n,
         const double mx = mean[2 * i], my = mean[2 * i + 1];
         const double l11 = chol[3 * i], l21 = chol[3 * i + 1], l22 = chol[3 * i + 2];
         int32_t r[4];
-        if (!or_support_rect(s, ow, oh, mx, my, l11, l21, l22, radius_of(radius, i), r)) continue;
+        if (!rect_of(i, H, W, s, oh, ow, mean, chol, radius, window_r, r)) continue;
         if (!isfinite(opacity[i]) || !isfinite(color[3 * i]) || !isfinite(color[3 * i + 1]) ||
             !isfinite(color[3 * i + 2]))
             continue;
@@ -169,16 +212,17 @@ static void forward_rows(int32_t oh, int32_t ow, double s, int64_t n,
 
 /* Forward render of one image (Algorithm 1 with Eq. 1, 2, 4).
  * mean [n][2] (mu_x, mu_y); chol [n][3] (l11, l21, l22); color [n][3];
- * opacity [n]; radius [n] or NULL (NULL = 3 standard deviations).
+ * opacity [n]; radius [n] or NULL (NULL = 3 standard deviations);
+ * window_r > 0 takes Algorithm 1's r-window instead (radius ignored).
  * out [3][out_h][out_w] is overwritten. */
 void or_forward(int32_t H, int32_t W, double s, int64_t n,
                 const double* mean, const double* chol, const double* color,
-                const double* opacity, const double* radius, double* out)
+                const double* opacity, const double* radius, double window_r, double* out)
 {
     int32_t oh, ow;
     if (or_output_size(H, W, s, &oh, &ow) != 0) return;
     memset(out, 0, sizeof(double) * 3 * (size_t)oh * (size_t)ow);
-    forward_rows(oh, ow, s, n, mean, chol, color, opacity, radius, 0, oh, out);
+    forward_rows(H, W, oh, ow, s, n, mean, chol, color, opacity, radius, window_r, 0, oh, out);
 }
 
 /* or_forward on up to nthreads host threads (OpenMP), for timing the oracle
@@ -187,7 +231,8 @@ void or_forward(int32_t H, int32_t W, double s, int64_t n,
  * that of or_forward. */
 void or_forward_mt(int32_t H, int32_t W, double s, int64_t n,
                    const double* mean, const double* chol, const double* color,
-                   const double* opacity, const double* radius, double* out, int32_t nthreads)
+                   const double* opacity, const double* radius, double window_r, double* out,
+                   int32_t nthreads)
 {
     int32_t oh, ow;
     if (or_output_size(H, W, s, &oh, &ow) != 0) return;
@@ -198,7 +243,8 @@ void or_forward_mt(int32_t H, int32_t W, double s, int64_t n,
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
     for (int32_t b = 0; b < nb; ++b) {
         const int32_t y1 = (b + 1) * band < oh ? (b + 1) * band : oh;
-        forward_rows(oh, ow, s, n, mean, chol, color, opacity, radius, b * band, y1, out);
+        forward_rows(H, W, oh, ow, s, n, mean, chol, color, opacity, radius, window_r, b * band,
+                     y1, out);
     }
 }
 
@@ -220,9 +266,10 @@ void or_forward_mt(int32_t H, int32_t W, double s, int64_t n,
  * Outputs are overwritten: grad_mean [n][2], grad_chol [n][3],
  * grad_color [n][3], grad_opacity [n]. */
 /* The gradients of Gaussian i (see or_backward). */
-static void backward_one(int64_t i, int32_t oh, int32_t ow, double s,
+static void backward_one(int64_t i, int32_t H, int32_t W, int32_t oh, int32_t ow, double s,
                          const double* mean, const double* chol, const double* color,
-                         const double* opacity, const double* radius, const double* grad_out,
+                         const double* opacity, const double* radius, double window_r,
+                         const double* grad_out,
                          double* grad_mean, double* grad_chol, double* grad_color,
                          double* grad_opacity)
 {
@@ -232,7 +279,7 @@ static void backward_one(int64_t i, int32_t oh, int32_t ow, double s,
     const double al = opacity[i];
     const double* c = color + 3 * i;
     int32_t r[4];
-    if (!or_support_rect(s, ow, oh, mx, my, l11, l21, l22, radius_of(radius, i), r)) return;
+    if (!rect_of(i, H, W, s, oh, ow, mean, chol, radius, window_r, r)) return;
     if (!isfinite(al) || !isfinite(c[0]) || !isfinite(c[1]) || !isfinite(c[2])) return;
     double sx, sy, rho;
     chol_to_eq2(l11, l21, l22, &sx, &sy, &rho);
@@ -273,7 +320,8 @@ static void backward_one(int64_t i, int32_t oh, int32_t ow, double s,
 
 void or_backward(int32_t H, int32_t W, double s, int64_t n,
                  const double* mean, const double* chol, const double* color,
-                 const double* opacity, const double* radius, const double* grad_out,
+                 const double* opacity, const double* radius, double window_r,
+                 const double* grad_out,
                  double* grad_mean, double* grad_chol, double* grad_color, double* grad_opacity)
 {
     int32_t oh, ow;
@@ -283,8 +331,8 @@ void or_backward(int32_t H, int32_t W, double s, int64_t n,
     memset(grad_opacity, 0, sizeof(double) * (size_t)n);
     if (or_output_size(H, W, s, &oh, &ow) != 0) return;
     for (int64_t i = 0; i < n; ++i)
-        backward_one(i, oh, ow, s, mean, chol, color, opacity, radius, grad_out, grad_mean,
-                     grad_chol, grad_color, grad_opacity);
+        backward_one(i, H, W, oh, ow, s, mean, chol, color, opacity, radius, window_r, grad_out,
+                     grad_mean, grad_chol, grad_color, grad_opacity);
 }
 
 /* or_backward on up to nthreads host threads (OpenMP), for timing the
@@ -292,7 +340,8 @@ void or_backward(int32_t H, int32_t W, double s, int64_t n,
  * that of or_backward. */
 void or_backward_mt(int32_t H, int32_t W, double s, int64_t n,
                     const double* mean, const double* chol, const double* color,
-                    const double* opacity, const double* radius, const double* grad_out,
+                    const double* opacity, const double* radius, double window_r,
+                    const double* grad_out,
                     double* grad_mean, double* grad_chol, double* grad_color,
                     double* grad_opacity, int32_t nthreads)
 {
@@ -305,8 +354,8 @@ void or_backward_mt(int32_t H, int32_t W, double s, int64_t n,
     if (nthreads < 1) nthreads = 1;
 #pragma omp parallel for schedule(dynamic, 256) num_threads(nthreads)
     for (int64_t i = 0; i < n; ++i)
-        backward_one(i, oh, ow, s, mean, chol, color, opacity, radius, grad_out, grad_mean,
-                     grad_chol, grad_color, grad_opacity);
+        backward_one(i, H, W, oh, ow, s, mean, chol, color, opacity, radius, window_r, grad_out,
+                     grad_mean, grad_chol, grad_color, grad_opacity);
 }
 
 /* Tile lists of one image: tiles are tw x th HR pixels, numbered row-major
@@ -319,7 +368,8 @@ void or_backward_mt(int32_t H, int32_t W, double s, int64_t n,
  * order again and append each to its tiles' lists. */
 int64_t or_tile_lists(int32_t H, int32_t W, double s, int64_t n,
                       const double* mean, const double* chol, const double* radius,
-                      int32_t tw, int32_t th, int32_t* counts, int32_t* lists, int64_t cap)
+                      double window_r, int32_t tw, int32_t th, int32_t* counts, int32_t* lists,
+                      int64_t cap)
 {
     int32_t oh, ow;
     if (tw < 1 || th < 1 || or_output_size(H, W, s, &oh, &ow) != 0) return -1;
@@ -330,9 +380,7 @@ int64_t or_tile_lists(int32_t H, int32_t W, double s, int64_t n,
     int64_t total = 0;
     for (int64_t i = 0; i < n; ++i) {
         int32_t r[4];
-        if (!or_support_rect(s, ow, oh, mean[2 * i], mean[2 * i + 1], chol[3 * i],
-                             chol[3 * i + 1], chol[3 * i + 2], radius_of(radius, i), r))
-            continue;
+        if (!rect_of(i, H, W, s, oh, ow, mean, chol, radius, window_r, r)) continue;
         for (int32_t ty = r[2] / th; ty <= r[3] / th; ++ty)
             for (int32_t tx = r[0] / tw; tx <= r[1] / tw; ++tx) {
                 counts[(int64_t)ty * tiles_x + tx] += 1;
@@ -348,9 +396,7 @@ int64_t or_tile_lists(int32_t H, int32_t W, double s, int64_t n,
     for (int64_t t = 0; t < n_tiles; ++t) { fill[t] = start; start += counts[t]; }
     for (int64_t i = 0; i < n; ++i) {
         int32_t r[4];
-        if (!or_support_rect(s, ow, oh, mean[2 * i], mean[2 * i + 1], chol[3 * i],
-                             chol[3 * i + 1], chol[3 * i + 2], radius_of(radius, i), r))
-            continue;
+        if (!rect_of(i, H, W, s, oh, ow, mean, chol, radius, window_r, r)) continue;
         for (int32_t ty = r[2] / th; ty <= r[3] / th; ++ty)
             for (int32_t tx = r[0] / tw; tx <= r[1] / tw; ++tx)
                 lists[fill[(int64_t)ty * tiles_x + tx]++] = (int32_t)i;
@@ -363,15 +409,14 @@ int64_t or_tile_lists(int32_t H, int32_t W, double s, int64_t n,
  * boxes themselves (rects [n][4] may be NULL). */
 int64_t or_support_pairs(int32_t H, int32_t W, double s, int64_t n,
                          const double* mean, const double* chol, const double* radius,
-                         int32_t* rects)
+                         double window_r, int32_t* rects)
 {
     int32_t oh, ow;
     if (or_output_size(H, W, s, &oh, &ow) != 0) return -1;
     int64_t total = 0;
     for (int64_t i = 0; i < n; ++i) {
         int32_t r[4];
-        int ok = or_support_rect(s, ow, oh, mean[2 * i], mean[2 * i + 1], chol[3 * i],
-                                 chol[3 * i + 1], chol[3 * i + 2], radius_of(radius, i), r);
+        int ok = rect_of(i, H, W, s, oh, ow, mean, chol, radius, window_r, r);
         if (rects) memcpy(rects + 4 * i, r, sizeof r);
         if (ok) total += (int64_t)(r[1] - r[0] + 1) * (r[3] - r[2] + 1);
     }
@@ -384,7 +429,7 @@ int64_t or_support_pairs(int32_t H, int32_t W, double s, int64_t n,
  * to evaluate whole. */
 void or_pixel_values(int32_t H, int32_t W, double s, int64_t n,
                      const double* mean, const double* chol, const double* color,
-                     const double* opacity, const double* radius,
+                     const double* opacity, const double* radius, double window_r,
                      int64_t npix, const int32_t* xs, const int32_t* ys, double* out)
 {
     int32_t oh, ow;
@@ -394,7 +439,7 @@ void or_pixel_values(int32_t H, int32_t W, double s, int64_t n,
         const double mx = mean[2 * i], my = mean[2 * i + 1];
         const double l11 = chol[3 * i], l21 = chol[3 * i + 1], l22 = chol[3 * i + 2];
         int32_t r[4];
-        if (!or_support_rect(s, ow, oh, mx, my, l11, l21, l22, radius_of(radius, i), r)) continue;
+        if (!rect_of(i, H, W, s, oh, ow, mean, chol, radius, window_r, r)) continue;
         if (!isfinite(opacity[i]) || !isfinite(color[3 * i]) || !isfinite(color[3 * i + 1]) ||
             !isfinite(color[3 * i + 2]))
             continue;
