@@ -174,11 +174,12 @@ def cpu_baseline(wl, seconds: float):
 class Bench:
     """Device-resident inputs of one workload and helpers to time its step."""
 
-    def __init__(self, G, synth, torch, np, name, seed=0):
+    def __init__(self, G, synth, torch, np, name, seed=0, wl=None, window=0.0):
         self.G, self.torch, self.np = G, torch, np
         self.dev = torch.device("cuda:0")
         self.name = name
-        self.wl = synth.by_name(name, seed=seed, with_target=True)
+        self.window = window
+        self.wl = wl if wl is not None else synth.by_name(name, seed=seed, with_target=True)
         t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(self.dev)
         wl = self.wl
         self.mean, self.chol, self.color, self.opacity = (t(wl.mean), t(wl.chol), t(wl.color),
@@ -197,7 +198,7 @@ class Bench:
         return ws, out, grads, loss
 
     def plan(self, launch, radius=None, headroom=1.0):
-        plan = self.G.RasterPlan(self.imgs, self.n, **launch)
+        plan = self.G.RasterPlan(self.imgs, self.n, window=self.window, **launch)
         pairs = plan.ensure_capacity(self.mean, self.chol, radius, headroom=headroom)
         return plan, pairs
 
@@ -273,7 +274,7 @@ def step_record(B, launch, reps, kernels=True):
         raise SystemExit(f"pair capacity overflow during replay ({B.name})")
     graph.close()
     hr_px = plan.out_numel // 3
-    rec = {"workload": f"{B.name}: {WORKLOADS[B.name]}", "ms_per_step": round(ms, 5),
+    rec = {"workload": f"{B.name}: {WORKLOADS.get(B.name, B.name)}", "ms_per_step": round(ms, 5),
            "brackets_ms": [round(x, 5) for x in brackets], "replays_per_bracket": reps,
            "mp_s": round(hr_px / (ms * 1e-3) / 1e6, 2), "hr_pixels": hr_px,
            "gaussians": B.n, "tile_pairs": npairs, "support_pairs": n_support,
@@ -319,6 +320,122 @@ def batched_uneven(G, synth, torch, np, reps):
         done[key] = name
     out["launch"] = "each step captured as one HIP graph, replayed"
     return out
+
+
+def forward_record(B, launch, reps):
+    """Captured forward-only pass (binning + tile render) of one workload:
+    median of three brackets of reps replays, and the forward tile kernel's
+    HIP-event time."""
+    torch = B.torch
+    plan, _ = B.plan(launch)
+    ws, out = plan.new_workspace(B.dev), plan.new_output(B.dev)
+    graph = B.G.StepGraph(plan, B.mean, B.chol, B.color, B.opacity, ws, out)
+    for _ in range(3):
+        graph.launch()
+    ms, brackets = time_graph(torch, graph.launch, reps)
+    if plan.diagnostics(ws)[1]:
+        raise SystemExit(f"pair capacity overflow ({B.name})")
+    graph.close()
+    npairs, _, _, n_support = plan.diagnostics(ws, support=True)
+    stream = torch.cuda.current_stream()
+    fwd = kernel_ms(torch, stream, lambda: plan.render(ws, out), reps)
+    hr_px = plan.out_numel // 3
+    tf = n_support * FLOPEQ_FWD / (fwd * 1e-3) / 1e12
+    del ws, out
+    return {"ms_per_pass": round(ms, 5), "brackets_ms": [round(x, 5) for x in brackets],
+            "mp_s": round(hr_px / (ms * 1e-3) / 1e6, 2), "tile_pairs": npairs,
+            "support_pairs": n_support, "fwd_kernel_us": round(fwd * 1e3, 2),
+            "fwd_kernel_tflops": round(tf, 3),
+            "fwd_kernel_frac": round(tf / PEAK_FP32_VECTOR_TFLOPS, 4)}
+
+
+# The paper's render-only forward times on an A100 (supplement, "Rendering
+# Cost Comparison", 720x720 GT, r = 0.1): context, another machine.
+PAPER_RENDER_MS = {4: 168.0, 8: 71.0}
+
+
+def paper_window(G, synth, torch, np, scales, reps):
+    """Algorithm 1's r-window (r = 0.1) on the paper's cost workload (720x720
+    output, m = 16 Gaussians per LR pixel): the forward-only pass the paper
+    times, and the fwd+bwd training step, each captured as one graph."""
+    out = []
+    for s in scales:
+        wl = synth.paper720(s, seed=0, with_target=True)
+        log(f"paper720 x{s}: {wl.n_gauss} Gaussians, r = 0.1")
+        B = Bench(G, synth, torch, np, f"paper720_x{s}", wl=wl, window=0.1)
+        launch = {"tile": 16, "lds_batch": 96, "flags": 0}
+        fwd = forward_record(B, launch, reps)
+        step = step_record(B, launch, reps)
+        rec = {"workload": f"paper720_x{s}: {wl.images[0].lr_h}x{wl.images[0].lr_w} LR, "
+                           f"{wl.n_gauss} Gaussians (16 per LR pixel) -> 720x720 at s={s}, "
+                           f"r-window r = 0.1",
+               "forward": fwd, "fwd_bwd_step": step}
+        if s in PAPER_RENDER_MS:
+            rec["paper_render_ms_a100"] = PAPER_RENDER_MS[s]
+            rec["forward_vs_paper_render"] = round(PAPER_RENDER_MS[s] / fwd["ms_per_pass"], 1)
+        log(f"  forward {fwd['ms_per_pass']} ms, fwd+bwd {step['ms_per_step']} ms "
+            f"(paper's A100 render: {PAPER_RENDER_MS.get(s)} ms)")
+        out.append(rec)
+        del B
+    return out
+
+
+def head_and_psnr(G, synth, torch, np, reps):
+    """The Gaussian primary head (forward + backward) on the paper's x4
+    workload size (518,400 Gaussians) and the Y-channel PSNR of two
+    2048x2048 renders: HIP-event times against the HBM peak."""
+    from paper_2501_06838_amd.head import head_images, psnr_y
+    from paper_2501_06838_amd import _native as N
+    from paper_2501_06838_amd.raster import _ptr, _stream
+    import ctypes
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    grid, H = 4, 180
+    images = head_images([(H, H)], grid)
+    n = images[0][3]
+    g = torch.Generator(device=dev).manual_seed(5)
+    raw = [torch.randn(sh, device=dev, generator=g) for sh in [(n,), (n, 3), (n, 2), (n,),
+                                                               (n, 2)]]
+    outs = [torch.empty(sh, device=dev) for sh in [(n, 2), (n, 3), (n, 3), (n,)]]
+    grads = [torch.randn(sh, device=dev, generator=g) for sh in [(n, 2), (n, 3), (n, 3), (n,)]]
+    d = [torch.empty(sh, device=dev) for sh in [(n,), (n, 3), (n, 2), (n,), (n, 2)]]
+    arr = (N.gs_image * 1)(N.gs_image(H, H, 1.0, 0, n, 0))
+    L = N.lib()
+
+    def fwd():
+        N.check(L.gs_gaussian_head_forward(arr, 1, grid, *[_ptr(t) for t in raw], n,
+                                           *[_ptr(t) for t in outs], _stream()), "head")
+
+    def bwd():
+        N.check(L.gs_gaussian_head_backward(n, *[_ptr(t) for t in raw[:4]],
+                                            *[_ptr(t) for t in grads], *[_ptr(t) for t in d],
+                                            _stream()), "head bwd")
+    fwd(), bwd()
+    f_ms = kernel_ms(torch, stream, fwd, reps)
+    b_ms = kernel_ms(torch, stream, bwd, reps)
+    f_bytes, b_bytes = 72.0 * n, 100.0 * n
+    head = {"gaussians": n, "grid": grid,
+            "forward": {"us": round(f_ms * 1e3, 2), "bytes": f_bytes,
+                        "gb_s": round(f_bytes / (f_ms * 1e-3) / 1e9, 1),
+                        "frac_hbm": round(f_bytes / (f_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)},
+            "backward": {"us": round(b_ms * 1e3, 2), "bytes": b_bytes,
+                         "gb_s": round(b_bytes / (b_ms * 1e-3) / 1e9, 1),
+                         "frac_hbm": round(b_bytes / (b_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}}
+    del raw, outs, grads, d
+    plan = G.RasterPlan([(512, 512, 4.0, 0, 0)], 0)
+    a = torch.rand(plan.out_numel, device=dev, generator=g)
+    b = (a + 0.01 * torch.randn(plan.out_numel, device=dev, generator=g)).contiguous()
+    psnr_y(plan, a, b)
+    p_ms = kernel_ms(torch, stream, lambda: psnr_y(plan, a, b), reps)
+    p_bytes = 24.0 * plan.out_numel // 3
+    p, _ = psnr_y(plan, a, b)
+    ps = {"hr_pixels": plan.out_numel // 3, "us": round(p_ms * 1e3, 2), "psnr_db": round(p.item(), 3),
+          "bytes": p_bytes, "gb_s": round(p_bytes / (p_ms * 1e-3) / 1e9, 1),
+          "frac_hbm": round(p_bytes / (p_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+          "note": "three launches per call (clear, sums, PSNR)"}
+    log(f"head fwd {head['forward']['gb_s']} GB/s, bwd {head['backward']['gb_s']} GB/s; "
+        f"psnr_y {ps['gb_s']} GB/s")
+    return {"gaussian_head": head, "psnr_y_2048": ps}
 
 
 def calibrate_control(G, synth, torch, np, tau, target_db=50.5):
@@ -459,6 +576,10 @@ def main():
                     help="skip the other single workloads (config1, config2b)")
     ap.add_argument("--pruned-workload", default="config2a,config2b",
                     help="comma-separated, from config2a, config2b")
+    ap.add_argument("--no-paper", action="store_true",
+                    help="skip the r-window paper-shaped workloads and the head / PSNR kernels")
+    ap.add_argument("--paper-scales", default="4,8",
+                    help="comma-separated integer scales of the 720x720 r-window workload")
     ap.add_argument("--calibration-copy", type=int, default=0, metavar="MIB",
                     help="finish with 5 plain device-to-device copies of MIB MiB (a known "
                          "byte count for scaling hardware traffic counters)")
@@ -574,6 +695,12 @@ def main():
         d = batched["default_launch"]
         d = batched[d["same_as"]] if "same_as" in d else d
         log(f"batched: default launch {d['mp_s']} MP/s")
+    paper = extras = None
+    if not args.no_paper:
+        paper = paper_window(G, synth, torch, np,
+                             [int(x) for x in args.paper_scales.split(",") if x.strip()],
+                             args.steps)
+        extras = head_and_psnr(G, synth, torch, np, max(20, args.steps))
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline")
@@ -590,6 +717,7 @@ def main():
                    "launch": "whole step captured in one HIP graph, replayed"},
         "roofline": roofline, "cpu_baseline": cpu, "surrogate_pruned": pruned,
         "workloads": others, "batched_uneven": batched, "binning": binning,
+        "paper_window": paper, "head_psnr": extras,
     }
     print(json.dumps(rec), flush=True)
     if args.calibration_copy > 0:

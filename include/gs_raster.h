@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define GS_ABI_VERSION 2
+#define GS_ABI_VERSION 3
 
 typedef int32_t gs_status;
 enum {
@@ -84,6 +84,16 @@ typedef struct {
     int32_t reserved;
     int64_t pair_capacity; /* max (tile, Gaussian) pairs the workspace holds;
                               0 = n_gauss * 16 (use gs_count_pairs to size)  */
+    double window_r;       /* 0: each Gaussian's support is the box of R
+                              standard deviations (R = 3, or the radius
+                              array of the pruned path).  > 0: Algorithm 1's
+                              own window with rasterization ratio r
+                              (Sec. 3.1 "Fast Rasterization"): the strict
+                              test |x - s mu_x| < r s W, |y - s mu_y| < r s H
+                              in HR pixels, each axis with its own extent,
+                              the same for every Gaussian of an image; the
+                              radius array must then be NULL.  Negative or
+                              non-finite: GS_E_INVALID.                      */
 } gs_config;
 
 /* flags */
@@ -381,6 +391,61 @@ gs_status gs_sq_error(const float* a, const float* b, int64_t n, double* sum, vo
 /* Opaque executable graph of one whole pass over a fixed batch layout and
  * fixed device pointers. */
 typedef struct gs_graph_s* gs_graph;
+
+/* ---- Gaussian primary head (Sec. 3.2, "Gaussian Primary Head" and
+ * "Gaussian Embedding") ------------------------------------------------------
+ * Turns the raw outputs of the five property heads into the rasterizer's
+ * inputs, per Gaussian:
+ *     alpha = sigmoid(a), c = sigmoid(r) per channel, sigma = sigmoid(u) per
+ *     axis, rho = tanh(v), mu = p + o (no activation on the offset o),
+ *     chol = (sigma_x, rho sigma_y, sigma_y sqrt(1 - rho^2)).
+ * p is the Gaussian's reference position: image k holds grid^2 H W Gaussians
+ * (the paper's m = grid^2 per LR pixel), entry j of its range (row-major)
+ * sits at the centre of cell (j mod grid W, j div grid W) of a
+ * (grid H) x (grid W) grid of equal cells over the image area
+ * [-1/2, W - 1/2] x [-1/2, H - 1/2]: p = ((2 col + 1 - grid) / (2 grid), same
+ * for the row).  Device arrays, FP32, C-contiguous:
+ *   raw_opacity [N], raw_color [N][3], raw_sigma [N][2], raw_rho [N],
+ *   offset [N][2]; outputs mean [N][2], chol [N][3], color [N][3],
+ *   opacity [N] (the layouts of gs_raster_forward).
+ * images: host array; only lr_h, lr_w, g_begin and g_count are read; each
+ * g_count must be grid^2 lr_h lr_w, ranges ascending and disjoint within
+ * [0, n_gauss) (GS_E_INVALID otherwise; GS_E_UNSUPPORTED if grid * max(H, W)
+ * >= 2^23).  Gaussians between the images' ranges are left untouched.  A raw
+ * rho so large that tanh rounds to +-1 gives l22 = 0 (no support). */
+gs_status gs_gaussian_head_forward(const gs_image* images, int32_t n_img, int32_t grid,
+                                   const float* raw_opacity, const float* raw_color,
+                                   const float* raw_sigma, const float* raw_rho,
+                                   const float* offset, int64_t n_gauss, float* mean,
+                                   float* chol, float* color, float* opacity, void* stream);
+
+/* Backward of gs_gaussian_head_forward: from the gradients w.r.t. mean,
+ * chol, color and opacity (e.g. gs_raster_backward's), the gradients w.r.t.
+ * the raw outputs (overwritten; the layouts of the raw inputs):
+ *   d_opacity = g_opacity sigmoid'(a), d_color = g_color sigmoid'(r),
+ *   d_sigma = (g_l11, g_l21 rho + g_l22 sqrt(1 - rho^2)) sigmoid'(u),
+ *   d_rho = (g_l21 sigma_y - g_l22 sigma_y rho / sqrt(1 - rho^2)) (1 - rho^2),
+ *   d_offset = g_mean. */
+gs_status gs_gaussian_head_backward(int64_t n_gauss, const float* raw_opacity,
+                                    const float* raw_color, const float* raw_sigma,
+                                    const float* raw_rho, const float* grad_mean,
+                                    const float* grad_chol, const float* grad_color,
+                                    const float* grad_opacity, float* d_opacity,
+                                    float* d_color, float* d_sigma, float* d_rho,
+                                    float* d_offset, void* stream);
+
+/* ---- Y-channel PSNR (Sec. 4.1, evaluation protocols) ------------------------
+ * Per image k of the batch layout (images as for gs_raster_forward: the
+ * planar [3][out_h][out_w] block at out_offset of test and ref, device FP32,
+ * RGB on [0, 1]): the BT.601 luma Y = (16 + 65.481 R + 128.553 G +
+ * 24.966 B) / 255 of both, the sum of squared Y differences over the pixels
+ * at least `crop` pixels inside every border (FP64; written to sse[k]) and
+ * psnr[k] = 10 log10(count / sse[k]) (+inf for equal images, NaN when the
+ * crop leaves no pixel).  sse and psnr: device double [n_img], overwritten.
+ * No clamping or quantisation.  Partial sums are added with FP64 atomics, so
+ * the last bits of sse may differ between calls. */
+gs_status gs_psnr_y(const gs_image* images, int32_t n_img, const float* test, const float* ref,
+                    int32_t crop, double* sse, double* psnr, void* stream);
 
 /* Captures, on a private stream, gs_raster_step_l1 (when target is not
  * NULL) or gs_raster_forward (when it is) with the same arguments, and

@@ -19,7 +19,7 @@ GS_E_DEVICE = -3
 GS_E_UNSUPPORTED = -4
 GS_E_WORKSPACE = -5
 
-ABI_VERSION = 2  # GS_ABI_VERSION of include/gs_raster.h
+ABI_VERSION = 3  # GS_ABI_VERSION of include/gs_raster.h
 
 GS_FLAG_PERSISTENT = 0x1
 GS_FLAG_ATOMIC_GRADS = 0x2
@@ -33,7 +33,9 @@ EXPORTED = (
     "gs_l1_loss_value", "gs_raster_backward_l1", "gs_graph_create", "gs_graph_launch",
     "gs_graph_destroy", "gs_mlp_features", "gs_mlp_forward", "gs_mlp_workspace_size",
     "gs_mlp_grad", "gs_mlp_adam", "gs_radius_stats", "gs_sq_error", "gs_tile_order",
-    "gs_raster_render_fused_l1", "gs_raster_step_l1", "gs_mlp_radius", "gs_closed_form_radius",
+    "gs_raster_render_fused_l1", "gs_raster_step_l1",
+    "gs_mlp_radius", "gs_closed_form_radius", "gs_gaussian_head_forward",
+    "gs_gaussian_head_backward", "gs_psnr_y",
 )
 
 
@@ -46,7 +48,7 @@ class gs_image(ctypes.Structure):
 class gs_config(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("lds_batch", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("pair_capacity", ctypes.c_int64)]
+                ("pair_capacity", ctypes.c_int64), ("window_r", ctypes.c_double)]
 
 
 class GSError(RuntimeError):
@@ -124,6 +126,13 @@ def lib():
         L.gs_raster_step_l1.argtypes = [_cfgp, _imgp, _i32, _vp, _vp, _vp, _vp, _vp, _i64, _vp,
                                         _sz, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
         L.gs_raster_step_l1.restype = _i32
+        L.gs_gaussian_head_forward.argtypes = [_imgp, _i32, _i32] + [_vp] * 5 + [_i64] + \
+            [_vp] * 5
+        L.gs_gaussian_head_forward.restype = _i32
+        L.gs_gaussian_head_backward.argtypes = [_i64] + [_vp] * 14
+        L.gs_gaussian_head_backward.restype = _i32
+        L.gs_psnr_y.argtypes = [_imgp, _i32, _vp, _vp, _i32, _vp, _vp, _vp]
+        L.gs_psnr_y.restype = _i32
         L.gs_graph_create.argtypes = [_cfgp, _imgp, _i32, _vp, _vp, _vp, _vp, _vp, _i64, _vp,
                                       _sz, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                       ctypes.POINTER(_vp)]

@@ -51,6 +51,8 @@ gs_status make_layout(const gs_config* cfg, const gs_image* images, int32_t n_im
     l.flags = cfg ? cfg->flags : 0;
     if (l.flags & ~(GS_FLAG_PERSISTENT | GS_FLAG_ATOMIC_GRADS | GS_FLAG_RADIX_SORT))
         return GS_E_INVALID;
+    l.window_r = cfg ? cfg->window_r : 0.0;
+    if (!std::isfinite(l.window_r) || l.window_r < 0.0) return GS_E_INVALID;
     l.n_img = n_img;
     l.n_gauss = n_gauss;
 
@@ -77,6 +79,8 @@ gs_status make_layout(const gs_config* cfg, const gs_image* images, int32_t n_im
         d.g_count = im.g_count;
         d.tile_base = tiles;
         d.scale = im.scale;
+        d.lr_w = im.lr_w;
+        d.lr_h = im.lr_h;
         tiles += (int64_t)d.tiles_x * d.tiles_y;
     }
     std::sort(blocks.begin(), blocks.end());
@@ -162,6 +166,7 @@ gs_status dev(hipError_t e) { return e == hipSuccess ? GS_OK : GS_E_DEVICE; }
 gs_status run_binning(const Layout& L, const Ws& w, const std::vector<ImgDev>& table,
                       const float* mean, const float* chol, const float* color,
                       const float* opacity, const float* radius, hipStream_t st) {
+    if (radius && L.window_r > 0.0) return GS_E_INVALID;  // one support rule at a time
     GS_TRY(dev(launch_support(L, w, table.data(), mean, chol, color, opacity, radius, false,
                               st)));
     GS_TRY(dev(launch_emit(L, w, st)));
@@ -398,6 +403,7 @@ gs_status gs_count_pairs(const gs_config* cfg, const gs_image* images, int32_t n
     c.pair_capacity = 1;
     GS_TRY(make_layout(&c, images, n_img, n_gauss, &L, &table));
     if (n_gauss > 0 && (!mean || !chol)) return GS_E_INVALID;
+    if (radius && L.window_r > 0.0) return GS_E_INVALID;
     if (!workspace || ws_bytes < counting_bytes(L)) return GS_E_WORKSPACE;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const Ws w = bind(L, workspace);
@@ -548,6 +554,65 @@ gs_status gs_sq_error(const float* a, const float* b, int64_t n, double* sum, vo
     return dev(launch_sq_error(a, b, n, sum, static_cast<hipStream_t>(stream)));
 }
 
+gs_status gs_gaussian_head_forward(const gs_image* images, int32_t n_img, int32_t grid,
+                                   const float* raw_opacity, const float* raw_color,
+                                   const float* raw_sigma, const float* raw_rho,
+                                   const float* offset, int64_t n_gauss, float* mean,
+                                   float* chol, float* color, float* opacity, void* stream) {
+    if (n_img < 1 || !images || grid < 1 || n_gauss < 0) return GS_E_INVALID;
+    int64_t prev_end = 0;
+    for (int k = 0; k < n_img; ++k) {
+        const gs_image& im = images[k];
+        if (im.lr_h < 1 || im.lr_w < 1) return GS_E_INVALID;
+        // grid coordinates stay exact in FP32
+        if ((int64_t)grid * std::max(im.lr_h, im.lr_w) >= (1 << 23)) return GS_E_UNSUPPORTED;
+        if (im.g_count != (int64_t)grid * grid * im.lr_h * im.lr_w) return GS_E_INVALID;
+        if (im.g_begin < prev_end || im.g_begin + im.g_count > n_gauss) return GS_E_INVALID;
+        prev_end = im.g_begin + im.g_count;
+    }
+    if (n_gauss > 0 && (!raw_opacity || !raw_color || !raw_sigma || !raw_rho || !offset ||
+                        !mean || !chol || !color || !opacity))
+        return GS_E_INVALID;
+    return dev(launch_head_fwd(images, n_img, grid, raw_opacity, raw_color, raw_sigma, raw_rho,
+                               offset, mean, chol, color, opacity,
+                               static_cast<hipStream_t>(stream)));
+}
+
+gs_status gs_gaussian_head_backward(int64_t n_gauss, const float* raw_opacity,
+                                    const float* raw_color, const float* raw_sigma,
+                                    const float* raw_rho, const float* grad_mean,
+                                    const float* grad_chol, const float* grad_color,
+                                    const float* grad_opacity, float* d_opacity,
+                                    float* d_color, float* d_sigma, float* d_rho,
+                                    float* d_offset, void* stream) {
+    if (n_gauss < 0) return GS_E_INVALID;
+    if (n_gauss > 0 && (!raw_opacity || !raw_color || !raw_sigma || !raw_rho || !grad_mean ||
+                        !grad_chol || !grad_color || !grad_opacity || !d_opacity ||
+                        !d_color || !d_sigma || !d_rho || !d_offset))
+        return GS_E_INVALID;
+    return dev(launch_head_bwd(n_gauss, raw_opacity, raw_color, raw_sigma, raw_rho, grad_mean,
+                               grad_chol, grad_color, grad_opacity, d_opacity, d_color, d_sigma,
+                               d_rho, d_offset, static_cast<hipStream_t>(stream)));
+}
+
+gs_status gs_psnr_y(const gs_image* images, int32_t n_img, const float* test, const float* ref,
+                    int32_t crop, double* sse, double* psnr, void* stream) {
+    if (n_img < 1 || !images || crop < 0 || !test || !ref || !sse || !psnr)
+        return GS_E_INVALID;
+    std::vector<std::pair<int64_t, int64_t>> blocks;
+    for (int k = 0; k < n_img; ++k) {
+        int32_t oh, ow;
+        GS_TRY(size_of(images[k].lr_h, images[k].lr_w, images[k].scale, &oh, &ow));
+        if (images[k].out_offset < 0) return GS_E_INVALID;
+        blocks.emplace_back(images[k].out_offset, images[k].out_offset + 3LL * oh * ow);
+    }
+    std::sort(blocks.begin(), blocks.end());
+    for (size_t k = 1; k < blocks.size(); ++k)
+        if (blocks[k].first < blocks[k - 1].second) return GS_E_INVALID;
+    return dev(launch_psnr_y(images, n_img, test, ref, crop, sse, psnr,
+                             static_cast<hipStream_t>(stream)));
+}
+
 struct gs_graph_s {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -567,7 +632,7 @@ gs_status gs_graph_create(const gs_config* cfg, const gs_image* images, int32_t 
     std::vector<ImgDev> table;
     GS_TRY(make_layout(cfg, images, n_img, n_gauss, &L, &table));
     GS_TRY(check_gauss_ptrs(n_gauss, mean, chol, color, opacity));
-    if (!out) return GS_E_INVALID;
+    if (!out || (radius && L.window_r > 0.0)) return GS_E_INVALID;
     if (target && n_gauss > 0 && (!grad_mean || !grad_chol || !grad_color || !grad_opacity))
         return GS_E_INVALID;
     if (!workspace || ws_bytes < L.total) return GS_E_WORKSPACE;

@@ -98,6 +98,34 @@ __device__ bool support_box(double s, int out_w, int out_h, double mx, double my
     return true;
 }
 
+// Algorithm 1's own window (the rasterization ratio r): the strict test
+// |x - s mu_x| < r s W, |y - s mu_y| < r s H with both sides in HR pixels
+// and each axis paired with its own extent, clipped to the image; the
+// Gaussian must still be valid.  Same FP64 operation sequence as the
+// standard-deviation box, so boxes are reproducible bit for bit.
+__device__ bool window_box(double s, int out_w, int out_h, int lr_w, int lr_h, double r,
+                           double mx, double my, double l11, double l21, double l22, int* box,
+                           bool* clipped) {
+#pragma clang fp contract(off)
+    if (!finite_d(mx) || !finite_d(my) || !finite_d(l11) || !finite_d(l21) ||
+        !finite_d(l22) || !finite_d(r))
+        return false;
+    if (!(l11 > 0.0) || !(l22 > 0.0) || !(r > 0.0)) return false;
+    const double hx = r * (s * (double)lr_w);
+    const double hy = r * (s * (double)lr_h);
+    const double cx = s * mx, cy = s * my;
+    double x0 = __builtin_floor(cx - hx) + 1.0, x1 = __builtin_ceil(cx + hx) - 1.0;
+    double y0 = __builtin_floor(cy - hy) + 1.0, y1 = __builtin_ceil(cy + hy) - 1.0;
+    *clipped = x0 < 0.0 || y0 < 0.0 || x1 > (double)(out_w - 1) || y1 > (double)(out_h - 1);
+    if (x0 < 0.0) x0 = 0.0;
+    if (y0 < 0.0) y0 = 0.0;
+    if (x1 > (double)(out_w - 1)) x1 = (double)(out_w - 1);
+    if (y1 > (double)(out_h - 1)) y1 = (double)(out_h - 1);
+    if (x0 > x1 || y0 > y1) return false;
+    box[0] = (int)x0; box[1] = (int)x1; box[2] = (int)y0; box[3] = (int)y1;
+    return true;
+}
+
 // One thread per Gaussian: box, record, tile count; per-block sums of the
 // pair counts, in-support areas and invalid flags.  Also clears the per-tile
 // pair counts (and, for the radix path, the ranges), the backward
@@ -109,9 +137,9 @@ __global__ __launch_bounds__(kBlockG) void k_support(
     ImgChunk arg_imgs, ImgDev* __restrict__ imgs, int n_img, int64_t n_gauss, int tile,
     const float* __restrict__ mean, const float* __restrict__ chol,
     const float* __restrict__ color, const float* __restrict__ opacity,
-    const float* __restrict__ radius, GRec* __restrict__ recs, int32_t* __restrict__ counts,
-    BlockSums* __restrict__ blocksums, int32_t* __restrict__ tile_cnt,
-    int2* __restrict__ ranges_clear, int64_t n_tiles,
+    const float* __restrict__ radius, double window_r, GRec* __restrict__ recs,
+    int32_t* __restrict__ counts, BlockSums* __restrict__ blocksums,
+    int32_t* __restrict__ tile_cnt, int2* __restrict__ ranges_clear, int64_t n_tiles,
     float4* __restrict__ moments, uint32_t* __restrict__ counters) {
     __shared__ int64_t tmp[3][kBlockG / 64];
     const int64_t i = (int64_t)blockIdx.x * kBlockG + threadIdx.x;
@@ -149,7 +177,13 @@ __global__ __launch_bounds__(kBlockG) void k_support(
             const bool shape_ok = finite_d(mx) && finite_d(my) && finite_d(l11) &&
                                   finite_d(l21) && finite_d(l22) && l11 > 0.0 && l22 > 0.0;
             bad = shape_ok ? 0 : 1;
-            if (support_box(s, im.out_w, im.out_h, mx, my, l11, l21, l22, R, box, &clipped)) {
+            const bool has_box =
+                window_r > 0.0
+                    ? window_box(s, im.out_w, im.out_h, im.lr_w, im.lr_h, window_r, mx, my, l11,
+                                 l21, l22, box, &clipped)
+                    : support_box(s, im.out_w, im.out_h, mx, my, l11, l21, l22, R, box,
+                                  &clipped);
+            if (has_box) {
                 // colour / opacity may be NULL when only the pairs are counted
                 const double al = opacity ? (double)opacity[i] : 0.0;
                 const double c0 = color ? (double)color[3 * i] : 0.0;
@@ -962,12 +996,12 @@ hipError_t launch_support(const Layout& L, const Ws& w, const ImgDev* host_imgs,
     if (by_value)
         hipLaunchKernelGGL(k_support<true>, dim3(L.nblk_g), dim3(kBlockG), 0, st, chunk, w.imgs,
                            L.n_img, L.n_gauss, L.tile, mean, chol, color, opacity, radius,
-                           w.recs, w.counts, w.blocksums, w.tile_cnt, radix ? w.ranges : nullptr, L.n_tiles, mom,
+                           L.window_r, w.recs, w.counts, w.blocksums, w.tile_cnt, radix ? w.ranges : nullptr, L.n_tiles, mom,
                            w.counters);
     else
         hipLaunchKernelGGL(k_support<false>, dim3(L.nblk_g), dim3(kBlockG), 0, st, chunk, w.imgs,
                            L.n_img, L.n_gauss, L.tile, mean, chol, color, opacity, radius,
-                           w.recs, w.counts, w.blocksums, w.tile_cnt, radix ? w.ranges : nullptr, L.n_tiles, mom,
+                           L.window_r, w.recs, w.counts, w.blocksums, w.tile_cnt, radix ? w.ranges : nullptr, L.n_tiles, mom,
                            w.counters);
     if (count_only || L.nblk_g > kFoldScanBlocks)
         hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kBlockG), 0, st, w.blocksums, L.nblk_g,

@@ -49,7 +49,7 @@ struct ImgDev {
     int64_t g_begin, g_count;
     int64_t tile_base;      // first global tile id of this image
     double scale;
-    int64_t pad;
+    int32_t lr_w, lr_h;     // LR size (the r-window's extents)
 };
 static_assert(sizeof(ImgDev) == 64, "ImgDev layout");
 
@@ -105,6 +105,7 @@ struct Layout {
     int32_t nblk_sort = 0;    // radix-sort binning: blocks of a pass at full capacity
     int32_t n_passes = 0;     // radix-sort binning: passes over the tile-id bits
     int32_t nblk_order = 0;   // blocks of the tile-order sort
+    double window_r = 0.0;    // > 0: Algorithm 1's r-window support instead of the sigma box
     size_t off_order = 0, off_order_hist = 0, off_counters = 0;
     size_t off_header = 0, off_imgs = 0, off_recs = 0, off_counts = 0, off_offsets = 0,
            off_blocksums = 0, off_tile_cnt = 0, off_loss_parts = 0, off_scan_sums = 0, off_slots = 0, off_lists = 0, off_spare = 0,
@@ -249,5 +250,20 @@ hipError_t launch_closed_form_radius(const float* chol, const float* color,
                                     float* R, hipStream_t st);
 hipError_t launch_sq_error(const float* a, const float* b, int64_t n, double* sum,
                            hipStream_t st);
+
+// ---- launchers (gs_head.hip) ---------------------------------------------
+hipError_t launch_head_fwd(const gs_image* images, int32_t n_img, int32_t grid,
+                           const float* raw_opacity, const float* raw_color,
+                           const float* raw_sigma, const float* raw_rho, const float* offset,
+                           float* mean, float* chol, float* color, float* opacity,
+                           hipStream_t st);
+hipError_t launch_head_bwd(int64_t n, const float* raw_opacity, const float* raw_color,
+                           const float* raw_sigma, const float* raw_rho, const float* g_mean,
+                           const float* g_chol, const float* g_color, const float* g_opacity,
+                           float* d_opacity, float* d_color, float* d_sigma, float* d_rho,
+                           float* d_offset, hipStream_t st);
+hipError_t launch_psnr_y(const gs_image* images, int32_t n_img, const float* test,
+                         const float* ref, int32_t crop, double* sse, double* psnr,
+                         hipStream_t st);
 
 }  // namespace gs

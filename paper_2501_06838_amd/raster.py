@@ -50,17 +50,20 @@ class RasterPlan:
 
     images: sequence of (lr_h, lr_w, scale, g_begin, g_count).
     tile:   HR tile side (8, 16 or 32).
+    window: 0 for the standard-deviation support box; r > 0 for Algorithm 1's
+            r-window (rasterization ratio r).
     """
 
     def __init__(self, images: Sequence[Tuple[int, int, float, int, int]], n_gauss: int,
                  tile: int = 16, lds_batch: int = 0, flags: int = 0,
-                 pair_capacity: int = 0):
+                 pair_capacity: int = 0, window: float = 0.0):
         if len(images) < 1:
             raise ValueError("need at least one image")
         self.n_gauss = int(n_gauss)
         self.tile = int(tile)
         self.lds_batch = int(lds_batch)
         self.flags = int(flags)
+        self.window = float(window)
         self.sizes: List[Tuple[int, int]] = []
         self.offsets: List[int] = []
         arr = (N.gs_image * len(images))()
@@ -83,7 +86,7 @@ class RasterPlan:
     # -- configuration --------------------------------------------------------
     def config(self, capacity: Optional[int] = None) -> N.gs_config:
         cap = self.capacity if capacity is None else int(capacity)
-        return N.gs_config(self.tile, self.lds_batch, self.flags, 0, cap)
+        return N.gs_config(self.tile, self.lds_batch, self.flags, 0, cap, self.window)
 
     def workspace_bytes(self, capacity: Optional[int] = None) -> int:
         cfg = self.config(max(1, self.capacity if capacity is None else capacity))

@@ -22,6 +22,11 @@ Workloads (HR size = floor(s*LR + 0.5)):
   config2b : 256x256 LR, 65,536 Gaussians, s = 12 -> 3072x3072, wide sigmas.
   config3  : 64 images, H, W ~ U{48..256}, 25% extra Gaussians at uniform
              random positions, s ~ U[1.5, 12].
+  paper720 : the paper's cost workload: a 720x720 HR output at s in
+             {2, 3, 4, 6, 8, 12} from a (720/s)^2 LR image holding m = 16
+             Gaussians per LR pixel, one per cell of a 4x4 sub-grid of each
+             pixel with a free offset inside its cell; per-axis log-std
+             N(log 0.35, 0.3) LR pixels (not published: a stand-in).
 """
 from __future__ import annotations
 
@@ -34,7 +39,7 @@ import numpy as np
 __all__ = [
     "Image", "Workload", "draw_image_gaussians", "cholesky_from_axes",
     "tiny", "config0", "config1", "config2a", "config2b", "config3",
-    "by_name", "concat",
+    "paper720", "draw_grid_gaussians", "by_name", "concat",
 ]
 
 
@@ -109,6 +114,45 @@ def draw_image_gaussians(rng: np.random.Generator, H: int, W: int,
     chol = np.stack([l11, l21, l22], axis=1)
     return (mean.astype(np.float32), chol.astype(np.float32),
             color.astype(np.float32), opacity.astype(np.float32))
+
+
+def draw_grid_gaussians(rng: np.random.Generator, H: int, W: int, grid: int,
+                        log_sigma_mean: float, log_sigma_std: float):
+    """grid^2 Gaussians per LR pixel, row-major over a (grid H) x (grid W)
+    sub-grid of equal cells covering [-1/2, W - 1/2] x [-1/2, H - 1/2], each
+    uniformly inside its own cell.  FP32 (mean, chol, color, opacity)."""
+    gx = (np.arange(grid * W, dtype=np.float64) + 0.5) / grid - 0.5
+    gy = (np.arange(grid * H, dtype=np.float64) + 0.5) / grid - 0.5
+    X, Y = np.meshgrid(gx, gy, indexing="xy")
+    n = X.size
+    mean = np.stack([X.ravel(), Y.ravel()], axis=1)
+    mean += rng.uniform(-0.5 / grid, 0.5 / grid, size=(n, 2))
+    log_sig = rng.normal(math.log(log_sigma_mean), log_sigma_std, size=(n, 2))
+    theta = rng.uniform(0.0, math.pi, size=n)
+    color = rng.uniform(0.0, 1.0, size=(n, 3))
+    opacity = rng.uniform(0.5, 1.0, size=n)
+    l11, l21, l22 = cholesky_from_axes(np.exp(log_sig[:, 0]), np.exp(log_sig[:, 1]), theta)
+    chol = np.stack([l11, l21, l22], axis=1)
+    return (mean.astype(np.float32), chol.astype(np.float32),
+            color.astype(np.float32), opacity.astype(np.float32))
+
+
+def paper720(s: int = 4, seed: int = 0, with_target: bool = False, hr: int = 720,
+             grid: int = 4) -> "Workload":
+    """The paper's rendering-cost workload at integer scale s: an hr x hr
+    output (720 by default) from an (hr/s)^2 LR image with grid^2 Gaussians
+    per LR pixel (m = 16)."""
+    if hr % s:
+        raise ValueError("the HR side must be a multiple of the scale")
+    H = W = hr // s
+    rng = np.random.default_rng([seed, 0])
+    m, c, col, op = draw_grid_gaussians(rng, H, W, grid, 0.35, 0.3)
+    targets = None
+    if with_target:
+        targets = [np.random.default_rng([seed, 0, 1]).uniform(0.0, 1.0, size=(3, hr, hr))
+                   .astype(np.float32)]
+    return Workload(name=f"paper720_x{s}", images=[Image(H, W, float(s), 0, m.shape[0])],
+                    mean=m, chol=c, color=col, opacity=op, target=targets)
 
 
 def _build(name, shapes, sigma, extra_frac, seed, with_target=False):

@@ -26,7 +26,7 @@ def test_library_exports_every_declared_symbol():
     for name in names:
         assert hasattr(lib, name), name
     assert set(names) == set(N.EXPORTED)
-    assert lib.gs_abi_version() == 2
+    assert lib.gs_abi_version() == 3
     assert N.status_string(-2) == "pair capacity exceeded"
 
 
@@ -78,3 +78,26 @@ def test_plan_layout():
     assert plan.offsets == [0, 3 * 237 * 237]
     assert plan.out_numel == 3 * (237 * 237 + 120 * 100)
     assert plan.n_tiles == 15 * 15 + 7 * 8
+
+
+def test_head_and_psnr_host_validation():
+    """The head checks each image's Gaussian count (grid^2 H W) and ranges,
+    the PSNR its crop and pointers, on the host, before any device call."""
+    from paper_2501_06838_amd import _native as N
+    L = N.lib()
+    fake = ctypes.c_void_p(16)  # never dereferenced: every call below fails validation
+
+    def head(imgs, grid, n):
+        arr = (N.gs_image * len(imgs))(*[N.gs_image(h, w, 1.0, gb, gc, 0)
+                                         for h, w, gb, gc in imgs])
+        return L.gs_gaussian_head_forward(arr, len(imgs), grid, *([fake] * 5), n,
+                                          *([fake] * 4), None)
+    assert head([(3, 4, 0, 47)], 2, 48) == N.GS_E_INVALID       # 2^2 x 3 x 4 = 48
+    assert head([(3, 4, 0, 48)], 0, 48) == N.GS_E_INVALID       # grid < 1
+    assert head([(3, 4, 0, 48)], 2, 40) == N.GS_E_INVALID       # range past n_gauss
+    assert head([(3, 4, 10, 48), (1, 1, 0, 4)], 2, 100) == N.GS_E_INVALID  # not ascending
+    assert head([(5, 1 << 21, 0, 16 * 5 << 21)], 4, 16 * 5 << 21) == N.GS_E_UNSUPPORTED
+    arr = (N.gs_image * 1)(N.gs_image(4, 4, 2.0, 0, 0, 0))
+    assert L.gs_psnr_y(arr, 1, fake, fake, -1, fake, fake, None) == N.GS_E_INVALID
+    assert L.gs_psnr_y(arr, 1, None, fake, 0, fake, fake, None) == N.GS_E_INVALID
+    assert L.gs_psnr_y(arr, 0, fake, fake, 0, fake, fake, None) == N.GS_E_INVALID
