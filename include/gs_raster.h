@@ -30,7 +30,8 @@
  *     the caller, FP32, C-contiguous.  gs_image arrays are host memory.  The
  *     library allocates nothing on the device and keeps no global state:
  *     calls on different streams with different workspaces may run
- *     concurrently.
+ *     concurrently.  (The one exception is gs_raster_step_l1_noalloc, whose
+ *     workspace is a library-owned device array shared by its calls.)
  *   - Streams: stream is a hipStream_t passed as void* (NULL = default
  *     stream).  Every device entry point only enqueues work on it and returns
  *     without synchronising, unless marked "synchronising".
@@ -233,6 +234,36 @@ gs_status gs_raster_step_l1(const gs_config* cfg, const gs_image* images, int32_
                             void* workspace, size_t ws_bytes, float* out, const float* target,
                             float* grad_mean, float* grad_chol, float* grad_color,
                             float* grad_opacity, double* loss, void* stream);
+
+/* Bytes of the device scratch array behind gs_raster_step_l1_noalloc. */
+#define GS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* gs_raster_step_l1 without a caller workspace and without any device
+ * allocation, for callers that cannot allocate: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * workspace is a library-owned device array of GS_NOALLOC_SCRATCH_BYTES
+ * (64 MiB), one per device, held from library load until the process ends;
+ * the call runs on the current device, which must be the stream's.
+ *   - cfg->pair_capacity = 0 (or cfg NULL) takes the largest capacity whose
+ *     layout fits the array; a layout larger than the array (an explicit
+ *     capacity, or many Gaussians or tiles) returns GS_E_WORKSPACE with
+ *     nothing enqueued.
+ *   - overflow (device int32, may be NULL) is set, in stream order, to 1 if
+ *     the step's pairs exceeded that capacity (its outputs are then
+ *     undefined), else 0.
+ *   - The first call on a device looks the array's address up
+ *     (hipGetSymbolAddress); make it outside graph capture.
+ *   - Every call on one device shares the array, and each call overwrites
+ *     what the previous one left there: calls that overlap on one device
+ *     (two streams, two threads) race.  Serialise them.
+ * Otherwise as gs_raster_step_l1 (same kernels, same results). */
+gs_status gs_raster_step_l1_noalloc(const gs_config* cfg, const gs_image* images,
+                                    int32_t n_img, const float* mean, const float* chol,
+                                    const float* color, const float* opacity,
+                                    const float* radius, int64_t n_gauss, float* out,
+                                    const float* target, float* grad_mean, float* grad_chol,
+                                    float* grad_color, float* grad_opacity, double* loss,
+                                    int32_t* overflow, void* stream);
 
 /* Mean L1 loss of the last gs_raster_render_backward_l1 in this workspace,
  * written to *loss (device double). */

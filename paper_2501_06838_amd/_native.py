@@ -33,7 +33,7 @@ EXPORTED = (
     "gs_l1_loss_value", "gs_raster_backward_l1", "gs_graph_create", "gs_graph_launch",
     "gs_graph_destroy", "gs_mlp_features", "gs_mlp_forward", "gs_mlp_workspace_size",
     "gs_mlp_grad", "gs_mlp_adam", "gs_radius_stats", "gs_sq_error", "gs_tile_order",
-    "gs_raster_render_fused_l1", "gs_raster_step_l1",
+    "gs_raster_render_fused_l1", "gs_raster_step_l1", "gs_raster_step_l1_noalloc",
     "gs_mlp_radius", "gs_closed_form_radius", "gs_gaussian_head_forward",
     "gs_gaussian_head_backward", "gs_psnr_y",
 )
@@ -126,6 +126,10 @@ def lib():
         L.gs_raster_step_l1.argtypes = [_cfgp, _imgp, _i32, _vp, _vp, _vp, _vp, _vp, _i64, _vp,
                                         _sz, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
         L.gs_raster_step_l1.restype = _i32
+        L.gs_raster_step_l1_noalloc.argtypes = [_cfgp, _imgp, _i32, _vp, _vp, _vp, _vp, _vp,
+                                                _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                                _vp]
+        L.gs_raster_step_l1_noalloc.restype = _i32
         L.gs_gaussian_head_forward.argtypes = [_imgp, _i32, _i32] + [_vp] * 5 + [_i64] + \
             [_vp] * 5
         L.gs_gaussian_head_forward.restype = _i32

@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -175,6 +176,37 @@ gs_status run_binning(const Layout& L, const Ws& w, const std::vector<ImgDev>& t
     return GS_OK;
 }
 
+// Device scratch of gs_raster_step_l1_noalloc: the workspace of one step
+// lives here instead of in caller memory.  Each device holds its own copy
+// from module load until the process ends.  In host code the array's name is
+// only a stand-in; its device address comes from hipGetSymbolAddress, once
+// per device, and only that address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[GS_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of `scratch` (looked up on first use).
+gs_status scratch_ptr(void** out) {
+    int d = -1;
+    if (hipGetDevice(&d) != hipSuccess) return GS_E_DEVICE;
+    if (d < 0 || d >= kMaxDevices) return GS_E_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[d]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p)
+            return GS_E_DEVICE;
+        g_scratch_ptr[d] = p;
+    }
+    *out = g_scratch_ptr[d];
+    return GS_OK;
+}
+
+__global__ void k_overflow_flag(const WsHeader* h, int32_t* dst) {
+    if (threadIdx.x == 0) *dst = h->overflow ? 1 : 0;
+}
+
 }  // namespace
 }  // namespace gs
 
@@ -303,6 +335,45 @@ gs_status gs_raster_step_l1(const gs_config* cfg, const gs_image* images, int32_
     GS_TRY(dev(launch_render_fused_l1(L, w, out, target, batch_numel(table), st)));
     return dev(launch_finalize(L, w, chol, color, opacity, grad_mean, grad_chol, grad_color,
                                grad_opacity, st, batch_numel(table), loss));
+}
+
+gs_status gs_raster_step_l1_noalloc(const gs_config* cfg, const gs_image* images,
+                                    int32_t n_img, const float* mean, const float* chol,
+                                    const float* color, const float* opacity,
+                                    const float* radius, int64_t n_gauss, float* out,
+                                    const float* target, float* grad_mean, float* grad_chol,
+                                    float* grad_color, float* grad_opacity, double* loss,
+                                    int32_t* overflow, void* stream) {
+    gs_config c = cfg ? *cfg : gs_config{};
+    Layout L;
+    std::vector<ImgDev> table;
+    if (c.pair_capacity == 0) {
+        // the largest pair capacity whose layout fits the scratch array
+        c.pair_capacity = 1;
+        GS_TRY(make_layout(&c, images, n_img, n_gauss, &L, &table));
+        const size_t base = L.total;
+        c.pair_capacity = 1 << 20;
+        GS_TRY(make_layout(&c, images, n_img, n_gauss, &L, &table));
+        const size_t per_pair = (L.total - base + ((1 << 20) - 2)) / ((1 << 20) - 1);
+        const size_t slack = 16 * 256;  // alignment of the per-pair sections
+        if (base + slack + per_pair > GS_NOALLOC_SCRATCH_BYTES) return GS_E_WORKSPACE;
+        c.pair_capacity =
+            (int64_t)std::min<size_t>((GS_NOALLOC_SCRATCH_BYTES - base - slack) / per_pair,
+                                      (size_t)2147483647);
+    }
+    GS_TRY(make_layout(&c, images, n_img, n_gauss, &L, &table));
+    if (L.total > GS_NOALLOC_SCRATCH_BYTES) return GS_E_WORKSPACE;
+    void* ws = nullptr;
+    GS_TRY(scratch_ptr(&ws));
+    GS_TRY(gs_raster_step_l1(&c, images, n_img, mean, chol, color, opacity, radius, n_gauss, ws,
+                             GS_NOALLOC_SCRATCH_BYTES, out, target, grad_mean, grad_chol,
+                             grad_color, grad_opacity, loss, stream));
+    if (overflow) {
+        hipLaunchKernelGGL(k_overflow_flag, dim3(1), dim3(64), 0,
+                           static_cast<hipStream_t>(stream), bind(L, ws).hdr, overflow);
+        return dev(hipGetLastError());
+    }
+    return GS_OK;
 }
 
 gs_status gs_l1_loss_value(const gs_config* cfg, const gs_image* images, int32_t n_img,

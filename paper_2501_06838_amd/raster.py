@@ -227,6 +227,19 @@ class RasterPlan:
                                           _ptr(gc), _ptr(gcol), _ptr(gop), _ptr(loss),
                                           _stream(stream)), "step l1")
 
+    def step_l1_noalloc(self, mean, chol, color, opacity, out, target, grads, loss=None,
+                        radius=None, overflow=None, stream=None):
+        """step_l1 on the library's own device scratch array (no workspace, no
+        device allocation).  overflow: optional int32 device tensor [1] set to
+        1 if the pairs exceeded the capacity that fits the array."""
+        cfg = self.config(self.capacity)
+        gm, gc, gcol, gop = grads
+        N.check(N.lib().gs_raster_step_l1_noalloc(
+            ctypes.byref(cfg), self._arr, len(self.images), _ptr(mean), _ptr(chol),
+            _ptr(color), _ptr(opacity), _ptr(radius), self.n_gauss, _ptr(out), _ptr(target),
+            _ptr(gm), _ptr(gc), _ptr(gcol), _ptr(gop), _ptr(loss), _ptr(overflow),
+            _stream(stream)), "step l1 (no allocation)")
+
     def l1_loss_value(self, workspace, loss, stream=None, capacity=None):
         """Mean L1 loss of the last fused backward into `loss` (0-d float64 tensor)."""
         cfg = self.config(capacity)

@@ -80,6 +80,22 @@ def test_plan_layout():
     assert plan.n_tiles == 15 * 15 + 7 * 8
 
 
+def test_noalloc_step_rejects_layouts_beyond_its_array():
+    """The allocation-free step checks the layout against its fixed scratch
+    array on the host: too many Gaussians, or an explicit pair capacity that
+    does not fit, return GS_E_WORKSPACE before any device call."""
+    from paper_2501_06838_amd import _native as N
+    L = N.lib()
+    img = (N.gs_image * 1)(N.gs_image(512, 512, 4.0, 0, 2_000_000, 0))
+    cfg = N.gs_config(16, 0, 0, 0, 0)
+    args = [None] * 5 + [2_000_000] + [None] * 9
+    assert L.gs_raster_step_l1_noalloc(ctypes.byref(cfg), img, 1, *args) == N.GS_E_WORKSPACE
+    img = (N.gs_image * 1)(N.gs_image(64, 64, 3.7, 0, 4096, 0))
+    cfg = N.gs_config(16, 0, 0, 0, 10_000_000)  # 10 M pairs: far beyond 64 MiB
+    args = [None] * 5 + [4096] + [None] * 9
+    assert L.gs_raster_step_l1_noalloc(ctypes.byref(cfg), img, 1, *args) == N.GS_E_WORKSPACE
+
+
 def test_head_and_psnr_host_validation():
     """The head checks each image's Gaussian count (grid^2 H W) and ranges,
     the PSNR its crop and pointers, on the host, before any device call."""
