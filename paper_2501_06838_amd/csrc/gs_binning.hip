@@ -211,6 +211,7 @@ __global__ __launch_bounds__(kBlockG) void k_support(
                     r.flags |= kRecNoAmp;  // listed in tiles but adds and receives nothing
                 }
                 if (clipped) r.flags |= kRecClipped;
+                if (window_r > 0.0) r.flags |= kRecCull;
                 const int tx0 = r.x0 / tile, tx1 = r.x1 / tile;
                 const int ty0 = r.y0 / tile, ty1 = r.y1 / tile;
                 cnt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);

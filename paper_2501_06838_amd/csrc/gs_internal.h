@@ -70,6 +70,10 @@ struct GRec {
 // receives nothing); the support box was cut by the image border.
 constexpr int32_t kRecNoAmp = 1;
 constexpr int32_t kRecClipped = 2;
+// The support is a window wider than the Gaussian (Algorithm 1's r-window):
+// the tile kernels drop (block, Gaussian) records whose weights all round to
+// zero.
+constexpr int32_t kRecCull = 4;
 static_assert(sizeof(GRec) == 64, "GRec layout");
 
 

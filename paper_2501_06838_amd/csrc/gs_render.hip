@@ -136,6 +136,28 @@ struct TileInfo {
     int2 rg;
 };
 
+// A record whose box has q = z1^2 + z2^2 (log2-scaled) above kQCull
+// everywhere adds exactly zero: its FP32 weights exp2(-q) < 2^-159 round to
+// zero.  Such records are dropped at staging when the support is a window
+// much wider than the Gaussian (Algorithm 1's r-window), which leaves every
+// sum bit for bit as it was.
+constexpr float kQCull = 160.f;
+
+// A lower bound of q = (a X + z10)^2 + (e Y - g X + z20)^2 over the real box
+// [x0, x1] x [y0, y1] (a, e > 0): z1 and z2 are linear, so each one's
+// smallest square over the box follows from its range (z1 over x0..x1, z2
+// over the four corners), and q is at least their sum.
+__device__ __forceinline__ float box_qlow(float a, float e, float g, float z10, float z20,
+                                          float x0, float x1, float y0, float y1) {
+    const float u0 = __builtin_fmaf(a, x0, z10), u1 = __builtin_fmaf(a, x1, z10);
+    const float d1 = u0 > 0.f ? u0 : (u1 < 0.f ? -u1 : 0.f);
+    const float gx0 = __builtin_fmaf(-g, x0, z20), gx1 = __builtin_fmaf(-g, x1, z20);
+    const float v0 = __builtin_fmaf(e, y0, fminf(gx0, gx1));
+    const float v1 = __builtin_fmaf(e, y1, fmaxf(gx0, gx1));
+    const float d2 = v0 > 0.f ? v0 : (v1 < 0.f ? -v1 : 0.f);
+    return __builtin_fmaf(d1, d1, d2 * d2);
+}
+
 // Stages entries [base, base + nb) of the tile's sorted list (Gaussian ids)
 // from the Gaussians' render records and builds the per-block record lists.
 // Ends with a barrier.
@@ -167,12 +189,20 @@ __device__ __forceinline__ StagedMine stage_round(StageLds<T, B>& st,
         kyr = (float)(ti.py0 - r.ky);
         const int lx0 = max(r.x0 - ti.px0, 0), lx1 = min(r.x1 - ti.px0, T - 1);
         const int ly0 = max(r.y0 - ti.py0, 0), ly1 = min(r.y1 - ti.py0, T - 1);
+        const bool cull = (r.flags & kRecCull) != 0;
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
             const int bx = (j % S::kBlocksX) * 8, by = (j / S::kBlocksX) * 8;
             const int c0 = max(lx0, bx) - bx, c1 = min(lx1, bx + 7) - bx;
             const int r0 = max(ly0, by) - by, r1 = min(ly1, by + 7) - by;
             if (c0 <= c1 && r0 <= r1) {
+                if (cull) {
+                    const float Xb = (kxr + (float)bx) - r.fx;
+                    const float Yb = (kyr + (float)by) - r.fy;
+                    if (box_qlow(r.a, r.e, r.g, r.a * Xb, r.e * Yb - r.g * Xb, (float)c0,
+                                 (float)c1, (float)r0, (float)r1) > kQCull)
+                        continue;
+                }
                 const uint64_t cols = ((1ull << (c1 - c0 + 1)) - 1ull) << c0;
                 my_mask[j] = (cols * 0x0101010101010101ull) & rows_mask(r0, r1);
             }
@@ -268,6 +298,54 @@ __device__ __forceinline__ void fwd_round(const StageLds<T, B>& st,
 // l1 entries of the record it came from.  Idle lanes of the last pass read
 // entry (0, 0), which may already hold sums; their masks are zero and they
 // write nothing.  Ends with a barrier.
+// One lane's eight backward sums over the block-local pixels [cx0, cx1] x
+// [ry0, ry1] (the pass's union of boxes; kFull: the whole block, no bounds
+// checks).  The lane's own box is a rectangle: a column outside it gets a far
+// z1 (its weight underflows to 0, and 0 times the finite z is 0), a row
+// outside it a zero weight.  Column by column: z1 is constant down a column,
+// so the z1 moments follow from the column's sums of H w, H w z2 and
+// H w z2^2 (H = sum_c A_c G_c).  rec0 = {z1, z2 at the block's first pixel,
+// a, e}, rec1 = {g, A0, A1, A2}.
+template <int T, bool kFull>
+__device__ __forceinline__ void bwd_columns(const float4* __restrict__ gcol, uint32_t colset,
+                                            uint32_t rows, int cx0, int cx1, int ry0, int ry1,
+                                            float4 rec0, float4 rec1, float (&m)[8]) {
+    const float a = rec0.z, e = rec0.w, gg = rec1.x;
+    bool rv[8];
+#pragma unroll
+    for (int ry = 0; ry < 8; ++ry) rv[ry] = (rows >> ry) & 1u;
+#pragma unroll
+    for (int cx = 0; cx < 8; ++cx) {
+        if (!kFull && (cx < cx0 || cx > cx1)) continue;  // uniform
+        const float z1 = ((colset >> cx) & 1u) ? __builtin_fmaf(a, (float)cx, rec0.x) : 1e19f;
+        const float z1sq = z1 * z1;
+        const float zb = __builtin_fmaf(-gg, (float)cx, rec0.y);
+        float sa = 0.f, sb = 0.f, sc = 0.f;
+#pragma unroll
+        for (int ry = 0; ry < 8; ++ry) {
+            if (!kFull && (ry < ry0 || ry > ry1)) continue;  // uniform
+            const float4 G = gcol[ry * T + cx];
+            const float z2 = __builtin_fmaf(e, (float)ry, zb);
+            float w = fast_exp2(-__builtin_fmaf(z2, z2, z1sq));
+            w = rv[ry] ? w : 0.f;
+            m[0] = __builtin_fmaf(G.x, w, m[0]);
+            m[1] = __builtin_fmaf(G.y, w, m[1]);
+            m[2] = __builtin_fmaf(G.z, w, m[2]);
+            const float hw =
+                __builtin_fmaf(rec1.y, G.x, __builtin_fmaf(rec1.z, G.y, rec1.w * G.z)) * w;
+            const float hz = hw * z2;
+            sa += hw;
+            sb += hz;
+            sc = __builtin_fmaf(hz, z2, sc);
+        }
+        m[3] = __builtin_fmaf(z1, sa, m[3]);
+        m[4] += sb;
+        m[5] = __builtin_fmaf(z1sq, sa, m[5]);
+        m[6] = __builtin_fmaf(z1, sb, m[6]);
+        m[7] += sc;
+    }
+}
+
 template <int T, int B>
 __device__ __forceinline__ void bwd_round(BwdLds<T, B>& sm) {
     using S = TileShape<T>;
@@ -306,39 +384,15 @@ __device__ __forceinline__ void bwd_round(BwdLds<T, B>& sm) {
         any = __builtin_amdgcn_readfirstlane(any);
         const int cx0 = __builtin_ctz(any & 255u), cx1 = 31 - __builtin_clz(any & 255u);
         const int ry0 = __builtin_ctz(any >> 8), ry1 = 31 - __builtin_clz(any >> 8);
-        const float a = c0.z, e = c0.w, gg = c1.x;
-        float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f, m5 = 0.f, m6 = 0.f, m7 = 0.f;
-        // the box is a rectangle: a column outside it gets a far z1 (its
-        // weight underflows to 0, and 0 times the finite z is 0), a row
-        // outside it a zero row factor
         const uint32_t colset = cm & 255u;
-        float zc1[8];
-#pragma unroll
-        for (int cx = 0; cx < 8; ++cx)
-            zc1[cx] = ((colset >> cx) & 1u) ? __builtin_fmaf(a, (float)cx, c0.x) : 1e19f;
-        for (int ry = ry0; ry <= ry1; ++ry) {
-            const uint32_t rowbits = ((ry < 4 ? mlo : mhi) >> (8 * (ry & 3))) & 255u;
-            const float rmul = rowbits ? 1.f : 0.f;
-            const float4* grow = &sm.gt[(by + ry) * T + bx];
-#pragma unroll
-            for (int cx = 0; cx < 8; ++cx) {
-                if (cx < cx0 || cx > cx1) continue;  // uniform
-                const float4 G = grow[cx];
-                const float z1 = zc1[cx];
-                const float z2 = __builtin_fmaf(e, (float)ry, __builtin_fmaf(-gg, (float)cx, c0.y));
-                const float w = fast_exp2(-(z1 * z1 + z2 * z2)) * rmul;
-                m0 += G.x * w;
-                m1 += G.y * w;
-                m2 += G.z * w;
-                const float hw = (c1.y * G.x + c1.z * G.y + c1.w * G.z) * w;
-                const float t1 = hw * z1, t2 = hw * z2;
-                m3 += t1;
-                m4 += t2;
-                m5 += t1 * z1;
-                m6 += t1 * z2;
-                m7 += t2 * z2;
-            }
-        }
+        const float4* gcol = &sm.gt[by * T + bx];
+        float m[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (cx0 == 0 && cx1 == 7 && ry0 == 0 && ry1 == 7)  // uniform: the whole block
+            bwd_columns<T, true>(gcol, colset, rows, 0, 7, 0, 7, c0, c1, m);
+        else
+            bwd_columns<T, false>(gcol, colset, rows, cx0, cx1, ry0, ry1, c0, c1, m);
+        const float m0 = m[0], m1 = m[1], m2 = m[2], m3 = m[3], m4 = m[4], m5 = m[5],
+                    m6 = m[6], m7 = m[7];
         if (active) {
             // in place of the record this lane read (no other lane reads it)
             sm.st.l0[j][pos] = make_float4(m0, m1, m2, m3);
