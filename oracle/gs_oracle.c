@@ -97,15 +97,78 @@ int or_support_rect(double s, int32_t out_w, int32_t out_h,
     return 1;
 }
 
+/* Support modes (bits of `mode`), alternative readings of Eq. 4 and of the
+ * truncation:
+ *   OR_PIXEL_CENTER: HR pixel x samples the LR coordinate u = (x + 1/2)/s - 1/2
+ *     (pixel centres of both grids aligned) instead of the literal u = x/s;
+ *     every box, window and weight moves with it (the HR centre becomes
+ *     s (mu + 1/2) - 1/2).
+ *   OR_ELLIPSE: within the box, only pixels with Mahalanobis distance d < R
+ *     (d^2 = z1^2 + z2^2 of Eq. 2) are in the support (box test first). */
+#define OR_PIXEL_CENTER 1
+#define OR_ELLIPSE 2
+
+/* The LR coordinate HR pixel index x samples. */
+static double sample_u(int32_t x, double s, int32_t mode)
+{
+    if (mode & OR_PIXEL_CENTER) return ((double)x + 0.5) / s - 0.5;
+    return (double)x / s;
+}
+
+/* Squared Mahalanobis distance (Eq. 2's quadratic form in the Cholesky
+ * coordinates) of HR pixel (x, y), in this exact operation sequence:
+ *   z1 = (u - mx) / l11,  z2 = ((v - my) - l21 z1) / l22,  d2 = z1 z1 + z2 z2. */
+double or_pixel_d2(int32_t x, int32_t y, double s, int32_t mode, double mx, double my,
+                   double l11, double l21, double l22)
+{
+    double z1 = (sample_u(x, s, mode) - mx) / l11;
+    double z2 = ((sample_u(y, s, mode) - my) - l21 * z1) / l22;
+    return z1 * z1 + z2 * z2;
+}
+
+/* Box of one Gaussian (Algorithm 1's strict window test with the
+ * half-window R standard deviations per axis), for either sampling
+ * convention: {x : s((mx - R sx) + c) - c < x < s((mx + R sx) + c) - c},
+ * c = 1/2 with OR_PIXEL_CENTER, else the literal box (c = 0). */
+int or_support_rect_m(double s, int32_t out_w, int32_t out_h, double mx, double my, double l11,
+                      double l21, double l22, double R, int32_t mode, int32_t rect[4])
+{
+    if (!(mode & OR_PIXEL_CENTER))
+        return or_support_rect(s, out_w, out_h, mx, my, l11, l21, l22, R, rect);
+    rect[0] = 0; rect[1] = -1; rect[2] = 0; rect[3] = -1;
+    if (!isfinite(mx) || !isfinite(my) || !isfinite(l11) || !isfinite(l21) ||
+        !isfinite(l22) || !isfinite(R))
+        return 0;
+    if (!(l11 > 0.0) || !(l22 > 0.0) || !(R > 0.0)) return 0;
+    double sx = l11;
+    double sy = sqrt(l21 * l21 + l22 * l22);
+    double lo_x = s * ((mx - R * sx) + 0.5) - 0.5;
+    double hi_x = s * ((mx + R * sx) + 0.5) - 0.5;
+    double lo_y = s * ((my - R * sy) + 0.5) - 0.5;
+    double hi_y = s * ((my + R * sy) + 0.5) - 0.5;
+    double x0 = floor(lo_x) + 1.0, x1 = ceil(hi_x) - 1.0;
+    double y0 = floor(lo_y) + 1.0, y1 = ceil(hi_y) - 1.0;
+    if (x0 < 0.0) x0 = 0.0;
+    if (y0 < 0.0) y0 = 0.0;
+    if (x1 > (double)(out_w - 1)) x1 = (double)(out_w - 1);
+    if (y1 > (double)(out_h - 1)) y1 = (double)(out_h - 1);
+    if (x0 > x1 || y0 > y1) return 0;
+    rect[0] = (int32_t)x0; rect[1] = (int32_t)x1;
+    rect[2] = (int32_t)y0; rect[3] = (int32_t)y1;
+    return 1;
+}
+
 /* Support of one Gaussian under Algorithm 1's own window, the rasterization
  * ratio r of Sec. 3.1 "Fast Rasterization": the strict test |x - mu_x| < r s H,
  * |y - mu_y| < r s W, read with both sides in HR pixels (the HR centre is
  * s mu) and each axis paired with its own image extent (x with W, y with H):
  *     { x integer : s mx - r (s W) < x < s mx + r (s W) }, same for y with H,
  * clipped to the image.  The Gaussian must still be valid (finite, l11 > 0,
- * l22 > 0).  rect = {x0, x1, y0, y1}; returns 1 if non-empty, else 0. */
+ * l22 > 0).  With OR_PIXEL_CENTER the window is centred on s (mu + 1/2) - 1/2.
+ * rect = {x0, x1, y0, y1}; returns 1 if non-empty, else 0. */
 int or_window_rect(double s, int32_t out_w, int32_t out_h, int32_t H, int32_t W, double r,
-                   double mx, double my, double l11, double l21, double l22, int32_t rect[4])
+                   double mx, double my, double l11, double l21, double l22, int32_t mode,
+                   int32_t rect[4])
 {
     rect[0] = 0; rect[1] = -1; rect[2] = 0; rect[3] = -1;
     if (!isfinite(mx) || !isfinite(my) || !isfinite(l11) || !isfinite(l21) ||
@@ -115,6 +178,10 @@ int or_window_rect(double s, int32_t out_w, int32_t out_h, int32_t H, int32_t W,
     double hx = r * (s * (double)W);
     double hy = r * (s * (double)H);
     double cx = s * mx, cy = s * my;
+    if (mode & OR_PIXEL_CENTER) {  /* HR centre of the pixel-centre convention */
+        cx = s * (mx + 0.5) - 0.5;
+        cy = s * (my + 0.5) - 0.5;
+    }
     double x0 = floor(cx - hx) + 1.0, x1 = ceil(cx + hx) - 1.0;
     double y0 = floor(cy - hy) + 1.0, y1 = ceil(cy + hy) - 1.0;
     if (x0 < 0.0) x0 = 0.0;
@@ -169,13 +236,25 @@ static double radius_of(const double* radius, int64_t i)
  * else the box of radius[i] (NULL: 3) standard deviations per axis. */
 static int rect_of(int64_t i, int32_t H, int32_t W, double s, int32_t oh, int32_t ow,
                    const double* mean, const double* chol, const double* radius,
-                   double window_r, int32_t r[4])
+                   double window_r, int32_t mode, int32_t r[4])
 {
     if (window_r > 0.0)
         return or_window_rect(s, ow, oh, H, W, window_r, mean[2 * i], mean[2 * i + 1],
-                              chol[3 * i], chol[3 * i + 1], chol[3 * i + 2], r);
-    return or_support_rect(s, ow, oh, mean[2 * i], mean[2 * i + 1], chol[3 * i],
-                           chol[3 * i + 1], chol[3 * i + 2], radius_of(radius, i), r);
+                              chol[3 * i], chol[3 * i + 1], chol[3 * i + 2], mode, r);
+    return or_support_rect_m(s, ow, oh, mean[2 * i], mean[2 * i + 1], chol[3 * i],
+                             chol[3 * i + 1], chol[3 * i + 2], radius_of(radius, i), mode, r);
+}
+
+/* Whether HR pixel (x, y) of Gaussian i's box is in its support: always for
+ * the box readings; with OR_ELLIPSE (not with the r-window), d^2 < R^2. */
+static int in_support(int64_t i, int32_t x, int32_t y, double s, int32_t mode,
+                      const double* mean, const double* chol, const double* radius,
+                      double window_r)
+{
+    if (!(mode & OR_ELLIPSE) || window_r > 0.0) return 1;
+    double R = radius_of(radius, i);
+    return or_pixel_d2(x, y, s, mode, mean[2 * i], mean[2 * i + 1], chol[3 * i],
+                       chol[3 * i + 1], chol[3 * i + 2]) < R * R;
 }
 
 /* Adds every Gaussian's contribution to the HR rows [y_lo, y_hi) of one image
@@ -185,14 +264,14 @@ static int rect_of(int64_t i, int32_t H, int32_t W, double s, int32_t oh, int32_
 static void forward_rows(int32_t H, int32_t W, int32_t oh, int32_t ow, double s, int64_t n,
                          const double* mean, const double* chol, const double* color,
                          const double* opacity, const double* radius, double window_r,
-                         int32_t y_lo, int32_t y_hi, double* out)
+                         int32_t mode, int32_t y_lo, int32_t y_hi, double* out)
 {
     int64_t plane = (int64_t)oh * ow;
     for (int64_t i = 0; i < n; ++i) {
         const double mx = mean[2 * i], my = mean[2 * i + 1];
         const double l11 = chol[3 * i], l21 = chol[3 * i + 1], l22 = chol[3 * i + 2];
         int32_t r[4];
-        if (!rect_of(i, H, W, s, oh, ow, mean, chol, radius, window_r, r)) continue;
+        if (!rect_of(i, H, W, s, oh, ow, mean, chol, radius, window_r, mode, r)) continue;
         if (!isfinite(opacity[i]) || !isfinite(color[3 * i]) || !isfinite(color[3 * i + 1]) ||
             !isfinite(color[3 * i + 2]))
             continue;
@@ -202,7 +281,9 @@ static void forward_rows(int32_t H, int32_t W, int32_t oh, int32_t ow, double s,
         chol_to_eq2(l11, l21, l22, &sx, &sy, &rho);
         for (int32_t y = ya; y <= yb; ++y) {
             for (int32_t x = r[0]; x <= r[1]; ++x) {
-                double f = eq2_density((double)x / s - mx, (double)y / s - my, sx, sy, rho);
+                if (!in_support(i, x, y, s, mode, mean, chol, radius, window_r)) continue;
+                double f = eq2_density(sample_u(x, s, mode) - mx, sample_u(y, s, mode) - my, sx,
+                                       sy, rho);
                 for (int c = 0; c < 3; ++c)
                     out[c * plane + (int64_t)y * ow + x] += opacity[i] * color[3 * i + c] * f; /* Eq. 1 */
             }
@@ -213,16 +294,18 @@ static void forward_rows(int32_t H, int32_t W, int32_t oh, int32_t ow, double s,
 /* Forward render of one image (Algorithm 1 with Eq. 1, 2, 4).
  * mean [n][2] (mu_x, mu_y); chol [n][3] (l11, l21, l22); color [n][3];
  * opacity [n]; radius [n] or NULL (NULL = 3 standard deviations);
- * window_r > 0 takes Algorithm 1's r-window instead (radius ignored).
- * out [3][out_h][out_w] is overwritten. */
+ * window_r > 0 takes Algorithm 1's r-window instead (radius ignored); mode
+ * holds the OR_* support bits.  out [3][out_h][out_w] is overwritten. */
 void or_forward(int32_t H, int32_t W, double s, int64_t n,
                 const double* mean, const double* chol, const double* color,
-                const double* opacity, const double* radius, double window_r, double* out)
+                const double* opacity, const double* radius, double window_r, int32_t mode,
+                double* out)
 {
     int32_t oh, ow;
     if (or_output_size(H, W, s, &oh, &ow) != 0) return;
     memset(out, 0, sizeof(double) * 3 * (size_t)oh * (size_t)ow);
-    forward_rows(H, W, oh, ow, s, n, mean, chol, color, opacity, radius, window_r, 0, oh, out);
+    forward_rows(H, W, oh, ow, s, n, mean, chol, color, opacity, radius, window_r, mode, 0, oh,
+                 out);
 }
 
 /* or_forward on up to nthreads host threads (OpenMP), for timing the oracle
@@ -231,8 +314,8 @@ void or_forward(int32_t H, int32_t W, double s, int64_t n,
  * that of or_forward. */
 void or_forward_mt(int32_t H, int32_t W, double s, int64_t n,
                    const double* mean, const double* chol, const double* color,
-                   const double* opacity, const double* radius, double window_r, double* out,
-                   int32_t nthreads)
+                   const double* opacity, const double* radius, double window_r, int32_t mode,
+                   double* out, int32_t nthreads)
 {
     int32_t oh, ow;
     if (or_output_size(H, W, s, &oh, &ow) != 0) return;
@@ -243,8 +326,8 @@ void or_forward_mt(int32_t H, int32_t W, double s, int64_t n,
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
     for (int32_t b = 0; b < nb; ++b) {
         const int32_t y1 = (b + 1) * band < oh ? (b + 1) * band : oh;
-        forward_rows(H, W, oh, ow, s, n, mean, chol, color, opacity, radius, window_r, b * band,
-                     y1, out);
+        forward_rows(H, W, oh, ow, s, n, mean, chol, color, opacity, radius, window_r, mode,
+                     b * band, y1, out);
     }
 }
 
@@ -269,7 +352,7 @@ void or_forward_mt(int32_t H, int32_t W, double s, int64_t n,
 static void backward_one(int64_t i, int32_t H, int32_t W, int32_t oh, int32_t ow, double s,
                          const double* mean, const double* chol, const double* color,
                          const double* opacity, const double* radius, double window_r,
-                         const double* grad_out,
+                         int32_t mode, const double* grad_out,
                          double* grad_mean, double* grad_chol, double* grad_color,
                          double* grad_opacity)
 {
@@ -279,7 +362,7 @@ static void backward_one(int64_t i, int32_t H, int32_t W, int32_t oh, int32_t ow
     const double al = opacity[i];
     const double* c = color + 3 * i;
     int32_t r[4];
-    if (!rect_of(i, H, W, s, oh, ow, mean, chol, radius, window_r, r)) return;
+    if (!rect_of(i, H, W, s, oh, ow, mean, chol, radius, window_r, mode, r)) return;
     if (!isfinite(al) || !isfinite(c[0]) || !isfinite(c[1]) || !isfinite(c[2])) return;
     double sx, sy, rho;
     chol_to_eq2(l11, l21, l22, &sx, &sy, &rho);
@@ -289,7 +372,8 @@ static void backward_one(int64_t i, int32_t H, int32_t W, int32_t oh, int32_t ow
     double g_c[3] = {0, 0, 0};
     for (int32_t y = r[2]; y <= r[3]; ++y) {
         for (int32_t x = r[0]; x <= r[1]; ++x) {
-            const double dx = (double)x / s - mx, dy = (double)y / s - my;
+            if (!in_support(i, x, y, s, mode, mean, chol, radius, window_r)) continue;
+            const double dx = sample_u(x, s, mode) - mx, dy = sample_u(y, s, mode) - my;
             const double f = eq2_density(dx, dy, sx, sy, rho);
             const int64_t p = (int64_t)y * ow + x;
             double gc_dot = 0.0; /* sum_c dL/dI_c * c_c */
@@ -320,7 +404,7 @@ static void backward_one(int64_t i, int32_t H, int32_t W, int32_t oh, int32_t ow
 
 void or_backward(int32_t H, int32_t W, double s, int64_t n,
                  const double* mean, const double* chol, const double* color,
-                 const double* opacity, const double* radius, double window_r,
+                 const double* opacity, const double* radius, double window_r, int32_t mode,
                  const double* grad_out,
                  double* grad_mean, double* grad_chol, double* grad_color, double* grad_opacity)
 {
@@ -331,8 +415,8 @@ void or_backward(int32_t H, int32_t W, double s, int64_t n,
     memset(grad_opacity, 0, sizeof(double) * (size_t)n);
     if (or_output_size(H, W, s, &oh, &ow) != 0) return;
     for (int64_t i = 0; i < n; ++i)
-        backward_one(i, H, W, oh, ow, s, mean, chol, color, opacity, radius, window_r, grad_out,
-                     grad_mean, grad_chol, grad_color, grad_opacity);
+        backward_one(i, H, W, oh, ow, s, mean, chol, color, opacity, radius, window_r, mode,
+                     grad_out, grad_mean, grad_chol, grad_color, grad_opacity);
 }
 
 /* or_backward on up to nthreads host threads (OpenMP), for timing the
@@ -341,7 +425,7 @@ void or_backward(int32_t H, int32_t W, double s, int64_t n,
 void or_backward_mt(int32_t H, int32_t W, double s, int64_t n,
                     const double* mean, const double* chol, const double* color,
                     const double* opacity, const double* radius, double window_r,
-                    const double* grad_out,
+                    int32_t mode, const double* grad_out,
                     double* grad_mean, double* grad_chol, double* grad_color,
                     double* grad_opacity, int32_t nthreads)
 {
@@ -354,8 +438,8 @@ void or_backward_mt(int32_t H, int32_t W, double s, int64_t n,
     if (nthreads < 1) nthreads = 1;
 #pragma omp parallel for schedule(dynamic, 256) num_threads(nthreads)
     for (int64_t i = 0; i < n; ++i)
-        backward_one(i, H, W, oh, ow, s, mean, chol, color, opacity, radius, window_r, grad_out,
-                     grad_mean, grad_chol, grad_color, grad_opacity);
+        backward_one(i, H, W, oh, ow, s, mean, chol, color, opacity, radius, window_r, mode,
+                     grad_out, grad_mean, grad_chol, grad_color, grad_opacity);
 }
 
 /* Tile lists of one image: tiles are tw x th HR pixels, numbered row-major
@@ -368,8 +452,8 @@ void or_backward_mt(int32_t H, int32_t W, double s, int64_t n,
  * order again and append each to its tiles' lists. */
 int64_t or_tile_lists(int32_t H, int32_t W, double s, int64_t n,
                       const double* mean, const double* chol, const double* radius,
-                      double window_r, int32_t tw, int32_t th, int32_t* counts, int32_t* lists,
-                      int64_t cap)
+                      double window_r, int32_t mode, int32_t tw, int32_t th, int32_t* counts,
+                      int32_t* lists, int64_t cap)
 {
     int32_t oh, ow;
     if (tw < 1 || th < 1 || or_output_size(H, W, s, &oh, &ow) != 0) return -1;
@@ -380,7 +464,7 @@ int64_t or_tile_lists(int32_t H, int32_t W, double s, int64_t n,
     int64_t total = 0;
     for (int64_t i = 0; i < n; ++i) {
         int32_t r[4];
-        if (!rect_of(i, H, W, s, oh, ow, mean, chol, radius, window_r, r)) continue;
+        if (!rect_of(i, H, W, s, oh, ow, mean, chol, radius, window_r, mode, r)) continue;
         for (int32_t ty = r[2] / th; ty <= r[3] / th; ++ty)
             for (int32_t tx = r[0] / tw; tx <= r[1] / tw; ++tx) {
                 counts[(int64_t)ty * tiles_x + tx] += 1;
@@ -396,7 +480,7 @@ int64_t or_tile_lists(int32_t H, int32_t W, double s, int64_t n,
     for (int64_t t = 0; t < n_tiles; ++t) { fill[t] = start; start += counts[t]; }
     for (int64_t i = 0; i < n; ++i) {
         int32_t r[4];
-        if (!rect_of(i, H, W, s, oh, ow, mean, chol, radius, window_r, r)) continue;
+        if (!rect_of(i, H, W, s, oh, ow, mean, chol, radius, window_r, mode, r)) continue;
         for (int32_t ty = r[2] / th; ty <= r[3] / th; ++ty)
             for (int32_t tx = r[0] / tw; tx <= r[1] / tw; ++tx)
                 lists[fill[(int64_t)ty * tiles_x + tx]++] = (int32_t)i;
@@ -409,16 +493,23 @@ int64_t or_tile_lists(int32_t H, int32_t W, double s, int64_t n,
  * boxes themselves (rects [n][4] may be NULL). */
 int64_t or_support_pairs(int32_t H, int32_t W, double s, int64_t n,
                          const double* mean, const double* chol, const double* radius,
-                         double window_r, int32_t* rects)
+                         double window_r, int32_t mode, int32_t* rects)
 {
     int32_t oh, ow;
     if (or_output_size(H, W, s, &oh, &ow) != 0) return -1;
     int64_t total = 0;
     for (int64_t i = 0; i < n; ++i) {
         int32_t r[4];
-        int ok = rect_of(i, H, W, s, oh, ow, mean, chol, radius, window_r, r);
+        int ok = rect_of(i, H, W, s, oh, ow, mean, chol, radius, window_r, mode, r);
         if (rects) memcpy(rects + 4 * i, r, sizeof r);
-        if (ok) total += (int64_t)(r[1] - r[0] + 1) * (r[3] - r[2] + 1);
+        if (!ok) continue;
+        if (!(mode & OR_ELLIPSE) || window_r > 0.0) {
+            total += (int64_t)(r[1] - r[0] + 1) * (r[3] - r[2] + 1);
+            continue;
+        }
+        for (int32_t y = r[2]; y <= r[3]; ++y)
+            for (int32_t x = r[0]; x <= r[1]; ++x)
+                total += in_support(i, x, y, s, mode, mean, chol, radius, window_r);
     }
     return total;
 }
@@ -430,7 +521,7 @@ int64_t or_support_pairs(int32_t H, int32_t W, double s, int64_t n,
 void or_pixel_values(int32_t H, int32_t W, double s, int64_t n,
                      const double* mean, const double* chol, const double* color,
                      const double* opacity, const double* radius, double window_r,
-                     int64_t npix, const int32_t* xs, const int32_t* ys, double* out)
+                     int32_t mode, int64_t npix, const int32_t* xs, const int32_t* ys, double* out)
 {
     int32_t oh, ow;
     memset(out, 0, sizeof(double) * 3 * (size_t)npix);
@@ -439,7 +530,7 @@ void or_pixel_values(int32_t H, int32_t W, double s, int64_t n,
         const double mx = mean[2 * i], my = mean[2 * i + 1];
         const double l11 = chol[3 * i], l21 = chol[3 * i + 1], l22 = chol[3 * i + 2];
         int32_t r[4];
-        if (!rect_of(i, H, W, s, oh, ow, mean, chol, radius, window_r, r)) continue;
+        if (!rect_of(i, H, W, s, oh, ow, mean, chol, radius, window_r, mode, r)) continue;
         if (!isfinite(opacity[i]) || !isfinite(color[3 * i]) || !isfinite(color[3 * i + 1]) ||
             !isfinite(color[3 * i + 2]))
             continue;
@@ -448,7 +539,9 @@ void or_pixel_values(int32_t H, int32_t W, double s, int64_t n,
         for (int64_t k = 0; k < npix; ++k) {
             const int32_t x = xs[k], y = ys[k];
             if (x < r[0] || x > r[1] || y < r[2] || y > r[3]) continue;
-            double f = eq2_density((double)x / s - mx, (double)y / s - my, sx, sy, rho);
+            if (!in_support(i, x, y, s, mode, mean, chol, radius, window_r)) continue;
+            double f = eq2_density(sample_u(x, s, mode) - mx, sample_u(y, s, mode) - my, sx, sy,
+                                   rho);
             for (int c = 0; c < 3; ++c) out[c * npix + k] += opacity[i] * color[3 * i + c] * f;
         }
     }

@@ -53,11 +53,12 @@ def lib():
         L.or_box_cut.argtypes = L.or_support_rect.argtypes[:-1]
         L.or_box_cut.restype = ctypes.c_int
         L.or_forward.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
-                                 ctypes.c_int64, _D, _D, _D, _D, _D, ctypes.c_double, _D]
+                                 ctypes.c_int64, _D, _D, _D, _D, _D, ctypes.c_double,
+                                 ctypes.c_int32, _D]
         L.or_forward.restype = None
         L.or_backward.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
-                                  ctypes.c_int64, _D, _D, _D, _D, _D, ctypes.c_double, _D, _D,
-                                  _D, _D, _D]
+                                  ctypes.c_int64, _D, _D, _D, _D, _D, ctypes.c_double,
+                                  ctypes.c_int32, _D, _D, _D, _D, _D]
         L.or_backward.restype = None
         L.or_forward_mt.argtypes = L.or_forward.argtypes + [ctypes.c_int32]
         L.or_forward_mt.restype = None
@@ -65,14 +66,16 @@ def lib():
         L.or_backward_mt.restype = None
         L.or_tile_lists.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                     ctypes.c_int64, _D, _D, _D, ctypes.c_double, ctypes.c_int32,
+                                    ctypes.c_int32,
                                     ctypes.c_int32, _I32, _I32, ctypes.c_int64]
         L.or_tile_lists.restype = ctypes.c_int64
         L.or_support_pairs.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
-                                       ctypes.c_int64, _D, _D, _D, ctypes.c_double, _I32]
+                                       ctypes.c_int64, _D, _D, _D, ctypes.c_double,
+                                       ctypes.c_int32, _I32]
         L.or_support_pairs.restype = ctypes.c_int64
         L.or_pixel_values.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                       ctypes.c_int64, _D, _D, _D, _D, _D, ctypes.c_double,
-                                      ctypes.c_int64,
+                                      ctypes.c_int32, ctypes.c_int64,
                                       _I32, _I32, _D]
         L.or_pixel_values.restype = None
         L.or_radius_labels.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
@@ -80,7 +83,13 @@ def lib():
         L.or_radius_labels.restype = None
         L.or_window_rect.argtypes = [ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.c_int32, ctypes.c_int32, ctypes.c_double] + \
-            [ctypes.c_double] * 5 + [_I32]
+            [ctypes.c_double] * 5 + [ctypes.c_int32, _I32]
+        L.or_support_rect_m.argtypes = [ctypes.c_double, ctypes.c_int32, ctypes.c_int32] + \
+            [ctypes.c_double] * 6 + [ctypes.c_int32, _I32]
+        L.or_support_rect_m.restype = ctypes.c_int
+        L.or_pixel_d2.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                  ctypes.c_int32] + [ctypes.c_double] * 5
+        L.or_pixel_d2.restype = ctypes.c_double
         L.or_window_rect.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -120,15 +129,34 @@ def box_cut(H, W, s, mean, chol, R=3.0):
                      for i in range(mean.shape[0])], dtype=np.int32)
 
 
-def window_rect(s, out_w, out_h, H, W, r, mx, my, l11, l21, l22):
+# support-mode bits (see gs_oracle.c): pixel-centre sampling, elliptical support
+PIXEL_CENTER = 1
+ELLIPSE = 2
+
+
+def window_rect(s, out_w, out_h, H, W, r, mx, my, l11, l21, l22, mode=0):
     """Algorithm 1's r-window of one Gaussian (see gs_oracle.c)."""
     rr = (ctypes.c_int32 * 4)()
     ok = lib().or_window_rect(float(s), out_w, out_h, H, W, float(r), float(mx), float(my),
-                              float(l11), float(l21), float(l22), rr)
+                              float(l11), float(l21), float(l22), int(mode), rr)
     return bool(ok), tuple(rr)
 
 
-def support_rects(H, W, s, mean, chol, radius=None, window=0.0):
+def support_rect_m(s, out_w, out_h, mx, my, l11, l21, l22, R=3.0, mode=0):
+    """The box of one Gaussian under either sampling convention."""
+    r = (ctypes.c_int32 * 4)()
+    ok = lib().or_support_rect_m(float(s), out_w, out_h, float(mx), float(my), float(l11),
+                                 float(l21), float(l22), float(R), int(mode), r)
+    return bool(ok), tuple(r)
+
+
+def pixel_d2(x, y, s, mode, mx, my, l11, l21, l22):
+    """Squared Mahalanobis distance of HR pixel (x, y) (the pinned sequence)."""
+    return lib().or_pixel_d2(int(x), int(y), float(s), int(mode), float(mx), float(my),
+                             float(l11), float(l21), float(l22))
+
+
+def support_rects(H, W, s, mean, chol, radius=None, window=0.0, mode=0):
     """Support boxes [n][4] (x0, x1, y0, y1; empty = x1 < x0) and the number of
     in-support (pixel, Gaussian) pairs.  window > 0: Algorithm 1's r-window
     with r = window instead of the standard-deviation box."""
@@ -137,11 +165,11 @@ def support_rects(H, W, s, mean, chol, radius=None, window=0.0):
     n = mean.shape[0]
     rects = np.zeros((n, 4), dtype=np.int32)
     total = lib().or_support_pairs(H, W, float(s), n, _p(mean), _p(chol), _p(rad),
-                                   float(window), _p(rects, _I32))
+                                   float(window), int(mode), _p(rects, _I32))
     return rects, int(total)
 
 
-def forward(H, W, s, mean, chol, color, opacity, radius=None, threads=1, window=0.0):
+def forward(H, W, s, mean, chol, color, opacity, radius=None, threads=1, window=0.0, mode=0):
     """HR image [3, out_h, out_w] (FP64) of one image.  threads > 1 runs the
     OpenMP variant (row bands; bitwise the same image)."""
     oh, ow = output_size(H, W, s)
@@ -149,7 +177,7 @@ def forward(H, W, s, mean, chol, color, opacity, radius=None, threads=1, window=
     rad = None if radius is None else _d(radius)
     out = np.zeros((3, oh, ow), dtype=np.float64)
     args = (H, W, float(s), mean.shape[0], _p(mean), _p(chol), _p(color), _p(opacity),
-            _p(rad), float(window), _p(out))
+            _p(rad), float(window), int(mode), _p(out))
     if threads > 1:
         lib().or_forward_mt(*args, int(threads))
     else:
@@ -158,7 +186,7 @@ def forward(H, W, s, mean, chol, color, opacity, radius=None, threads=1, window=
 
 
 def backward(H, W, s, mean, chol, color, opacity, grad_out, radius=None, threads=1,
-             window=0.0):
+             window=0.0, mode=0):
     """Gradients (mean, chol, color, opacity) for upstream dL/dI grad_out.
     threads > 1 runs the OpenMP variant (bitwise the same result)."""
     mean, chol, color, opacity = _d(mean), _d(chol), _d(color), _d(opacity)
@@ -168,7 +196,7 @@ def backward(H, W, s, mean, chol, color, opacity, grad_out, radius=None, threads
     gm, gc = np.zeros((n, 2)), np.zeros((n, 3))
     gcol, gop = np.zeros((n, 3)), np.zeros(n)
     args = (H, W, float(s), n, _p(mean), _p(chol), _p(color), _p(opacity), _p(rad),
-            float(window), _p(g), _p(gm), _p(gc), _p(gcol), _p(gop))
+            float(window), int(mode), _p(g), _p(gm), _p(gc), _p(gcol), _p(gop))
     if threads > 1:
         lib().or_backward_mt(*args, int(threads))
     else:
@@ -176,7 +204,8 @@ def backward(H, W, s, mean, chol, color, opacity, grad_out, radius=None, threads
     return gm, gc, gcol, gop
 
 
-def pixel_values(H, W, s, mean, chol, color, opacity, xs, ys, radius=None, window=0.0):
+def pixel_values(H, W, s, mean, chol, color, opacity, xs, ys, radius=None, window=0.0,
+                 mode=0):
     """Image values [3, npix] at HR pixels (xs[k], ys[k]) of one image."""
     mean, chol, color, opacity = _d(mean), _d(chol), _d(color), _d(opacity)
     rad = None if radius is None else _d(radius)
@@ -184,7 +213,7 @@ def pixel_values(H, W, s, mean, chol, color, opacity, xs, ys, radius=None, windo
     ys = np.ascontiguousarray(ys, dtype=np.int32)
     out = np.zeros((3, xs.size), dtype=np.float64)
     lib().or_pixel_values(H, W, float(s), mean.shape[0], _p(mean), _p(chol), _p(color),
-                          _p(opacity), _p(rad), float(window), xs.size, _p(xs, _I32),
+                          _p(opacity), _p(rad), float(window), int(mode), xs.size, _p(xs, _I32),
                           _p(ys, _I32), _p(out))
     return out
 
@@ -218,7 +247,7 @@ def radius_labels_batch(wl, tau):
     return out
 
 
-def tile_lists(H, W, s, mean, chol, tw, th, radius=None, window=0.0):
+def tile_lists(H, W, s, mean, chol, tw, th, radius=None, window=0.0, mode=0):
     """(counts [tiles] int32, lists [P] int32) for one image."""
     mean, chol = _d(mean), _d(chol)
     rad = None if radius is None else _d(radius)
@@ -226,11 +255,11 @@ def tile_lists(H, W, s, mean, chol, tw, th, radius=None, window=0.0):
     n_tiles = ((ow + tw - 1) // tw) * ((oh + th - 1) // th)
     counts = np.zeros(n_tiles, dtype=np.int32)
     total = lib().or_tile_lists(H, W, float(s), mean.shape[0], _p(mean), _p(chol), _p(rad),
-                                float(window), tw, th, _p(counts, _I32), None, 0)
+                                float(window), int(mode), tw, th, _p(counts, _I32), None, 0)
     lists = np.zeros(max(total, 1), dtype=np.int32)
     total2 = lib().or_tile_lists(H, W, float(s), mean.shape[0], _p(mean), _p(chol), _p(rad),
-                                 float(window), tw, th, _p(counts, _I32), _p(lists, _I32),
-                                 total)
+                                 float(window), int(mode), tw, th, _p(counts, _I32),
+                                 _p(lists, _I32), total)
     assert total2 == total
     return counts, lists[:total]
 
@@ -241,18 +270,18 @@ def _radius_slice(radius, sl):
     return None if radius is None else np.asarray(radius)[sl]
 
 
-def forward_batch(wl, radius=None, threads=1, window=0.0):
+def forward_batch(wl, radius=None, threads=1, window=0.0, mode=0):
     """List of FP64 images [3, oh, ow], one per image of the workload."""
     out = []
     for k, im in enumerate(wl.images):
         sl = wl.image_slice(k)
         out.append(forward(im.lr_h, im.lr_w, im.scale, wl.mean[sl], wl.chol[sl],
                            wl.color[sl], wl.opacity[sl], _radius_slice(radius, sl), threads,
-                           window))
+                           window, mode))
     return out
 
 
-def backward_batch(wl, grads_out, radius=None, threads=1, window=0.0):
+def backward_batch(wl, grads_out, radius=None, threads=1, window=0.0, mode=0):
     """Packed gradients over the whole batch for per-image upstream gradients."""
     n = wl.n_gauss
     gm, gc = np.zeros((n, 2)), np.zeros((n, 3))
@@ -261,12 +290,12 @@ def backward_batch(wl, grads_out, radius=None, threads=1, window=0.0):
         sl = wl.image_slice(k)
         a, b, c, d = backward(im.lr_h, im.lr_w, im.scale, wl.mean[sl], wl.chol[sl],
                               wl.color[sl], wl.opacity[sl], grads_out[k],
-                              _radius_slice(radius, sl), threads, window)
+                              _radius_slice(radius, sl), threads, window, mode)
         gm[sl], gc[sl], gcol[sl], gop[sl] = a, b, c, d
     return gm, gc, gcol, gop
 
 
-def tile_lists_batch(wl, tw, th, radius=None, window=0.0):
+def tile_lists_batch(wl, tw, th, radius=None, window=0.0, mode=0):
     """Tile ranges and concatenated lists with tiles numbered image after image
     and Gaussian ids global over the packed batch.
 
@@ -276,7 +305,7 @@ def tile_lists_batch(wl, tw, th, radius=None, window=0.0):
     for k, im in enumerate(wl.images):
         sl = wl.image_slice(k)
         c, l = tile_lists(im.lr_h, im.lr_w, im.scale, wl.mean[sl], wl.chol[sl], tw, th,
-                          _radius_slice(radius, sl), window)
+                          _radius_slice(radius, sl), window, mode)
         counts_all.append(c)
         lists_all.append(l + im.g_begin)
     counts = np.concatenate(counts_all).astype(np.int64)
@@ -288,13 +317,13 @@ def tile_lists_batch(wl, tw, th, radius=None, window=0.0):
     return ranges.astype(np.int32), lists
 
 
-def support_pairs_batch(wl, radius=None, window=0.0):
+def support_pairs_batch(wl, radius=None, window=0.0, mode=0):
     """Total in-support (pixel, Gaussian) pairs over the batch."""
     total = 0
     for k, im in enumerate(wl.images):
         sl = wl.image_slice(k)
         total += support_rects(im.lr_h, im.lr_w, im.scale, wl.mean[sl], wl.chol[sl],
-                               _radius_slice(radius, sl), window)[1]
+                               _radius_slice(radius, sl), window, mode)[1]
     return total
 
 
