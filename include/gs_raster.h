@@ -113,6 +113,21 @@ typedef struct {
                                     bits) instead of counting each pair into
                                     its tile and sorting every tile's list
                                     (default).  Same lists, bitwise.           */
+#define GS_FLAG_PIXEL_CENTER 0x8 /* alternative reading of Eq. 4: HR pixel x
+                                    samples the LR coordinate (x + 1/2)/s - 1/2
+                                    (pixel centres of both grids aligned)
+                                    instead of x/s; boxes and windows move with
+                                    it (HR centre s (mu + 1/2) - 1/2).          */
+#define GS_FLAG_ELLIPSE 0x10     /* alternative reading of the truncation: a
+                                    pixel of the box is in the support only if
+                                    its Mahalanobis distance d (d^2 = z1^2 +
+                                    z2^2, z1 = (u - mu_x)/l11, z2 = ((v - mu_y)
+                                    - l21 z1)/l22, evaluated in FP64 in that
+                                    order) is below R; tile lists still follow
+                                    the box.  Not with window_r > 0
+                                    (GS_E_INVALID); lds_batch must be 0 or
+                                    the tile size's default
+                                    (GS_E_UNSUPPORTED).                        */
 
 /* ABI version of the loaded library (GS_ABI_VERSION). */
 int32_t gs_abi_version(void);

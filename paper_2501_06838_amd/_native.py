@@ -24,6 +24,8 @@ ABI_VERSION = 3  # GS_ABI_VERSION of include/gs_raster.h
 GS_FLAG_PERSISTENT = 0x1
 GS_FLAG_ATOMIC_GRADS = 0x2
 GS_FLAG_RADIX_SORT = 0x4
+GS_FLAG_PIXEL_CENTER = 0x8
+GS_FLAG_ELLIPSE = 0x10
 
 EXPORTED = (
     "gs_abi_version", "gs_status_string", "gs_output_size", "gs_workspace_size",

@@ -50,10 +50,14 @@ gs_status make_layout(const gs_config* cfg, const gs_image* images, int32_t n_im
                           (l.tile == 32 && (l.lds_batch == 32 || l.lds_batch == 64));
     if (!ok_batch) return GS_E_UNSUPPORTED;
     l.flags = cfg ? cfg->flags : 0;
-    if (l.flags & ~(GS_FLAG_PERSISTENT | GS_FLAG_ATOMIC_GRADS | GS_FLAG_RADIX_SORT))
+    if (l.flags & ~(GS_FLAG_PERSISTENT | GS_FLAG_ATOMIC_GRADS | GS_FLAG_RADIX_SORT |
+                    GS_FLAG_PIXEL_CENTER | GS_FLAG_ELLIPSE))
         return GS_E_INVALID;
     l.window_r = cfg ? cfg->window_r : 0.0;
     if (!std::isfinite(l.window_r) || l.window_r < 0.0) return GS_E_INVALID;
+    if ((l.flags & GS_FLAG_ELLIPSE) && l.window_r > 0.0) return GS_E_INVALID;
+    // the elliptical tile kernels exist at each tile size's default batch only
+    if ((l.flags & GS_FLAG_ELLIPSE) && l.lds_batch != dflt) return GS_E_UNSUPPORTED;
     l.n_img = n_img;
     l.n_gauss = n_gauss;
 
@@ -116,6 +120,10 @@ gs_status make_layout(const gs_config* cfg, const gs_image* images, int32_t n_im
     l.off_ranges = off; off = align_up(off + sizeof(int2) * (size_t)tiles);
     l.off_tile_cnt = off; off = align_up(off + sizeof(int32_t) * (size_t)tiles);
     l.off_moments = off; off = align_up(off + sizeof(float) * 8 * (size_t)n_gauss);
+    if (l.flags & GS_FLAG_ELLIPSE) {
+        l.off_eparams = off;
+        off = align_up(off + sizeof(EParams) * (size_t)n_gauss);
+    }
     l.off_tile_loss = off; off = align_up(off + sizeof(double) * (size_t)tiles);
     l.off_loss_parts = off;
     off = align_up(off + sizeof(double) * (size_t)std::max<int64_t>(

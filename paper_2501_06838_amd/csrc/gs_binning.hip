@@ -73,7 +73,7 @@ __device__ __forceinline__ bool finite_d(double v) { return __builtin_isfinite(v
 // Returns false when the box is empty or the parameters are invalid;
 // *clipped tells whether the image border cut the box.
 __device__ bool support_box(double s, int out_w, int out_h, double mx, double my,
-                            double l11, double l21, double l22, double R, int* box,
+                            double l11, double l21, double l22, double R, bool centre, int* box,
                             bool* clipped) {
 #pragma clang fp contract(off)
     if (!finite_d(mx) || !finite_d(my) || !finite_d(l11) || !finite_d(l21) ||
@@ -82,10 +82,11 @@ __device__ bool support_box(double s, int out_w, int out_h, double mx, double my
     if (!(l11 > 0.0) || !(l22 > 0.0) || !(R > 0.0)) return false;
     const double sx = l11;
     const double sy = __dsqrt_rn(l21 * l21 + l22 * l22);
-    const double lo_x = s * (mx - R * sx);
-    const double hi_x = s * (mx + R * sx);
-    const double lo_y = s * (my - R * sy);
-    const double hi_y = s * (my + R * sy);
+    // pixel-centre sampling: {x : s((mu - R sd) + 1/2) - 1/2 < x < ...}
+    const double lo_x = centre ? s * ((mx - R * sx) + 0.5) - 0.5 : s * (mx - R * sx);
+    const double hi_x = centre ? s * ((mx + R * sx) + 0.5) - 0.5 : s * (mx + R * sx);
+    const double lo_y = centre ? s * ((my - R * sy) + 0.5) - 0.5 : s * (my - R * sy);
+    const double hi_y = centre ? s * ((my + R * sy) + 0.5) - 0.5 : s * (my + R * sy);
     double x0 = __builtin_floor(lo_x) + 1.0, x1 = __builtin_ceil(hi_x) - 1.0;
     double y0 = __builtin_floor(lo_y) + 1.0, y1 = __builtin_ceil(hi_y) - 1.0;
     *clipped = x0 < 0.0 || y0 < 0.0 || x1 > (double)(out_w - 1) || y1 > (double)(out_h - 1);
@@ -104,8 +105,8 @@ __device__ bool support_box(double s, int out_w, int out_h, double mx, double my
 // Gaussian must still be valid.  Same FP64 operation sequence as the
 // standard-deviation box, so boxes are reproducible bit for bit.
 __device__ bool window_box(double s, int out_w, int out_h, int lr_w, int lr_h, double r,
-                           double mx, double my, double l11, double l21, double l22, int* box,
-                           bool* clipped) {
+                           double mx, double my, double l11, double l21, double l22,
+                           bool centre, int* box, bool* clipped) {
 #pragma clang fp contract(off)
     if (!finite_d(mx) || !finite_d(my) || !finite_d(l11) || !finite_d(l21) ||
         !finite_d(l22) || !finite_d(r))
@@ -113,7 +114,8 @@ __device__ bool window_box(double s, int out_w, int out_h, int lr_w, int lr_h, d
     if (!(l11 > 0.0) || !(l22 > 0.0) || !(r > 0.0)) return false;
     const double hx = r * (s * (double)lr_w);
     const double hy = r * (s * (double)lr_h);
-    const double cx = s * mx, cy = s * my;
+    const double cx = centre ? s * (mx + 0.5) - 0.5 : s * mx;
+    const double cy = centre ? s * (my + 0.5) - 0.5 : s * my;
     double x0 = __builtin_floor(cx - hx) + 1.0, x1 = __builtin_ceil(cx + hx) - 1.0;
     double y0 = __builtin_floor(cy - hy) + 1.0, y1 = __builtin_ceil(cy + hy) - 1.0;
     *clipped = x0 < 0.0 || y0 < 0.0 || x1 > (double)(out_w - 1) || y1 > (double)(out_h - 1);
@@ -137,7 +139,8 @@ __global__ __launch_bounds__(kBlockG) void k_support(
     ImgChunk arg_imgs, ImgDev* __restrict__ imgs, int n_img, int64_t n_gauss, int tile,
     const float* __restrict__ mean, const float* __restrict__ chol,
     const float* __restrict__ color, const float* __restrict__ opacity,
-    const float* __restrict__ radius, double window_r, GRec* __restrict__ recs,
+    const float* __restrict__ radius, double window_r, int mode, EParams* __restrict__ eparams,
+    GRec* __restrict__ recs,
     int32_t* __restrict__ counts, BlockSums* __restrict__ blocksums,
     int32_t* __restrict__ tile_cnt, int2* __restrict__ ranges_clear, int64_t n_tiles,
     float4* __restrict__ moments, uint32_t* __restrict__ counters) {
@@ -177,11 +180,12 @@ __global__ __launch_bounds__(kBlockG) void k_support(
             const bool shape_ok = finite_d(mx) && finite_d(my) && finite_d(l11) &&
                                   finite_d(l21) && finite_d(l22) && l11 > 0.0 && l22 > 0.0;
             bad = shape_ok ? 0 : 1;
+            const bool centre = (mode & GS_FLAG_PIXEL_CENTER) != 0;
             const bool has_box =
                 window_r > 0.0
                     ? window_box(s, im.out_w, im.out_h, im.lr_w, im.lr_h, window_r, mx, my, l11,
-                                 l21, l22, box, &clipped)
-                    : support_box(s, im.out_w, im.out_h, mx, my, l11, l21, l22, R, box,
+                                 l21, l22, centre, box, &clipped)
+                    : support_box(s, im.out_w, im.out_h, mx, my, l11, l21, l22, R, centre, box,
                                   &clipped);
             if (has_box) {
                 // colour / opacity may be NULL when only the pairs are counted
@@ -192,7 +196,8 @@ __global__ __launch_bounds__(kBlockG) void k_support(
                 const bool amp_ok = finite_d(al) && finite_d(c0) && finite_d(c1) && finite_d(c2);
                 if (!amp_ok) bad = 1;
                 r.x0 = box[0]; r.x1 = box[1]; r.y0 = box[2]; r.y1 = box[3];
-                const double cx = s * mx, cy = s * my;
+                const double cx = centre ? s * (mx + 0.5) - 0.5 : s * mx;
+                const double cy = centre ? s * (my + 0.5) - 0.5 : s * my;
                 const double lim = 1073741824.0;  // keep the integer part in int32
                 const double kx = __builtin_floor(fmin(fmax(cx, -lim), lim));
                 const double ky = __builtin_floor(fmin(fmax(cy, -lim), lim));
@@ -215,7 +220,23 @@ __global__ __launch_bounds__(kBlockG) void k_support(
                 const int tx0 = r.x0 / tile, tx1 = r.x1 / tile;
                 const int ty0 = r.y0 / tile, ty1 = r.y1 / tile;
                 cnt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
-                area = (int64_t)(r.x1 - r.x0 + 1) * (r.y1 - r.y0 + 1);
+                if (eparams) {
+                    // elliptical support: the tile kernels rebuild its pixel
+                    // masks from these; the in-support pairs are its pixels
+                    r.flags |= kRecEllipse;
+                    eparams[i].p0 = make_float4(mean[2 * i], mean[2 * i + 1], chol[3 * i],
+                                                chol[3 * i + 1]);
+                    eparams[i].p1 = make_float4(chol[3 * i + 2], (float)R, centre ? 1.f : 0.f, 0.f);
+                    const double R2 = R * R;
+                    for (int y = r.y0; y <= r.y1; ++y) {
+                        int xa, xb;
+                        ellipse_row(y, r.x0, r.x1, s, centre, mx, my, l11, l21, l22, R2, &xa,
+                                    &xb);
+                        if (xb >= xa) area += xb - xa + 1;
+                    }
+                } else {
+                    area = (int64_t)(r.x1 - r.x0 + 1) * (r.y1 - r.y0 + 1);
+                }
             }
         }
         recs[i] = r;
@@ -997,12 +1018,12 @@ hipError_t launch_support(const Layout& L, const Ws& w, const ImgDev* host_imgs,
     if (by_value)
         hipLaunchKernelGGL(k_support<true>, dim3(L.nblk_g), dim3(kBlockG), 0, st, chunk, w.imgs,
                            L.n_img, L.n_gauss, L.tile, mean, chol, color, opacity, radius,
-                           L.window_r, w.recs, w.counts, w.blocksums, w.tile_cnt, radix ? w.ranges : nullptr, L.n_tiles, mom,
+                           L.window_r, L.flags, w.eparams, w.recs, w.counts, w.blocksums, w.tile_cnt, radix ? w.ranges : nullptr, L.n_tiles, mom,
                            w.counters);
     else
         hipLaunchKernelGGL(k_support<false>, dim3(L.nblk_g), dim3(kBlockG), 0, st, chunk, w.imgs,
                            L.n_img, L.n_gauss, L.tile, mean, chol, color, opacity, radius,
-                           L.window_r, w.recs, w.counts, w.blocksums, w.tile_cnt, radix ? w.ranges : nullptr, L.n_tiles, mom,
+                           L.window_r, L.flags, w.eparams, w.recs, w.counts, w.blocksums, w.tile_cnt, radix ? w.ranges : nullptr, L.n_tiles, mom,
                            w.counters);
     if (count_only || L.nblk_g > kFoldScanBlocks)
         hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kBlockG), 0, st, w.blocksums, L.nblk_g,

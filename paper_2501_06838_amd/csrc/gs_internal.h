@@ -74,6 +74,65 @@ constexpr int32_t kRecClipped = 2;
 // the tile kernels drop (block, Gaussian) records whose weights all round to
 // zero.
 constexpr int32_t kRecCull = 4;
+// The support is the ellipse d < R inside the box: the tile kernels build the
+// pixel masks from the Gaussian's exact parameters (eparams).
+constexpr int32_t kRecEllipse = 8;
+
+// Per Gaussian, for the elliptical support: {mu_x, mu_y, l11, l21},
+// {l22, R, centre, 0} (the FP32 inputs, widened to FP64 where used; centre
+// is 1 with GS_FLAG_PIXEL_CENTER).
+struct EParams {
+    float4 p0, p1;
+};
+
+// The LR coordinate HR pixel index x samples: x / s, or (x + 1/2)/s - 1/2
+// with pixel-centre sampling.
+__device__ __forceinline__ double sample_u(int x, double s, bool centre) {
+#pragma clang fp contract(off)
+    return centre ? ((double)x + 0.5) / s - 0.5 : (double)x / s;
+}
+
+// Elliptical support membership of HR pixel (x, y): d^2 < R^2 with
+// z1 = (u - mu_x)/l11, z2 = ((v - mu_y) - l21 z1)/l22, d^2 = z1 z1 + z2 z2,
+// evaluated in FP64 in exactly this order (IEEE division, no contraction), so
+// the decision is reproducible bit for bit.
+__device__ __forceinline__ bool in_ellipse(int x, int y, double s, bool centre, double mx,
+                                           double my, double l11, double l21, double l22,
+                                           double R2) {
+#pragma clang fp contract(off)
+    const double z1 = (sample_u(x, s, centre) - mx) / l11;
+    const double z2 = ((sample_u(y, s, centre) - my) - l21 * z1) / l22;
+    return z1 * z1 + z2 * z2 < R2;
+}
+
+// The pixels [*xa, *xb] of HR row y within [x0, x1] inside the ellipse
+// (*xa > *xb when none).  Along a row d^2 is a convex quadratic, so the set
+// is an interval: its ends come from the analytic roots (FP64), and the
+// pixels within two of them are decided by in_ellipse itself.
+__device__ __forceinline__ void ellipse_row(int y, int x0, int x1, double s, bool centre,
+                                            double mx, double my, double l11, double l21,
+                                            double l22, double R2, int* xa, int* xb) {
+    const double c = centre ? 0.5 : 0.0;
+    const double dy = sample_u(y, s, centre) - my;
+    const double k = l21 / l22;
+    const double A = 1.0 + k * k;
+    const double B = dy * k / l22;
+    const double C = (dy / l22) * (dy / l22) - R2;
+    const double disc = B * B - A * C;
+    const double zc = B / A;
+    const double r = disc > 0.0 ? sqrt(disc) / A : 0.0;
+    // HR x of z1: s (mu_x + l11 z1 + c) - c, clamped near the range
+    const double lim_lo = (double)x0 - 4.0, lim_hi = (double)x1 + 4.0;
+    double xl = s * (mx + l11 * (zc - r) + c) - c;
+    double xh = s * (mx + l11 * (zc + r) + c) - c;
+    xl = fmin(fmax(xl, lim_lo), lim_hi);
+    xh = fmin(fmax(xh, lim_lo), lim_hi);
+    int a = max(x0, (int)ceil(xl) - 2), b = min(x1, (int)floor(xh) + 2);
+    while (a <= b && !in_ellipse(a, y, s, centre, mx, my, l11, l21, l22, R2)) ++a;
+    while (b >= a && !in_ellipse(b, y, s, centre, mx, my, l11, l21, l22, R2)) --b;
+    *xa = a;
+    *xb = b;
+}
 static_assert(sizeof(GRec) == 64, "GRec layout");
 
 
@@ -114,7 +173,7 @@ struct Layout {
     size_t off_header = 0, off_imgs = 0, off_recs = 0, off_counts = 0, off_offsets = 0,
            off_blocksums = 0, off_tile_cnt = 0, off_loss_parts = 0, off_scan_sums = 0, off_slots = 0, off_lists = 0, off_spare = 0,
            off_ranges = 0, off_moments = 0, off_tile_loss = 0, off_partials = 0,
-           off_keys1 = 0, off_hist = 0, total = 0;
+           off_keys1 = 0, off_hist = 0, off_eparams = 0, total = 0;
     const ImgDev* host_imgs = nullptr;  // host copy of the table (valid during a call)
 };
 
@@ -141,6 +200,7 @@ struct Ws {
     double* tile_loss;
     double* loss_parts;  // per workgroup of the loss reduction: its tiles' sum
     float4* partials;    // per emitted pair (emission order): 8 backward sums (2 x float4)
+    EParams* eparams;    // GS_FLAG_ELLIPSE: per Gaussian, its exact parameters (else null)
     uint32_t* order;     // tiles, longest list first (persistent kernels)
     int32_t* order_hist; // histograms of the tile-order sort
     uint32_t* counters;  // device counters (kCounterWords, zeroed by the binning)
@@ -170,6 +230,7 @@ inline Ws bind(const Layout& L, void* base) {
     w.tile_loss = reinterpret_cast<double*>(b + L.off_tile_loss);
     w.loss_parts = reinterpret_cast<double*>(b + L.off_loss_parts);
     w.partials = reinterpret_cast<float4*>(b + L.off_partials);
+    w.eparams = L.off_eparams ? reinterpret_cast<EParams*>(b + L.off_eparams) : nullptr;
     w.order = reinterpret_cast<uint32_t*>(b + L.off_order);
     w.order_hist = reinterpret_cast<int32_t*>(b + L.off_order_hist);
     w.counters = reinterpret_cast<uint32_t*>(b + L.off_counters);

@@ -58,10 +58,11 @@ struct TileShape {
 // latency bound, so at 16 x 16 the register budget follows the workgroups
 // the LDS fits per CU: eight with 64 or 96 Gaussians per round (64 VGPRs),
 // seven with 112 (72), six with 128 (80); a few values spill, outside the
-// pixel loops.  Elsewhere the compiler's own register count decides.
-template <int T, int B>
+// pixel loops.  Elsewhere (and for the elliptical supports, whose FP64 mask
+// building needs more) the compiler's own register count decides.
+template <int T, int B, bool kEll>
 struct BwdOccupancy {
-    static constexpr int kMinWaves = T != 16 ? 1
+    static constexpr int kMinWaves = (T != 16 || kEll) ? 1
                                    : (B == 64 || B == 96) ? 8
                                    : B == 112             ? 7
                                    : B == 128             ? 6
@@ -161,11 +162,41 @@ __device__ __forceinline__ float box_qlow(float a, float e, float g, float z10, 
 // Stages entries [base, base + nb) of the tile's sorted list (Gaussian ids)
 // from the Gaussians' render records and builds the per-block record lists.
 // Ends with a barrier.
-template <int T, int B>
+// Pixel masks of an elliptical record: row by row, the pixels of the box
+// within the tile whose Mahalanobis distance is below R (ellipse_row: the
+// same FP64 predicate as the definition), split over the tile's blocks.
+template <int T>
+__device__ void ellipse_masks(const EParams& ep, double s, const TileInfo& ti, int lx0, int lx1,
+                              int ly0, int ly1, uint64_t (&mask)[TileShape<T>::kBlocks]) {
+    using S = TileShape<T>;
+    const double mx = ep.p0.x, my = ep.p0.y, l11 = ep.p0.z, l21 = ep.p0.w, l22 = ep.p1.x;
+    const double R = ep.p1.y;
+    const bool centre = ep.p1.z != 0.f;
+    for (int ly = ly0; ly <= ly1; ++ly) {
+        int xa, xb;
+        ellipse_row(ti.py0 + ly, ti.px0 + lx0, ti.px0 + lx1, s, centre, mx, my, l11, l21, l22,
+                    R * R, &xa, &xb);
+        if (xa > xb) continue;
+        xa -= ti.px0;
+        xb -= ti.px0;
+        const int byi = ly >> 3, ry = ly & 7;
+#pragma unroll
+        for (int j = 0; j < S::kBlocks; ++j) {
+            if (j / S::kBlocksX != byi) continue;
+            const int bx = (j % S::kBlocksX) * 8;
+            const int c0 = max(xa, bx) - bx, c1 = min(xb, bx + 7) - bx;
+            if (c0 <= c1)
+                mask[j] |= (uint64_t)(((1u << (c1 - c0 + 1)) - 1u) << c0) << (8 * ry);
+        }
+    }
+}
+
+template <int T, int B, bool kEll>
 __device__ __forceinline__ StagedMine stage_round(StageLds<T, B>& st,
                                                   const uint32_t* __restrict__ svals,
                                                   const GRec* __restrict__ recs,
                                                   const int32_t* __restrict__ offsets,
+                                                  const EParams* __restrict__ eparams,
                                                   const TileInfo& ti, int base, int nb) {
     using S = TileShape<T>;
     constexpr int NB = S::kBlocks;
@@ -190,21 +221,27 @@ __device__ __forceinline__ StagedMine stage_round(StageLds<T, B>& st,
         const int lx0 = max(r.x0 - ti.px0, 0), lx1 = min(r.x1 - ti.px0, T - 1);
         const int ly0 = max(r.y0 - ti.py0, 0), ly1 = min(r.y1 - ti.py0, T - 1);
         const bool cull = (r.flags & kRecCull) != 0;
+        if constexpr (kEll) {
+            // every listed record is elliptical
+            if (lx0 <= lx1 && ly0 <= ly1)
+                ellipse_masks<T>(eparams[mine.gid], ti.im.scale, ti, lx0, lx1, ly0, ly1, my_mask);
+        } else {
 #pragma unroll
-        for (int j = 0; j < NB; ++j) {
-            const int bx = (j % S::kBlocksX) * 8, by = (j / S::kBlocksX) * 8;
-            const int c0 = max(lx0, bx) - bx, c1 = min(lx1, bx + 7) - bx;
-            const int r0 = max(ly0, by) - by, r1 = min(ly1, by + 7) - by;
-            if (c0 <= c1 && r0 <= r1) {
-                if (cull) {
-                    const float Xb = (kxr + (float)bx) - r.fx;
-                    const float Yb = (kyr + (float)by) - r.fy;
-                    if (box_qlow(r.a, r.e, r.g, r.a * Xb, r.e * Yb - r.g * Xb, (float)c0,
-                                 (float)c1, (float)r0, (float)r1) > kQCull)
-                        continue;
+            for (int j = 0; j < NB; ++j) {
+                const int bx = (j % S::kBlocksX) * 8, by = (j / S::kBlocksX) * 8;
+                const int c0 = max(lx0, bx) - bx, c1 = min(lx1, bx + 7) - bx;
+                const int r0 = max(ly0, by) - by, r1 = min(ly1, by + 7) - by;
+                if (c0 <= c1 && r0 <= r1) {
+                    if (cull) {
+                        const float Xb = (kxr + (float)bx) - r.fx;
+                        const float Yb = (kyr + (float)by) - r.fy;
+                        if (box_qlow(r.a, r.e, r.g, r.a * Xb, r.e * Yb - r.g * Xb, (float)c0,
+                                     (float)c1, (float)r0, (float)r1) > kQCull)
+                            continue;
+                    }
+                    const uint64_t cols = ((1ull << (c1 - c0 + 1)) - 1ull) << c0;
+                    my_mask[j] = (cols * 0x0101010101010101ull) & rows_mask(r0, r1);
                 }
-                const uint64_t cols = ((1ull << (c1 - c0 + 1)) - 1ull) << c0;
-                my_mask[j] = (cols * 0x0101010101010101ull) & rows_mask(r0, r1);
             }
         }
     }
@@ -306,10 +343,11 @@ __device__ __forceinline__ void fwd_round(const StageLds<T, B>& st,
 // so the z1 moments follow from the column's sums of H w, H w z2 and
 // H w z2^2 (H = sum_c A_c G_c).  rec0 = {z1, z2 at the block's first pixel,
 // a, e}, rec1 = {g, A0, A1, A2}.
-template <int T, bool kFull>
+template <int T, bool kFull, bool kMask>
 __device__ __forceinline__ void bwd_columns(const float4* __restrict__ gcol, uint32_t colset,
-                                            uint32_t rows, int cx0, int cx1, int ry0, int ry1,
-                                            float4 rec0, float4 rec1, float (&m)[8]) {
+                                            uint32_t rows, uint32_t mlo, uint32_t mhi, int cx0,
+                                            int cx1, int ry0, int ry1, float4 rec0, float4 rec1,
+                                            float (&m)[8]) {
     const float a = rec0.z, e = rec0.w, gg = rec1.x;
     bool rv[8];
 #pragma unroll
@@ -317,7 +355,10 @@ __device__ __forceinline__ void bwd_columns(const float4* __restrict__ gcol, uin
 #pragma unroll
     for (int cx = 0; cx < 8; ++cx) {
         if (!kFull && (cx < cx0 || cx > cx1)) continue;  // uniform
-        const float z1 = ((colset >> cx) & 1u) ? __builtin_fmaf(a, (float)cx, rec0.x) : 1e19f;
+        // kMask: the record's pixel mask decides every pixel (elliptical
+        // supports); a rectangular box gives the same bits either way
+        const float z1 = (kMask || ((colset >> cx) & 1u)) ? __builtin_fmaf(a, (float)cx, rec0.x)
+                                                          : 1e19f;
         const float z1sq = z1 * z1;
         const float zb = __builtin_fmaf(-gg, (float)cx, rec0.y);
         float sa = 0.f, sb = 0.f, sc = 0.f;
@@ -327,7 +368,10 @@ __device__ __forceinline__ void bwd_columns(const float4* __restrict__ gcol, uin
             const float4 G = gcol[ry * T + cx];
             const float z2 = __builtin_fmaf(e, (float)ry, zb);
             float w = fast_exp2(-__builtin_fmaf(z2, z2, z1sq));
-            w = rv[ry] ? w : 0.f;
+            if (kMask)
+                w = (((ry < 4 ? mlo : mhi) >> (8 * (ry & 3) + cx)) & 1u) ? w : 0.f;
+            else
+                w = rv[ry] ? w : 0.f;
             m[0] = __builtin_fmaf(G.x, w, m[0]);
             m[1] = __builtin_fmaf(G.y, w, m[1]);
             m[2] = __builtin_fmaf(G.z, w, m[2]);
@@ -346,7 +390,7 @@ __device__ __forceinline__ void bwd_columns(const float4* __restrict__ gcol, uin
     }
 }
 
-template <int T, int B>
+template <int T, int B, bool kEll>
 __device__ __forceinline__ void bwd_round(BwdLds<T, B>& sm) {
     using S = TileShape<T>;
     constexpr int NB = S::kBlocks, NW = S::kWaves;
@@ -387,10 +431,14 @@ __device__ __forceinline__ void bwd_round(BwdLds<T, B>& sm) {
         const uint32_t colset = cm & 255u;
         const float4* gcol = &sm.gt[by * T + bx];
         float m[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        if (cx0 == 0 && cx1 == 7 && ry0 == 0 && ry1 == 7)  // uniform: the whole block
-            bwd_columns<T, true>(gcol, colset, rows, 0, 7, 0, 7, c0, c1, m);
+        if constexpr (kEll)  // elliptical supports: the pixel mask decides
+            bwd_columns<T, false, true>(gcol, colset, rows, mlo, mhi, cx0, cx1, ry0, ry1, c0,
+                                        c1, m);
+        else if (cx0 == 0 && cx1 == 7 && ry0 == 0 && ry1 == 7)  // uniform: the whole block
+            bwd_columns<T, true, false>(gcol, colset, rows, mlo, mhi, 0, 7, 0, 7, c0, c1, m);
         else
-            bwd_columns<T, false>(gcol, colset, rows, cx0, cx1, ry0, ry1, c0, c1, m);
+            bwd_columns<T, false, false>(gcol, colset, rows, mlo, mhi, cx0, cx1, ry0, ry1, c0,
+                                         c1, m);
         const float m0 = m[0], m1 = m[1], m2 = m[2], m3 = m[3], m4 = m[4], m5 = m[5],
                     m6 = m[6], m7 = m[7];
         if (active) {
@@ -456,10 +504,10 @@ __device__ __forceinline__ TileInfo tile_info(const Table& imgs, int n_img,
     return ti;
 }
 
-template <int T, int B, typename Table>
+template <int T, int B, bool kEll, typename Table>
 __device__ __forceinline__ void fwd_tile(FwdLds<T, B>& sm, const Table& imgs, int n_img,
                                          const uint32_t* __restrict__ svals, const GRec* __restrict__ recs,
-    const int32_t* __restrict__ offsets,
+    const int32_t* __restrict__ offsets, const EParams* __restrict__ eparams,
                                          const int2* __restrict__ ranges,
                                          float* __restrict__ out, int64_t tile) {
     using S = TileShape<T>;
@@ -469,7 +517,7 @@ __device__ __forceinline__ void fwd_tile(FwdLds<T, B>& sm, const Table& imgs, in
 #pragma unroll
     for (int m = 0; m < S::kBlocksPerWave; ++m) acc[m][0] = acc[m][1] = acc[m][2] = 0.f;
     for (int base = ti.rg.x; base < ti.rg.y; base += B) {
-        stage_round<T, B>(sm.st, svals, recs, offsets, ti, base, min(B, ti.rg.y - base));
+        stage_round<T, B, kEll>(sm.st, svals, recs, offsets, eparams, ti, base, min(B, ti.rg.y - base));
         fwd_round<T, B>(sm.st, acc);
         __syncthreads();
     }
@@ -507,10 +555,10 @@ __device__ __forceinline__ void tile_loss_sum(BwdLds<T, B>& sm, double lsum,
 // kL1: the upstream gradient is the L1 loss's, sign(out - target) / numel,
 // formed here from the rendered image and the target (it is never stored),
 // and the tile's share of sum |out - target| goes to tile_loss[tile].
-template <int T, int B, bool kL1, typename Table>
+template <int T, int B, bool kL1, bool kEll, typename Table>
 __device__ __forceinline__ void bwd_tile(
     BwdLds<T, B>& sm, const Table& imgs, int n_img, const uint32_t* __restrict__ svals, const GRec* __restrict__ recs,
-    const int32_t* __restrict__ offsets,
+    const int32_t* __restrict__ offsets, const EParams* __restrict__ eparams,
     const int2* __restrict__ ranges, const float* __restrict__ grad_out,
     const float* __restrict__ target, float inv_numel, double* __restrict__ tile_loss,
     float* __restrict__ moments, float4* __restrict__ partials, int atomic_grads,
@@ -549,8 +597,8 @@ __device__ __forceinline__ void bwd_tile(
 
     for (int base = ti.rg.x; base < ti.rg.y; base += B) {
         const int nb = min(B, ti.rg.y - base);
-        const StagedMine mine = stage_round<T, B>(sm.st, svals, recs, offsets, ti, base, nb);
-        bwd_round<T, B>(sm);
+        const StagedMine mine = stage_round<T, B, kEll>(sm.st, svals, recs, offsets, eparams, ti, base, nb);
+        bwd_round<T, B, kEll>(sm);
         bwd_round_store<T, B>(sm, mine, base, nb, moments, partials, atomic_grads);
     }
 }
@@ -560,10 +608,10 @@ __device__ __forceinline__ void bwd_tile(
 // pixels from them and the target into LDS (with the tile's L1 sum); the
 // backward then runs over the same records, which stay staged when the
 // tile's list fits one round.
-template <int T, int B, typename Table>
+template <int T, int B, bool kEll, typename Table>
 __device__ __forceinline__ void fused_tile(
     BwdLds<T, B>& sm, const Table& imgs, int n_img, const uint32_t* __restrict__ svals, const GRec* __restrict__ recs,
-    const int32_t* __restrict__ offsets,
+    const int32_t* __restrict__ offsets, const EParams* __restrict__ eparams,
     const int2* __restrict__ ranges, float* __restrict__ out, const float* __restrict__ target,
     float inv_numel, double* __restrict__ tile_loss, float* __restrict__ moments,
     float4* __restrict__ partials, int atomic_grads, int64_t tile) {
@@ -576,7 +624,7 @@ __device__ __forceinline__ void fused_tile(
     const bool one_round = ti.rg.y - ti.rg.x <= B;
     StagedMine mine{0u, 0u, 0};
     for (int base = ti.rg.x; base < ti.rg.y; base += B) {
-        mine = stage_round<T, B>(sm.st, svals, recs, offsets, ti, base, min(B, ti.rg.y - base));
+        mine = stage_round<T, B, kEll>(sm.st, svals, recs, offsets, eparams, ti, base, min(B, ti.rg.y - base));
         fwd_round<T, B>(sm.st, acc);
         if (!one_round) __syncthreads();
     }
@@ -611,15 +659,15 @@ __device__ __forceinline__ void fused_tile(
     tile_loss_sum<T, B>(sm, lsum, tile_loss, tile);  // has a barrier
     if (ti.rg.y <= ti.rg.x) return;  // uniform
     if (one_round) {
-        bwd_round<T, B>(sm);
+        bwd_round<T, B, kEll>(sm);
         bwd_round_store<T, B>(sm, mine, ti.rg.x, ti.rg.y - ti.rg.x, moments, partials,
                               atomic_grads);
         return;
     }
     for (int base = ti.rg.x; base < ti.rg.y; base += B) {
         const int nb = min(B, ti.rg.y - base);
-        mine = stage_round<T, B>(sm.st, svals, recs, offsets, ti, base, nb);
-        bwd_round<T, B>(sm);
+        mine = stage_round<T, B, kEll>(sm.st, svals, recs, offsets, eparams, ti, base, nb);
+        bwd_round<T, B, kEll>(sm);
         bwd_round_store<T, B>(sm, mine, base, nb, moments, partials, atomic_grads);
     }
 }
@@ -642,30 +690,30 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t n) {
 // One tile per workgroup (grid of n_tiles, XCD-aware order), or, with
 // `persistent`, a grid sized to the resident workgroups that walks the longest-first tile order
 // (without a tile order from the matching binning, items are tiles).
-template <int T, int B, typename Table>
+template <int T, int B, bool kEll, typename Table>
 __global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_fwd(
     Table imgs, int n_img, const uint32_t* __restrict__ svals, const GRec* __restrict__ recs,
-    const int32_t* __restrict__ offsets,
+    const int32_t* __restrict__ offsets, const EParams* __restrict__ eparams,
     const int2* __restrict__ ranges, float* __restrict__ out,
     const uint32_t* __restrict__ order, const WsHeader* __restrict__ hdr, int64_t n_tiles,
     int persistent) {
     __shared__ FwdLds<T, B> sm;
     if (!persistent) {
-        fwd_tile<T, B>(sm, imgs, n_img, svals, recs, offsets, ranges, out, xcd_tile(blockIdx.x, n_tiles));
+        fwd_tile<T, B, kEll>(sm, imgs, n_img, svals, recs, offsets, eparams, ranges, out, xcd_tile(blockIdx.x, n_tiles));
         return;
     }
     const bool ordered = hdr->ordered != 0;
     run_persistent(n_tiles, [&](int64_t item) {
         const int64_t tile = ordered ? (int64_t)order[item] : item;
-        if (tile < n_tiles) fwd_tile<T, B>(sm, imgs, n_img, svals, recs, offsets, ranges, out, tile);
+        if (tile < n_tiles) fwd_tile<T, B, kEll>(sm, imgs, n_img, svals, recs, offsets, eparams, ranges, out, tile);
     });
 }
 
-template <int T, int B, bool kL1, typename Table>
+template <int T, int B, bool kL1, bool kEll, typename Table>
 __global__ __launch_bounds__(TileShape<T>::kThreads)
-__attribute__((amdgpu_waves_per_eu(BwdOccupancy<T, B>::kMinWaves, 8))) void k_render_bwd(
+__attribute__((amdgpu_waves_per_eu(BwdOccupancy<T, B, kEll>::kMinWaves, 8))) void k_render_bwd(
     Table imgs, int n_img, const uint32_t* __restrict__ svals, const GRec* __restrict__ recs,
-    const int32_t* __restrict__ offsets,
+    const int32_t* __restrict__ offsets, const EParams* __restrict__ eparams,
     const int2* __restrict__ ranges, const float* __restrict__ grad_out,
     const float* __restrict__ target, float inv_numel, double* __restrict__ tile_loss,
     float* __restrict__ moments, float4* __restrict__ partials, int atomic_grads,
@@ -673,7 +721,7 @@ __attribute__((amdgpu_waves_per_eu(BwdOccupancy<T, B>::kMinWaves, 8))) void k_re
     int persistent) {
     __shared__ BwdLds<T, B> sm;
     if (!persistent) {
-        bwd_tile<T, B, kL1>(sm, imgs, n_img, svals, recs, offsets, ranges, grad_out, target, inv_numel,
+        bwd_tile<T, B, kL1, kEll>(sm, imgs, n_img, svals, recs, offsets, eparams, ranges, grad_out, target, inv_numel,
                             tile_loss, moments, partials, atomic_grads, xcd_tile(blockIdx.x, n_tiles));
         return;
     }
@@ -681,16 +729,16 @@ __attribute__((amdgpu_waves_per_eu(BwdOccupancy<T, B>::kMinWaves, 8))) void k_re
     run_persistent(n_tiles, [&](int64_t item) {
         const int64_t tile = ordered ? (int64_t)order[item] : item;
         if (tile < n_tiles)
-            bwd_tile<T, B, kL1>(sm, imgs, n_img, svals, recs, offsets, ranges, grad_out, target, inv_numel,
+            bwd_tile<T, B, kL1, kEll>(sm, imgs, n_img, svals, recs, offsets, eparams, ranges, grad_out, target, inv_numel,
                                 tile_loss, moments, partials, atomic_grads, tile);
     });
 }
 
-template <int T, int B, typename Table>
+template <int T, int B, bool kEll, typename Table>
 __global__ __launch_bounds__(TileShape<T>::kThreads)
-__attribute__((amdgpu_waves_per_eu(BwdOccupancy<T, B>::kMinWaves, 8))) void k_render_fused(
+__attribute__((amdgpu_waves_per_eu(BwdOccupancy<T, B, kEll>::kMinWaves, 8))) void k_render_fused(
     Table imgs, int n_img, const uint32_t* __restrict__ svals, const GRec* __restrict__ recs,
-    const int32_t* __restrict__ offsets,
+    const int32_t* __restrict__ offsets, const EParams* __restrict__ eparams,
     const int2* __restrict__ ranges, float* __restrict__ out,
     const float* __restrict__ target, float inv_numel, double* __restrict__ tile_loss,
     float* __restrict__ moments, float4* __restrict__ partials, int atomic_grads,
@@ -698,7 +746,7 @@ __attribute__((amdgpu_waves_per_eu(BwdOccupancy<T, B>::kMinWaves, 8))) void k_re
     int persistent) {
     __shared__ BwdLds<T, B> sm;
     if (!persistent) {
-        fused_tile<T, B>(sm, imgs, n_img, svals, recs, offsets, ranges, out, target, inv_numel, tile_loss,
+        fused_tile<T, B, kEll>(sm, imgs, n_img, svals, recs, offsets, eparams, ranges, out, target, inv_numel, tile_loss,
                          moments, partials, atomic_grads, xcd_tile(blockIdx.x, n_tiles));
         return;
     }
@@ -706,7 +754,7 @@ __attribute__((amdgpu_waves_per_eu(BwdOccupancy<T, B>::kMinWaves, 8))) void k_re
     run_persistent(n_tiles, [&](int64_t item) {
         const int64_t tile = ordered ? (int64_t)order[item] : item;
         if (tile < n_tiles)
-            fused_tile<T, B>(sm, imgs, n_img, svals, recs, offsets, ranges, out, target, inv_numel, tile_loss,
+            fused_tile<T, B, kEll>(sm, imgs, n_img, svals, recs, offsets, eparams, ranges, out, target, inv_numel, tile_loss,
                              moments, partials, atomic_grads, tile);
     });
 }
@@ -933,16 +981,16 @@ static hipError_t tile_grid(const Layout& L, const void* kernel, int threads, un
     return hipSuccess;
 }
 
-template <int T, int B, typename Table>
+template <int T, int B, bool kEll, typename Table>
 static hipError_t launch_fwd_tb(const Layout& L, const Ws& w, const Table& tab, float* out,
                                 hipStream_t st) {
-    const auto kernel = k_render_fwd<T, B, Table>;
+    const auto kernel = k_render_fwd<T, B, kEll, Table>;
     unsigned grid = 0;
     const hipError_t e = tile_grid(L, reinterpret_cast<const void*>(kernel),
                                    TileShape<T>::kThreads, &grid);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(TileShape<T>::kThreads), 0, st, tab, L.n_img,
-                       w.lists, w.recs, w.offsets, w.ranges, out, w.order, w.hdr, L.n_tiles,
+                       w.lists, w.recs, w.offsets, w.eparams, w.ranges, out, w.order, w.hdr, L.n_tiles,
                        (L.flags & GS_FLAG_PERSISTENT) ? 1 : 0);
     return hipGetLastError();
 }
@@ -950,22 +998,28 @@ static hipError_t launch_fwd_tb(const Layout& L, const Ws& w, const Table& tab, 
 template <typename Table>
 static hipError_t launch_fwd_t(const Layout& L, const Ws& w, const Table& tab, float* out,
                                hipStream_t st) {
+    if (L.flags & GS_FLAG_ELLIPSE) {  // one batch per tile size (the default)
+        if (L.tile == 8) return launch_fwd_tb<8, 64, true>(L, w, tab, out, st);
+        if (L.tile == 16) return launch_fwd_tb<16, 96, true>(L, w, tab, out, st);
+        if (L.tile == 32) return launch_fwd_tb<32, 32, true>(L, w, tab, out, st);
+        return hipErrorInvalidValue;
+    }
     const int b = L.lds_batch;
     switch (L.tile) {
         case 8:
-            if (b == 32) return launch_fwd_tb<8, 32>(L, w, tab, out, st);
-            if (b == 64) return launch_fwd_tb<8, 64>(L, w, tab, out, st);
+            if (b == 32) return launch_fwd_tb<8, 32, false>(L, w, tab, out, st);
+            if (b == 64) return launch_fwd_tb<8, 64, false>(L, w, tab, out, st);
             break;
         case 16:
-            if (b == 64) return launch_fwd_tb<16, 64>(L, w, tab, out, st);
-            if (b == 96) return launch_fwd_tb<16, 96>(L, w, tab, out, st);
-            if (b == 112) return launch_fwd_tb<16, 112>(L, w, tab, out, st);
-            if (b == 128) return launch_fwd_tb<16, 128>(L, w, tab, out, st);
-            if (b == 256) return launch_fwd_tb<16, 256>(L, w, tab, out, st);
+            if (b == 64) return launch_fwd_tb<16, 64, false>(L, w, tab, out, st);
+            if (b == 96) return launch_fwd_tb<16, 96, false>(L, w, tab, out, st);
+            if (b == 112) return launch_fwd_tb<16, 112, false>(L, w, tab, out, st);
+            if (b == 128) return launch_fwd_tb<16, 128, false>(L, w, tab, out, st);
+            if (b == 256) return launch_fwd_tb<16, 256, false>(L, w, tab, out, st);
             break;
         case 32:
-            if (b == 32) return launch_fwd_tb<32, 32>(L, w, tab, out, st);
-            if (b == 64) return launch_fwd_tb<32, 64>(L, w, tab, out, st);
+            if (b == 32) return launch_fwd_tb<32, 32, false>(L, w, tab, out, st);
+            if (b == 64) return launch_fwd_tb<32, 64, false>(L, w, tab, out, st);
             break;
         default:
             break;
@@ -983,17 +1037,17 @@ hipError_t launch_render_fwd(const Layout& L, const Ws& w, float* out, hipStream
     return launch_fwd_t(L, w, MemTable{w.imgs}, out, st);
 }
 
-template <int T, int B, bool kL1, typename Table>
+template <int T, int B, bool kL1, bool kEll, typename Table>
 static hipError_t launch_bwd_tt(const Layout& L, const Ws& w, const Table& tab,
                                 const float* grad_out, const float* target, float inv_numel,
                                 hipStream_t st) {
-    const auto kernel = k_render_bwd<T, B, kL1, Table>;
+    const auto kernel = k_render_bwd<T, B, kL1, kEll, Table>;
     unsigned grid = 0;
     const hipError_t e = tile_grid(L, reinterpret_cast<const void*>(kernel),
                                    TileShape<T>::kThreads, &grid);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(TileShape<T>::kThreads), 0, st, tab, L.n_img,
-                       w.lists, w.recs, w.offsets, w.ranges, grad_out, target, inv_numel, w.tile_loss, w.moments,
+                       w.lists, w.recs, w.offsets, w.eparams, w.ranges, grad_out, target, inv_numel, w.tile_loss, w.moments,
                        w.partials, (L.flags & GS_FLAG_ATOMIC_GRADS) ? 1 : 0, w.order, w.hdr,
                        L.n_tiles, (L.flags & GS_FLAG_PERSISTENT) ? 1 : 0);
     return hipGetLastError();
@@ -1003,24 +1057,33 @@ template <bool kL1, typename Table>
 static hipError_t launch_bwd_t(const Layout& L, const Ws& w, const Table& tab,
                                const float* grad_out, const float* target, float inv_numel,
                                hipStream_t st) {
+    if (L.flags & GS_FLAG_ELLIPSE) {  // one batch per tile size (the default)
+        if (L.tile == 8)
+            return launch_bwd_tt<8, 64, kL1, true>(L, w, tab, grad_out, target, inv_numel, st);
+        if (L.tile == 16)
+            return launch_bwd_tt<16, 96, kL1, true>(L, w, tab, grad_out, target, inv_numel, st);
+        if (L.tile == 32)
+            return launch_bwd_tt<32, 32, kL1, true>(L, w, tab, grad_out, target, inv_numel, st);
+        return hipErrorInvalidValue;
+    }
     const int b = L.lds_batch;
     switch (L.tile) {
         case 8:
-            if (b == 32) return launch_bwd_tt<8, 32, kL1>(L, w, tab, grad_out, target, inv_numel, st);
-            if (b == 64) return launch_bwd_tt<8, 64, kL1>(L, w, tab, grad_out, target, inv_numel, st);
+            if (b == 32) return launch_bwd_tt<8, 32, kL1, false>(L, w, tab, grad_out, target, inv_numel, st);
+            if (b == 64) return launch_bwd_tt<8, 64, kL1, false>(L, w, tab, grad_out, target, inv_numel, st);
             break;
         case 16:
-            if (b == 64) return launch_bwd_tt<16, 64, kL1>(L, w, tab, grad_out, target, inv_numel, st);
-            if (b == 96) return launch_bwd_tt<16, 96, kL1>(L, w, tab, grad_out, target, inv_numel, st);
-            if (b == 112) return launch_bwd_tt<16, 112, kL1>(L, w, tab, grad_out, target, inv_numel, st);
+            if (b == 64) return launch_bwd_tt<16, 64, kL1, false>(L, w, tab, grad_out, target, inv_numel, st);
+            if (b == 96) return launch_bwd_tt<16, 96, kL1, false>(L, w, tab, grad_out, target, inv_numel, st);
+            if (b == 112) return launch_bwd_tt<16, 112, kL1, false>(L, w, tab, grad_out, target, inv_numel, st);
             if (b == 128)
-                return launch_bwd_tt<16, 128, kL1>(L, w, tab, grad_out, target, inv_numel, st);
+                return launch_bwd_tt<16, 128, kL1, false>(L, w, tab, grad_out, target, inv_numel, st);
             if (b == 256)
-                return launch_bwd_tt<16, 256, kL1>(L, w, tab, grad_out, target, inv_numel, st);
+                return launch_bwd_tt<16, 256, kL1, false>(L, w, tab, grad_out, target, inv_numel, st);
             break;
         case 32:
-            if (b == 32) return launch_bwd_tt<32, 32, kL1>(L, w, tab, grad_out, target, inv_numel, st);
-            if (b == 64) return launch_bwd_tt<32, 64, kL1>(L, w, tab, grad_out, target, inv_numel, st);
+            if (b == 32) return launch_bwd_tt<32, 32, kL1, false>(L, w, tab, grad_out, target, inv_numel, st);
+            if (b == 64) return launch_bwd_tt<32, 64, kL1, false>(L, w, tab, grad_out, target, inv_numel, st);
             break;
         default:
             break;
@@ -1050,16 +1113,16 @@ hipError_t launch_render_bwd_l1(const Layout& L, const Ws& w, const float* out,
     return launch_bwd_any<true>(L, w, out, target, (float)(1.0 / (double)numel), st);
 }
 
-template <int T, int B, typename Table>
+template <int T, int B, bool kEll, typename Table>
 static hipError_t launch_fused_tt(const Layout& L, const Ws& w, const Table& tab, float* out,
                                   const float* target, float inv_numel, hipStream_t st) {
-    const auto kernel = k_render_fused<T, B, Table>;
+    const auto kernel = k_render_fused<T, B, kEll, Table>;
     unsigned grid = 0;
     const hipError_t e = tile_grid(L, reinterpret_cast<const void*>(kernel),
                                    TileShape<T>::kThreads, &grid);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(TileShape<T>::kThreads), 0, st, tab, L.n_img,
-                       w.lists, w.recs, w.offsets, w.ranges, out, target, inv_numel, w.tile_loss, w.moments,
+                       w.lists, w.recs, w.offsets, w.eparams, w.ranges, out, target, inv_numel, w.tile_loss, w.moments,
                        w.partials, (L.flags & GS_FLAG_ATOMIC_GRADS) ? 1 : 0, w.order, w.hdr,
                        L.n_tiles, (L.flags & GS_FLAG_PERSISTENT) ? 1 : 0);
     return hipGetLastError();
@@ -1068,22 +1131,30 @@ static hipError_t launch_fused_tt(const Layout& L, const Ws& w, const Table& tab
 template <typename Table>
 static hipError_t launch_fused_t(const Layout& L, const Ws& w, const Table& tab, float* out,
                                  const float* target, float inv_numel, hipStream_t st) {
+    if (L.flags & GS_FLAG_ELLIPSE) {  // one batch per tile size (the default)
+        if (L.tile == 8) return launch_fused_tt<8, 64, true>(L, w, tab, out, target, inv_numel, st);
+        if (L.tile == 16)
+            return launch_fused_tt<16, 96, true>(L, w, tab, out, target, inv_numel, st);
+        if (L.tile == 32)
+            return launch_fused_tt<32, 32, true>(L, w, tab, out, target, inv_numel, st);
+        return hipErrorInvalidValue;
+    }
     const int b = L.lds_batch;
     switch (L.tile) {
         case 8:
-            if (b == 32) return launch_fused_tt<8, 32>(L, w, tab, out, target, inv_numel, st);
-            if (b == 64) return launch_fused_tt<8, 64>(L, w, tab, out, target, inv_numel, st);
+            if (b == 32) return launch_fused_tt<8, 32, false>(L, w, tab, out, target, inv_numel, st);
+            if (b == 64) return launch_fused_tt<8, 64, false>(L, w, tab, out, target, inv_numel, st);
             break;
         case 16:
-            if (b == 64) return launch_fused_tt<16, 64>(L, w, tab, out, target, inv_numel, st);
-            if (b == 96) return launch_fused_tt<16, 96>(L, w, tab, out, target, inv_numel, st);
-            if (b == 112) return launch_fused_tt<16, 112>(L, w, tab, out, target, inv_numel, st);
-            if (b == 128) return launch_fused_tt<16, 128>(L, w, tab, out, target, inv_numel, st);
-            if (b == 256) return launch_fused_tt<16, 256>(L, w, tab, out, target, inv_numel, st);
+            if (b == 64) return launch_fused_tt<16, 64, false>(L, w, tab, out, target, inv_numel, st);
+            if (b == 96) return launch_fused_tt<16, 96, false>(L, w, tab, out, target, inv_numel, st);
+            if (b == 112) return launch_fused_tt<16, 112, false>(L, w, tab, out, target, inv_numel, st);
+            if (b == 128) return launch_fused_tt<16, 128, false>(L, w, tab, out, target, inv_numel, st);
+            if (b == 256) return launch_fused_tt<16, 256, false>(L, w, tab, out, target, inv_numel, st);
             break;
         case 32:
-            if (b == 32) return launch_fused_tt<32, 32>(L, w, tab, out, target, inv_numel, st);
-            if (b == 64) return launch_fused_tt<32, 64>(L, w, tab, out, target, inv_numel, st);
+            if (b == 32) return launch_fused_tt<32, 32, false>(L, w, tab, out, target, inv_numel, st);
+            if (b == 64) return launch_fused_tt<32, 64, false>(L, w, tab, out, target, inv_numel, st);
             break;
         default:
             break;

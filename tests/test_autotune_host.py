@@ -26,7 +26,24 @@ def test_every_candidate_is_accepted_and_others_are_not():
             assert (_ws(tile, batch) == N.GS_OK) == ok, (tile, batch)
         assert _ws(tile, 0) == N.GS_OK   # default batch
     assert _ws(16, 0, 0x4) == N.GS_OK  # radix-sort binning
-    assert _ws(16, 0, 0x8) == N.GS_E_INVALID  # unknown flag bit
+    assert _ws(16, 0, 0x8) == N.GS_OK  # pixel-centre sampling
+    assert _ws(16, 0, 0x10) == N.GS_OK  # elliptical supports
+    assert _ws(16, 0, 0x18 | 0x1) == N.GS_OK
+    assert _ws(16, 0, 0x20) == N.GS_E_INVALID  # unknown flag bit
+    # the elliptical kernels exist at each tile size's default batch only
+    for tile, dflt, other in ((8, 64, 32), (16, 96, 128), (32, 32, 64)):
+        assert _ws(tile, dflt, 0x10) == N.GS_OK
+        assert _ws(tile, other, 0x10) == N.GS_E_UNSUPPORTED
+
+
+def test_ellipse_rejects_a_window():
+    from paper_2501_06838_amd import _native as N
+    arr = (N.gs_image * 1)(N.gs_image(40, 30, 3.3, 0, 1200, 0))
+    b = ctypes.c_size_t()
+    for flags, want in ((0x10, N.GS_E_INVALID), (0x8, N.GS_OK), (0, N.GS_OK)):
+        cfg = N.gs_config(16, 0, flags, 0, 0, 0.1)
+        assert N.lib().gs_workspace_size(ctypes.byref(cfg), arr, 1, 1200,
+                                         ctypes.byref(b)) == want, flags
 
 
 def test_layout_key_depends_on_layout_and_device():
