@@ -57,10 +57,16 @@ BYTES_PER_GAUSS = 108.0
 # kernel's VALU counters: busy = SQ_ACTIVE_INST_VALU x 4 / 1,024 SIMDs /
 # (GRBM_GUI_ACTIVE / 8 XCDs).  Valid only while the render sources hash to
 # `sources`; otherwise reported as null.
-PROFILE = {"workload": "config2a", "launch": {"tile": 16, "lds_batch": 96, "flags": 0},
-           "sources": None,
-           "fetch_kib": None, "write_kib": None, "fetch_factor": 2.0, "write_factor": 1.0,
-           "sq_active_inst_valu": None, "grbm_gui_active": None}
+# Counter readings of k_render_fused on config2a per launch configuration
+# (rocprofv3 --pmc runs, averaged per dispatch; summaries and commands in
+# profiles/config2a_k_render_fused_traffic.md), valid while the
+# render sources hash to `sources`.  The factors scale FETCH_SIZE and
+# WRITE_SIZE by what the counters read for a plain copy of known size.
+PROFILE = {"workload": "config2a", "sources": "590c201f579b19c0",
+           "launches": {
+               (16, 96, 0): {"fetch_kib": 38610.2, "write_kib": 98743.1},
+               (16, 112, 0): {"fetch_kib": 37865.3, "write_kib": 95014.9}},
+           "fetch_factor": 2.313, "write_factor": 1.157}
 PROFILE_SOURCES = ("paper_2501_06838_amd/csrc/gs_render.hip",
                    "paper_2501_06838_amd/csrc/gs_internal.h")
 
@@ -87,25 +93,19 @@ def render_sources_hash():
     return h.hexdigest()[:16]
 
 
-def profile_valid(workload, launch):
+def profile_entry(workload, launch):
     P = PROFILE
-    return (P["sources"] is not None and workload == P["workload"] and launch == P["launch"]
-            and render_sources_hash() == P["sources"])
+    if P["sources"] is None or workload != P["workload"] or render_sources_hash() != P["sources"]:
+        return None
+    return P["launches"].get((launch["tile"], launch["lds_batch"], launch["flags"]))
 
 
 def traffic_bytes(workload, launch):
-    P = PROFILE
-    if not profile_valid(workload, launch) or P["fetch_kib"] is None:
+    e = profile_entry(workload, launch)
+    if e is None:
         return None
-    return round(P["fetch_kib"] * 1024 * P["fetch_factor"] +
-                 P["write_kib"] * 1024 * P["write_factor"])
-
-
-def valu_busy(workload, launch):
-    P = PROFILE
-    if not profile_valid(workload, launch) or P["sq_active_inst_valu"] is None:
-        return None
-    return round(P["sq_active_inst_valu"] * 4 / 1024 / (P["grbm_gui_active"] / 8), 3)
+    return round(e["fetch_kib"] * 1024 * PROFILE["fetch_factor"] +
+                 e["write_kib"] * 1024 * PROFILE["write_factor"])
 
 
 def cpu_model():
@@ -657,7 +657,6 @@ def main():
         "achieved": round(fused_tflops, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
         "unit": "TFLOP/s", "frac": round(fused_tflops / PEAK_FP32_VECTOR_TFLOPS, 4),
         "traffic": traffic_bytes(args.workload, launch),
-        "valu_busy": valu_busy(args.workload, launch),
         "per_launch_flopeq": n_support * (FLOPEQ_FWD + FLOPEQ_BWD),
         "avg_launch_us": round(fused_ms * 1e3, 2),
         "fracs": roofline_fracs(n_support, hr_px, B.n, ms_step, fused_ms),
