@@ -33,8 +33,15 @@ constexpr int kPlaceScanTiles = 4096;  // up to this many tiles each placement b
 constexpr int kCounterStride = 16;  // words
 constexpr int kLossCounterWord = 0;
 constexpr int kCounterWords = kCounterStride;
-constexpr int kLossSlice = 4096;  // tiles per workgroup of the loss-value kernel
-constexpr int kLossParts = 64;    // workgroups of the gradient kernel that reduce the loss
+constexpr int kLossSlice = 4096;  // tiles per loss-reduction workgroup (at least)
+constexpr int kLossParts = 64;    // loss-reduction workgroups (at most)
+// The loss reductions (the stand-alone kernel and the gradient kernel's
+// appended workgroups) split the tiles the same way, so they give the same
+// bits: P parts, part b summing tiles [n b / P, n (b + 1) / P).
+inline int loss_parts(int64_t n_tiles) {
+    const int64_t p = (n_tiles + kLossSlice - 1) / kLossSlice;
+    return (int)(p < 1 ? 1 : (p > kLossParts ? kLossParts : p));
+}
 constexpr int kRadix = 1 << kRadixBits;
 
 // exp(-q/2) = exp2(-(kc z)^2) with kc = sqrt(log2(e) / 2); the render

@@ -54,12 +54,14 @@ struct TileShape {
     static constexpr int kBatch = kThreads;
 };
 
-// Waves per SIMD the backward and fused kernels are compiled for.  They are
-// latency bound, so at 16 x 16 the register budget follows the workgroups
-// the LDS fits per CU: eight with 64 or 96 Gaussians per round (64 VGPRs),
-// seven with 112 (72), six with 128 (80); a few values spill, outside the
-// pixel loops.  Elsewhere (and for the elliptical supports, whose FP64 mask
-// building needs more) the compiler's own register count decides.
+// Waves per SIMD the tile kernels are compiled for (their register
+// budget).  The backward and fused kernels are latency bound, so at 16 x 16
+// the budget follows the workgroups the LDS fits per CU: eight with 64 or 96
+// Gaussians per round (64 VGPRs), seven with 112 (72), six with 128 (80); a
+// few values spill, outside the pixel loops.  The forward kernel at 16 x 16
+// holds eight workgroups per CU up to 128 Gaussians per round.  Elsewhere
+// (and for the elliptical supports, whose FP64 mask building needs more) the
+// compiler's own register count decides.
 template <int T, int B, bool kEll>
 struct BwdOccupancy {
     static constexpr int kMinWaves = (T != 16 || kEll) ? 1
@@ -67,6 +69,7 @@ struct BwdOccupancy {
                                    : B == 112             ? 7
                                    : B == 128             ? 6
                                                           : 1;
+    static constexpr int kFwdMinWaves = (T != 16 || kEll || B > 128) ? 1 : 8;
 };
 
 // Persistent tile kernels: a grid of the resident workgroups walks the items
@@ -273,6 +276,11 @@ __device__ __forceinline__ StagedMine stage_round(StageLds<T, B>& st,
         int c = 0;
         for (int w = 0; w < S::kWaves; ++w) c += st.wcount[w][t];
         st.scount[t] = c;
+        if (c & 1) {  // an odd list gets an empty record (zero mask, zero amplitude)
+            st.l0[t][c] = make_float4(0.f, 0.f, 0.f, 0.f);
+            st.l1[t][c] = make_float4(0.f, 0.f, 0.f, 0.f);
+            st.l2[t][c] = make_uint2(0u, 0u);
+        }
     }
     __syncthreads();
     return mine;
@@ -290,20 +298,15 @@ __device__ __forceinline__ void fwd_round(const StageLds<T, B>& st,
 #pragma unroll
     for (int m = 0; m < S::kBlocksPerWave; ++m) {
         const int j = wave + S::kWaves * m;
-        const int cnt = __builtin_amdgcn_readfirstlane(st.scount[j]);  // uniform
-        // two records per iteration (the second of an odd tail repeats the
-        // first with an empty mask), so their LDS reads and sums overlap
-        for (int q = 0; q < cnt; q += 2) {
-            const bool two = q + 1 < cnt;  // uniform
-            const int q1 = two ? q + 1 : q;
+        // records in pairs (an odd list ends with the staging's empty
+        // record), two pairs per iteration, so LDS reads and sums overlap
+        auto pair = [&](int q) {
             const float4 a0 = st.l0[j][q], a1 = st.l1[j][q];
-            const float4 b0 = st.l0[j][q1], b1 = st.l1[j][q1];
+            const float4 b0 = st.l0[j][q + 1], b1 = st.l1[j][q + 1];
             const uint32_t alo = __builtin_amdgcn_readfirstlane(st.l2[j][q].x);
             const uint32_t ahi = __builtin_amdgcn_readfirstlane(st.l2[j][q].y);
-            uint32_t blo = __builtin_amdgcn_readfirstlane(st.l2[j][q1].x);
-            uint32_t bhi = __builtin_amdgcn_readfirstlane(st.l2[j][q1].y);
-            blo = two ? blo : 0u;
-            bhi = two ? bhi : 0u;
+            const uint32_t blo = __builtin_amdgcn_readfirstlane(st.l2[j][q + 1].x);
+            const uint32_t bhi = __builtin_amdgcn_readfirstlane(st.l2[j][q + 1].y);
             const uint64_t amask = ((uint64_t)ahi << 32) | alo;
             const uint64_t bmask = ((uint64_t)bhi << 32) | blo;
             const float za1 = __builtin_fmaf(a0.z, lxf, a0.x);
@@ -320,7 +323,15 @@ __device__ __forceinline__ void fwd_round(const StageLds<T, B>& st,
             acc[m][0] += b1.y * wb;
             acc[m][1] += b1.z * wb;
             acc[m][2] += b1.w * wb;
+        };
+        const int cnt = __builtin_amdgcn_readfirstlane(st.scount[j]);  // uniform
+        const int cntp = (cnt + 1) & ~1;
+        int q = 0;
+        for (; q + 4 <= cntp; q += 4) {
+            pair(q);
+            pair(q + 2);
         }
+        if (q < cntp) pair(q);  // uniform
     }
 }
 
@@ -564,16 +575,22 @@ __device__ __forceinline__ void bwd_tile(
     float* __restrict__ moments, float4* __restrict__ partials, int atomic_grads,
     int64_t tile) {
     using S = TileShape<T>;
-    constexpr int NT = S::kThreads;
-    const int t = threadIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const TileInfo ti = tile_info<T>(imgs, n_img, ranges, tile);
     if (!kL1 && ti.rg.y <= ti.rg.x) return;  // uniform: nothing listed in this tile
 
+    // the fused kernel's pixel-to-thread mapping, so that the tile's L1 sum
+    // is added in the same order (bitwise the same loss)
     const int64_t plane = (int64_t)ti.im.out_w * ti.im.out_h;
     const float* g = grad_out + ti.im.out_offset;
     double lsum = 0.0;
-    for (int p = t; p < T * T; p += NT) {
-        const int x = ti.px0 + (p % T), y = ti.py0 + (p / T);
+#pragma unroll
+    for (int m = 0; m < S::kBlocksPerWave; ++m) {
+        const int j = wave + S::kWaves * m;
+        const int lx = (j % S::kBlocksX) * 8 + (lane & 7);
+        const int ly = (j / S::kBlocksX) * 8 + (lane >> 3);
+        const int p = ly * T + lx;
+        const int x = ti.px0 + lx, y = ti.py0 + ly;
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
         if (x < ti.im.out_w && y < ti.im.out_h) {
             const int64_t q = (int64_t)y * ti.im.out_w + x;
@@ -691,7 +708,8 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t n) {
 // `persistent`, a grid sized to the resident workgroups that walks the longest-first tile order
 // (without a tile order from the matching binning, items are tiles).
 template <int T, int B, bool kEll, typename Table>
-__global__ __launch_bounds__(TileShape<T>::kThreads) void k_render_fwd(
+__global__ __launch_bounds__(TileShape<T>::kThreads)
+__attribute__((amdgpu_waves_per_eu(BwdOccupancy<T, B, kEll>::kFwdMinWaves, 8))) void k_render_fwd(
     Table imgs, int n_img, const uint32_t* __restrict__ svals, const GRec* __restrict__ recs,
     const int32_t* __restrict__ offsets, const EParams* __restrict__ eparams,
     const int2* __restrict__ ranges, float* __restrict__ out,
@@ -826,8 +844,8 @@ __global__ __launch_bounds__(kBlockG) void k_finalize(
     float* __restrict__ grad_color, float* __restrict__ grad_opacity,
     const double* __restrict__ tile_loss, int64_t n_tiles, double inv_numel,
     double* __restrict__ loss, double* __restrict__ loss_parts, uint32_t* __restrict__ counter) {
-    // with the loss, workgroups past the Gaussians' (at most kLossParts, a
-    // kLossSlice of tiles each) sum the per-tile L1 sums
+    // with the loss, loss_parts(n_tiles) workgroups past the Gaussians' sum
+    // the per-tile L1 sums
     const int64_t nbg = (n_gauss + kBlockG - 1) / kBlockG;
     if (loss && (int64_t)blockIdx.x >= nbg) {  // uniform
         const int64_t P = (int64_t)gridDim.x - nbg, b = (int64_t)blockIdx.x - nbg;
@@ -940,15 +958,16 @@ __global__ __launch_bounds__(kBlockG) void k_l1(const float* __restrict__ img,
     }
 }
 
-// The L1 loss value alone: kLossSlice tiles per workgroup.
+// The L1 loss value alone: loss_parts(n_tiles) workgroups, split as the
+// gradient kernel's loss workgroups split the tiles.
 __global__ __launch_bounds__(kBlockG) void k_sum_loss(const double* __restrict__ tile_loss,
                                                       int64_t n_tiles, double inv_numel,
                                                       double* __restrict__ loss,
                                                       double* __restrict__ parts,
                                                       uint32_t* __restrict__ counter) {
-    const int64_t b = blockIdx.x;
-    loss_reduce(tile_loss, b * kLossSlice, min(n_tiles, (b + 1) * kLossSlice), parts,
-                (int)gridDim.x, (int)b, counter, inv_numel, loss);
+    const int64_t P = gridDim.x, b = blockIdx.x;
+    loss_reduce(tile_loss, n_tiles * b / P, n_tiles * (b + 1) / P, parts, (int)P, (int)b,
+                counter, inv_numel, loss);
 }
 
 inline int blocks_for(int64_t n, int per) { return (int)((n + per - 1) / per); }
@@ -957,7 +976,7 @@ inline int blocks_for(int64_t n, int per) { return (int)((n + per - 1) / per); }
 
 hipError_t launch_sum_loss(const Layout& L, const Ws& w, int64_t numel, double* loss,
                            hipStream_t st) {
-    const int nb = std::max(1, blocks_for(L.n_tiles, kLossSlice));
+    const int nb = loss_parts(L.n_tiles);
     hipLaunchKernelGGL(k_sum_loss, dim3(nb), dim3(kBlockG), 0, st, w.tile_loss, L.n_tiles,
                        1.0 / (double)numel, loss, w.loss_parts, w.counters + kLossCounterWord);
     return hipGetLastError();
@@ -1178,7 +1197,7 @@ hipError_t launch_finalize(const Layout& L, const Ws& w, const float* chol,
                            const float* color, const float* opacity, float* grad_mean,
                            float* grad_chol, float* grad_color, float* grad_opacity,
                            hipStream_t st, int64_t numel, double* loss) {
-    const int nb_loss = std::min(kLossParts, std::max(1, blocks_for(L.n_tiles, kLossSlice)));
+    const int nb_loss = loss_parts(L.n_tiles);
     const int nb = (int)blocks_for(L.n_gauss, kBlockG) + (loss ? nb_loss : 0);
     if (nb == 0) return hipSuccess;
     hipLaunchKernelGGL(k_finalize, dim3(nb), dim3(kBlockG), 0, st, w.recs, L.n_gauss, chol,
