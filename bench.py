@@ -62,10 +62,11 @@ BYTES_PER_GAUSS = 108.0
 # profiles/config2a_k_render_fused_traffic.md), valid while the
 # render sources hash to `sources`.  The factors scale FETCH_SIZE and
 # WRITE_SIZE by what the counters read for a plain copy of known size.
-PROFILE = {"workload": "config2a", "sources": "590c201f579b19c0",
+PROFILE = {"workload": "config2a", "sources": "240d766f5e6d0038",
            "launches": {
-               (16, 96, 0): {"fetch_kib": 38610.2, "write_kib": 98743.1},
-               (16, 112, 0): {"fetch_kib": 37865.3, "write_kib": 95014.9}},
+               (16, 96, 0): {"fetch_kib": 41638.6, "write_kib": 108977.5},
+               (16, 112, 0): {"fetch_kib": 37878.7, "write_kib": 95027.5},
+               (16, 128, 0): {"fetch_kib": 37862.4, "write_kib": 95008.6}},
            "fetch_factor": 2.313, "write_factor": 1.157}
 PROFILE_SOURCES = ("paper_2501_06838_amd/csrc/gs_render.hip",
                    "paper_2501_06838_amd/csrc/gs_internal.h")
