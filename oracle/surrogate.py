@@ -151,10 +151,12 @@ def closed_form_radius(chol, color, opacity, tau, margin=0.0):
     chol = np.asarray(chol, np.float64)
     sx = chol[:, 0]
     sy = np.sqrt(chol[:, 1] ** 2 + chol[:, 2] ** 2)
-    rho = chol[:, 1] / sy
-    K = 1.0 / (2.0 * math.pi * sx * sy * np.sqrt(1.0 - rho * rho))
-    peak = np.asarray(opacity, np.float64) * np.asarray(color, np.float64).max(axis=1) * K
+    # invalid shapes (l22 = 0 gives |rho| = 1) divide by zero here; they are
+    # mapped to 3 below
     with np.errstate(invalid="ignore", divide="ignore"):
+        rho = chol[:, 1] / sy
+        K = 1.0 / (2.0 * math.pi * sx * sy * np.sqrt(1.0 - rho * rho))
+        peak = np.asarray(opacity, np.float64) * np.asarray(color, np.float64).max(axis=1) * K
         d = np.sqrt(2.0 * np.log(np.maximum(peak / tau, 1.0)))
     R = np.clip(d + margin, 0.0, 3.0)
     ok = (chol[:, 0] > 0) & (chol[:, 2] > 0) & np.isfinite(peak)
