@@ -204,6 +204,21 @@ class Bench:
         return plan, pairs
 
 
+def warm_up(torch, launch_fn, min_launches, seconds):
+    """At least min_launches untimed launches, continued until `seconds` of
+    back-to-back work have run: the GPU's clocks ramp up under sustained load
+    (a cold start measured 10-15% slow on the first brackets), so every timed
+    region follows continuous work."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n = 0
+    while n < min_launches or time.perf_counter() - t0 < seconds:
+        for _ in range(8):
+            launch_fn()
+        n += 8
+        torch.cuda.synchronize()
+
+
 def time_graph(torch, launch_fn, reps, brackets=3):
     """Median over `brackets` of the mean milliseconds per replay of reps
     back-to-back replays (wall clock, synchronised on both sides)."""
@@ -274,8 +289,7 @@ def step_record(B, launch, reps, kernels=True):
         raise SystemExit(f"pair capacity overflow ({B.name})")
     graph = G.StepGraph(plan, B.mean, B.chol, B.color, B.opacity, ws, out, B.target, grads,
                         loss)
-    for _ in range(3):
-        graph.launch()
+    warm_up(torch, graph.launch, 3, 0.05)
     ms, brackets = time_graph(torch, graph.launch, reps)
     if plan.diagnostics(ws)[1]:
         raise SystemExit(f"pair capacity overflow during replay ({B.name})")
@@ -341,8 +355,7 @@ def forward_record(B, launch, reps):
     plan, _ = B.plan(launch)
     ws, out = plan.new_workspace(B.dev), plan.new_output(B.dev)
     graph = B.G.StepGraph(plan, B.mean, B.chol, B.color, B.opacity, ws, out)
-    for _ in range(3):
-        graph.launch()
+    warm_up(torch, graph.launch, 3, 0.05)
     ms, brackets = time_graph(torch, graph.launch, reps)
     if plan.diagnostics(ws)[1]:
         raise SystemExit(f"pair capacity overflow ({B.name})")
@@ -556,8 +569,7 @@ def pruned_one(G, synth, torch, np, net, info, tau, cf_margin, name, reps):
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
             step()
-        for _ in range(5):
-            g.replay()
+        warm_up(torch, g.replay, 5, 0.05)
         ms, brackets = time_graph(torch, g.replay, reps)
         r = {"ms_per_step": round(ms, 4), "brackets_ms": [round(x, 4) for x in brackets],
              "mp_s": round(plan.out_numel / 3 / (ms * 1e-3) / 1e6, 2),
@@ -651,9 +663,8 @@ def main():
     log(f"tile pairs {npairs}, in-support pairs {n_support}, invalid {n_invalid}")
     graph = G.StepGraph(plan, B.mean, B.chol, B.color, B.opacity, ws, out, B.target, grads,
                         loss)
-    for _ in range(args.warmup):
-        graph.launch()
-    torch.cuda.synchronize()
+    # at least W warm-up replays, continued for 0.2 s of back-to-back work
+    warm_up(torch, graph.launch, args.warmup, 0.2)
 
     # timed region: exactly K replays of the whole step
     t0 = time.perf_counter()

@@ -1,19 +1,24 @@
 """Launch-configuration autotuner for a batch layout (host orchestration only).
 
 The tunable knobs of the library are the HR tile side, the number of
-Gaussians the forward stages in LDS per round (``lds_batch``) and whether the
+Gaussians the forward stages in LDS per round (``lds_batch``), whether the
 tile kernels run persistent over the longest-first tile order
-(``GS_FLAG_PERSISTENT``).  None of them changes the rendered image (the
-forward sums every pixel's Gaussians in ascending index whatever the tile
-and batch), and the gradients are bitwise independent of the batch and of
-the persistent flag.
+(``GS_FLAG_PERSISTENT``) and the binning (per-tile counting with a list sort,
+or the device radix sort, ``GS_FLAG_RADIX_SORT``).  None of them changes the
+rendered image (the forward sums every pixel's Gaussians in ascending index
+whatever the tile and batch, and both binnings give the same lists), and the
+gradients are bitwise independent of the batch, the binning and the
+persistent flag.
 
 ``tune`` times one whole training step (binning, the fused tile kernel:
 render, L1 gradient and backward, then the gradients) of the caller's own
-batch for each candidate
-with HIP events on the current stream and returns the fastest; results are
-cached in a JSON file keyed by the batch layout and the device, so a serving
-loop pays the search once per layout.
+batch for each candidate with HIP events on the current stream and returns
+the fastest; results are cached in a JSON file keyed by the batch layout,
+the device and the timing mode, so a serving loop pays the search once per
+layout.  By default the step is timed as a captured HIP graph replay, as a
+serving loop runs it: eager launches add a per-kernel launch cost that
+favours the binning with fewer kernels (on a 2048 x 2048 render the radix
+sort is the slower binning eagerly and the faster one replayed).
 """
 from __future__ import annotations
 
@@ -46,20 +51,24 @@ def pick(timings: List[dict], margin: float = 0.02) -> dict:
     return best
 
 
-def candidates(persistent: Sequence[bool] = (False, True)) -> List[Dict[str, int]]:
+def candidates(persistent: Sequence[bool] = (False, True),
+               radix: Sequence[bool] = (False, True)) -> List[Dict[str, int]]:
     out = []
     for tile, batch in TILE_BATCHES:
-        for p in persistent:
-            out.append({"tile": tile, "lds_batch": batch,
-                        "flags": N.GS_FLAG_PERSISTENT if p else 0})
+        for r in radix:
+            for p in persistent:
+                out.append({"tile": tile, "lds_batch": batch,
+                            "flags": (N.GS_FLAG_PERSISTENT if p else 0) |
+                                     (N.GS_FLAG_RADIX_SORT if r else 0)})
     return out
 
 
-def layout_key(images: Sequence[Tuple[int, int, float, int, int]], device_name: str) -> str:
+def layout_key(images: Sequence[Tuple[int, int, float, int, int]], device_name: str,
+               mode: str = "graph") -> str:
     """Cache key: the images' LR sizes, scales and Gaussian counts, the
-    device and the library ABI version."""
+    device, the timing mode and the library ABI version."""
     desc = [(int(h), int(w), float(s), int(gc)) for (h, w, s, _gb, gc) in images]
-    blob = json.dumps({"images": desc, "device": device_name,
+    blob = json.dumps({"images": desc, "device": device_name, "mode": mode,
                        "abi": int(N.lib().gs_abi_version())}, sort_keys=True)
     return hashlib.sha1(blob.encode()).hexdigest()
 
@@ -106,10 +115,12 @@ class TuneCache:
 
 
 def time_step(plan, mean, chol, color, opacity, target, reps: int = 3, warmup: int = 1,
-              headroom: float = 1.0) -> Tuple[float, int]:
-    """Median milliseconds of one training step (gs_raster_step_l1) for
-    plan's config, and its pair count."""
+              headroom: float = 1.0, captured: bool = True) -> Tuple[float, int]:
+    """Median milliseconds of one training step for plan's config (a replay
+    of the step captured as a HIP graph, or with `captured` False an eager
+    gs_raster_step_l1), and its pair count."""
     import torch
+    from .raster import StepGraph
     dev = mean.device
     n = plan.n_gauss
     pairs = plan.ensure_capacity(mean, chol, headroom=headroom)
@@ -119,8 +130,15 @@ def time_step(plan, mean, chol, color, opacity, target, reps: int = 3, warmup: i
              torch.empty(n, 3, device=dev), torch.empty(n, device=dev))
     stream = torch.cuda.current_stream()
 
+    graph = None
+    if captured:
+        graph = StepGraph(plan, mean, chol, color, opacity, ws, out, target, grads)
+
     def step():
-        plan.step_l1(mean, chol, color, opacity, ws, out, target, grads)
+        if graph is not None:
+            graph.launch()
+        else:
+            plan.step_l1(mean, chol, color, opacity, ws, out, target, grads)
 
     for _ in range(warmup):
         step()
@@ -133,6 +151,8 @@ def time_step(plan, mean, chol, color, opacity, target, reps: int = 3, warmup: i
         b.record(stream)
         b.synchronize()
         times.append(a.elapsed_time(b))
+    if graph is not None:
+        graph.close()
     if plan.diagnostics(ws)[1]:
         raise N.GSError(N.GS_E_CAPACITY, "autotune step")
     del ws, out, grads
@@ -142,13 +162,13 @@ def time_step(plan, mean, chol, color, opacity, target, reps: int = 3, warmup: i
 def tune(images: Sequence[Tuple[int, int, float, int, int]], mean, chol, color, opacity,
          target, reps: int = 3, warmup: int = 1,
          cands: Optional[List[Dict[str, int]]] = None, cache: Optional[TuneCache] = None,
-         force: bool = False, log=None, margin: float = 0.02) -> dict:
+         force: bool = False, log=None, margin: float = 0.02, captured: bool = True) -> dict:
     """Fastest configuration for this batch (see `pick`): {"config": {tile,
     lds_batch, flags}, "ms": ..., "timings": [...], "cached": bool}."""
     import torch
     from .raster import RasterPlan
     name = torch.cuda.get_device_name(mean.device)
-    key = layout_key(images, name)
+    key = layout_key(images, name, "graph" if captured else "eager")
     if cache is not None and not force:
         hit = cache.get(key)
         if hit is not None:
@@ -157,7 +177,8 @@ def tune(images: Sequence[Tuple[int, int, float, int, int]], mean, chol, color, 
     for c in (cands if cands is not None else candidates()):
         plan = RasterPlan(images, mean.shape[0], tile=c["tile"], lds_batch=c["lds_batch"],
                           flags=c["flags"])
-        ms, pairs = time_step(plan, mean, chol, color, opacity, target, reps, warmup)
+        ms, pairs = time_step(plan, mean, chol, color, opacity, target, reps, warmup,
+                              captured=captured)
         timings.append({"config": dict(c), "ms": round(ms, 5), "pairs": pairs})
         if log:
             log(f"autotune {c}: {ms:.4f} ms, {pairs} pairs")

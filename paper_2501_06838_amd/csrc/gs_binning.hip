@@ -447,10 +447,14 @@ __global__ __launch_bounds__(kBlockG) void k_emit(
     }
 }
 
-// Radix-sort binning (GS_FLAG_RADIX_SORT).  One thread per Gaussian: the
-// Gaussian's (tile id, Gaussian id) pairs in tile row-major order at its
-// emission indices, Gaussian-major overall, so a stable sort by tile id leaves
-// every tile's Gaussians in ascending id.
+// Radix-sort binning (GS_FLAG_RADIX_SORT).  Each Gaussian's (tile id,
+// Gaussian id) pairs go in tile row-major order to its emission indices,
+// Gaussian-major overall, so a stable sort by tile id leaves every tile's
+// Gaussians in ascending id.  The block's threads write the block's span of
+// pairs together, consecutive threads consecutive pairs (coalesced stores):
+// each finds its pair's Gaussian by binary search over the block's emission
+// starts in LDS and the tile from the pair's rank in the Gaussian's tile
+// rectangle.
 template <bool kFold, typename Table>
 __global__ __launch_bounds__(kBlockG) void k_emit_pairs(
     Table imgs, const GRec* __restrict__ recs, const int32_t* __restrict__ counts,
@@ -458,24 +462,49 @@ __global__ __launch_bounds__(kBlockG) void k_emit_pairs(
     uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, int32_t* __restrict__ offsets,
     WsHeader* __restrict__ hdr) {
     __shared__ int64_t tmp[kBlockG / 64];
+    __shared__ int64_t s_start[kBlockG];  // block-relative emission start
+    __shared__ uint32_t s_first[kBlockG];  // tile id of the rectangle's first tile
+    __shared__ int32_t s_width[kBlockG];   // tiles per rectangle row
+    __shared__ int32_t s_stride[kBlockG];  // tiles per image row
+    __shared__ int64_t s_total;
     const int64_t base = emission_base<kFold>(bs, nblk, cap, hdr);
-    const int64_t i = (int64_t)blockIdx.x * kBlockG + threadIdx.x;
+    const int t = threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * kBlockG + t;
     const int cnt = i < n_gauss ? counts[i] : 0;
     const int64_t inc = block_inclusive_scan((int64_t)cnt, tmp);
-    int64_t off = base + inc - cnt;
+    const int64_t off = base + inc - cnt;
     if (i < n_gauss) offsets[i] = (int32_t)(off < cap ? off : cap);
-    if (cnt == 0) return;
-    const GRec r = recs[i];
-    const ImgDev& im = imgs[r.img];
-    const int tx0 = r.x0 / tile, tx1 = r.x1 / tile;
-    const int ty0 = r.y0 / tile, ty1 = r.y1 / tile;
-    for (int ty = ty0; ty <= ty1; ++ty) {
-        for (int tx = tx0; tx <= tx1; ++tx) {
-            if (off < cap) {
-                keys[off] = (uint32_t)(im.tile_base + (int64_t)ty * im.tiles_x + tx);
-                vals[off] = (uint32_t)i;
-            }
-            ++off;
+    s_start[t] = inc - cnt;
+    s_first[t] = 0u;
+    s_width[t] = 1;
+    s_stride[t] = 0;
+    if (cnt > 0) {
+        const GRec r = recs[i];
+        const ImgDev& im = imgs[r.img];
+        const int tx0 = r.x0 / tile, tx1 = r.x1 / tile, ty0 = r.y0 / tile;
+        s_first[t] = (uint32_t)(im.tile_base + (int64_t)ty0 * im.tiles_x + tx0);
+        s_width[t] = tx1 - tx0 + 1;
+        s_stride[t] = im.tiles_x;
+    }
+    if (t == kBlockG - 1) s_total = inc;
+    __syncthreads();
+    const int64_t total = s_total;
+    int lo = 0;  // the pairs' Gaussians ascend with p
+    for (int64_t p = t; p < total; p += kBlockG) {
+        // the last Gaussian whose start is at most p (empty Gaussians share
+        // their successor's start and precede it)
+        int a = lo, b = kBlockG - 1;
+        while (a < b) {
+            const int m = (a + b + 1) >> 1;
+            if (s_start[m] <= p) a = m; else b = m - 1;
+        }
+        lo = a;
+        const int k = (int)(p - s_start[a]);  // below the Gaussian's int32 count
+        const int w = s_width[a];
+        const int row = k / w, col = k - row * w;
+        if (base + p < cap) {
+            keys[base + p] = s_first[a] + (uint32_t)row * (uint32_t)s_stride[a] + (uint32_t)col;
+            vals[base + p] = (uint32_t)((int64_t)blockIdx.x * kBlockG + a);
         }
     }
 }
@@ -914,25 +943,44 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(Src src, int nblk,
 }
 
 // One workgroup per digit: exclusive scan of that digit's row over blocks,
-// row total into totals[d].
+// row total into totals[d].  Each wave scans its own contiguous quarter of
+// the row 64 entries at a time with shuffles (no barrier per chunk), the
+// quarters' totals are combined once, and a second sweep adds each
+// quarter's offset.
 __global__ __launch_bounds__(kBlockG) void k_sort_rowscan(int32_t* __restrict__ hist,
                                                           int nblk,
                                                           int32_t* __restrict__ totals) {
-    __shared__ int64_t tmp[kBlockG / 64];
-    __shared__ int64_t last;
+    constexpr int NW = kBlockG / 64;
+    __shared__ int64_t wsum[NW];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int32_t* row = hist + (int64_t)blockIdx.x * nblk;
-    int64_t carry = 0;
-    for (int base = 0; base < nblk; base += kBlockG) {
-        const int j = base + threadIdx.x;
-        const int64_t v = j < nblk ? row[j] : 0;
-        const int64_t inc = block_inclusive_scan(v, tmp);
-        if (j < nblk) row[j] = (int32_t)(carry + inc - v);
-        if (threadIdx.x == kBlockG - 1) last = inc;
-        __syncthreads();
-        carry += last;
-        __syncthreads();
+    const int per = (nblk + NW - 1) / NW;
+    const int lo = min(nblk, wave * per), hi = min(nblk, lo + per);
+    int64_t carry = 0;  // within the wave's quarter
+    for (int b0 = lo; b0 < hi; b0 += 64) {
+        const int j = b0 + lane;
+        const int64_t v = j < hi ? row[j] : 0;
+        int64_t x = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int64_t u = __shfl_up(x, o, 64);
+            if (lane >= o) x += u;
+        }
+        if (j < hi) row[j] = (int32_t)(carry + x - v);  // exclusive within the quarter
+        carry += __shfl(x, 63, 64);
     }
-    if (threadIdx.x == 0) totals[blockIdx.x] = (int32_t)carry;
+    if (lane == 0) wsum[wave] = carry;
+    __syncthreads();
+    int64_t off = 0;
+    for (int k = 0; k < wave; ++k) off += wsum[k];
+    if (off != 0) {
+        for (int j = lo + lane; j < hi; j += 64) row[j] += (int32_t)off;
+    }
+    if (threadIdx.x == 0) {
+        int64_t tot = 0;
+        for (int k = 0; k < NW; ++k) tot += wsum[k];
+        totals[blockIdx.x] = (int32_t)tot;
+    }
 }
 
 // Stable scatter of one sort block.  Items are ranked 256 at a time in index

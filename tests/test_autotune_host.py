@@ -19,7 +19,8 @@ def test_every_candidate_is_accepted_and_others_are_not():
     from paper_2501_06838_amd.autotune import TILE_BATCHES, candidates
     for c in candidates():
         assert _ws(c["tile"], c["lds_batch"], c["flags"]) == N.GS_OK, c
-    assert len(candidates()) == 2 * len(TILE_BATCHES)
+    assert len(candidates()) == 4 * len(TILE_BATCHES)
+    assert {c["flags"] for c in candidates()} == {0, 0x1, 0x4, 0x5}
     for tile in (8, 16, 32):
         for batch in (16, 32, 48, 64, 96, 112, 128, 256, 512):
             ok = (tile, batch) in TILE_BATCHES
@@ -51,6 +52,8 @@ def test_layout_key_depends_on_layout_and_device():
     a = [(64, 64, 3.7, 0, 4096)] * 3
     assert layout_key(a, "gfx950") == layout_key([tuple(x) for x in a], "gfx950")
     assert layout_key(a, "gfx950") != layout_key(a, "other")
+    assert layout_key(a, "gfx950") == layout_key(a, "gfx950", "graph")
+    assert layout_key(a, "gfx950", "graph") != layout_key(a, "gfx950", "eager")
     b = [(64, 64, 3.7000001, 0, 4096)] * 3
     assert layout_key(a, "gfx950") != layout_key(b, "gfx950")
     c = [(64, 64, 3.7, 0, 4096)] * 2

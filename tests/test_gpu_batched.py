@@ -95,13 +95,14 @@ def test_tile_order_is_longest_first():
     assert plan2.tile_order(ws2)[1] == 0
 
 
-def test_persistent_graph_replays_match_default_launch():
-    """Several replays of a captured persistent step (and of the loss
-    reduction's counter), with eager work in between, each give bitwise the
-    default launch's image and gradients."""
+@pytest.mark.parametrize("flags", [PERSISTENT, RADIX, PERSISTENT | RADIX])
+def test_persistent_graph_replays_match_default_launch(flags):
+    """Several replays of a captured persistent or radix-binned step (and of
+    the loss reduction's counter), with eager work in between, each give
+    bitwise the default launch's image, gradients and loss."""
     import paper_2501_06838_amd as P
     wl = synth.config3(n_images=4, with_target=True)
-    plan = plan_for(wl, 16, flags=PERSISTENT)
+    plan = plan_for(wl, 16, flags=flags)
     m, c, col, op = to_dev(wl)
     plan.ensure_capacity(m, c, headroom=1.25)
     target = plan.pack([torch.from_numpy(t) for t in wl.target]).cuda()
