@@ -264,6 +264,32 @@ def tile_kernel_times(B, plan, ws, out, reps):
     return fused, fwd, bwd
 
 
+def valu_probe(torch, blocks=4096, iters=4096):
+    """The library's vector-ALU probe (gs_valu_probe, compiled like the tile
+    kernels: packed FP32 off): FMA rate, exp2 rate and the render-shaped mix
+    (five FMA-class operations and one exp2 per step), each from HIP events
+    around launches of `blocks` workgroups after an untimed launch."""
+    from paper_2501_06838_amd import _native as N
+    from paper_2501_06838_amd.raster import _ptr, _stream
+    out = torch.empty(blocks * 256, device="cuda")
+    L = N.lib()
+    stream = torch.cuda.current_stream()
+    steps = float(blocks) * 256 * iters * 8  # lane-steps per launch (8 chains)
+    res = {"blocks": blocks, "threads": 256, "iters": iters, "chains": 8}
+    for kind in (0, 1, 2):
+        def fn(k=kind):
+            N.check(L.gs_valu_probe(k, blocks, iters, _ptr(out), _stream()), "valu probe")
+        fn()
+        rate = steps / (kernel_ms(torch, stream, fn, 3) * 1e-3)
+        if kind == 0:
+            res["fma_tflops"] = round(2 * rate / 1e12, 2)
+        elif kind == 1:
+            res["exp2_per_s"] = round(rate, -9)
+        else:
+            res["mix_steps_per_s"] = round(rate, -9)
+    return res
+
+
 def roofline_fracs(n_support, hr_px, n_gauss, step_ms, fused_ms):
     """T_roof / T_measured end to end (the step) and render-only (the fused
     tile kernel), T_roof = max(VALU, HBM) time of the algorithmic work."""
@@ -705,14 +731,23 @@ def main():
                                        ("k_render_bwd (L1)", FLOPEQ_BWD, bwd_ms))},
     }
 
-    # the same step with the radix-sort binning (GS_FLAG_RADIX_SORT): same
-    # lists, bitwise; timed the same way
-    rlaunch = dict(launch, flags=launch["flags"] | G.GS_FLAG_RADIX_SORT)
-    binning = {"default": "pairs counted into their tiles, each tile's list sorted",
+    # the same step with the other binning (counting with per-tile list sort,
+    # or GS_FLAG_RADIX_SORT): same lists, bitwise; timed the same way
+    radix = (launch["flags"] & G.GS_FLAG_RADIX_SORT) != 0
+    other = "counting" if radix else "radix_sort"
+    olaunch = dict(launch, flags=launch["flags"] ^ G.GS_FLAG_RADIX_SORT)
+    binning = {"headline": "radix_sort" if radix else "counting",
                "ms_per_step": round(ms_step, 5),
-               "radix_sort": step_record(B, rlaunch, args.steps, kernels=False)}
-    log(f"radix-sort binning: {binning['radix_sort']['ms_per_step']:.4f} ms/step")
+               other: step_record(B, olaunch, args.steps, kernels=False)}
+    log(f"{other} binning: {binning[other]['ms_per_step']:.4f} ms/step")
     del ws, out, grads
+
+    # the vector-ALU probe: the FP32 rate the kernels can issue with packed
+    # FP32 off, against which the fused kernel's rate is also given
+    probe = valu_probe(torch)
+    roofline["measured_fma_tflops"] = probe["fma_tflops"]
+    roofline["frac_of_measured_fma"] = round(fused_tflops / probe["fma_tflops"], 4)
+    log(f"valu probe: FMA {probe['fma_tflops']} TFLOP/s, exp2 {probe['exp2_per_s']:.3g}/s")
 
     others = None
     if not args.no_others:
@@ -752,7 +787,8 @@ def main():
                    "autotune_ms": tuned, "hr_pixels": hr_px, "gaussians": B.n,
                    "tile_pairs": npairs, "support_pairs": n_support,
                    "launch": "whole step captured in one HIP graph, replayed"},
-        "roofline": roofline, "cpu_baseline": cpu, "surrogate_pruned": pruned,
+        "roofline": roofline, "valu_probe": probe, "cpu_baseline": cpu,
+        "surrogate_pruned": pruned,
         "workloads": others, "batched_uneven": batched, "binning": binning,
         "paper_window": paper, "head_psnr": extras,
     }

@@ -515,6 +515,17 @@ gs_status gs_graph_launch(gs_graph graph, void* stream);
 /* Releases the graph (NULL is a no-op). */
 gs_status gs_graph_destroy(gs_graph graph);
 
+/* Vector-ALU throughput probe (roofline calibration, not part of the
+ * method): `blocks` workgroups of 256 threads, each thread running 8
+ * independent FP32 chains of `iters` steps.  kind 0: one FMA per chain and
+ * step (2 FLOP); kind 1: one exp2 per chain and step; kind 2: five FMA-class
+ * operations and one exp2 per chain and step (the shape of the render's
+ * per-pixel work).  The caller times the launch on `stream` and owns `out`
+ * (device, blocks x 256 floats, overwritten).  Compiled like every kernel of
+ * the library (packed FP32 instructions disabled).  GS_E_INVALID for kind
+ * outside 0..2, blocks or iters below 1, or a NULL out. */
+gs_status gs_valu_probe(int32_t kind, int32_t blocks, int32_t iters, float* out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

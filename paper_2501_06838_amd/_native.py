@@ -37,7 +37,7 @@ EXPORTED = (
     "gs_mlp_grad", "gs_mlp_adam", "gs_radius_stats", "gs_sq_error", "gs_tile_order",
     "gs_raster_render_fused_l1", "gs_raster_step_l1", "gs_raster_step_l1_noalloc",
     "gs_mlp_radius", "gs_closed_form_radius", "gs_gaussian_head_forward",
-    "gs_gaussian_head_backward", "gs_psnr_y",
+    "gs_gaussian_head_backward", "gs_psnr_y", "gs_valu_probe",
 )
 
 
@@ -139,6 +139,8 @@ def lib():
         L.gs_gaussian_head_backward.restype = _i32
         L.gs_psnr_y.argtypes = [_imgp, _i32, _vp, _vp, _i32, _vp, _vp, _vp]
         L.gs_psnr_y.restype = _i32
+        L.gs_valu_probe.argtypes = [_i32, _i32, _i32, _vp, _vp]
+        L.gs_valu_probe.restype = _i32
         L.gs_graph_create.argtypes = [_cfgp, _imgp, _i32, _vp, _vp, _vp, _vp, _vp, _i64, _vp,
                                       _sz, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                       ctypes.POINTER(_vp)]

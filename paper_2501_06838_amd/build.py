@@ -17,7 +17,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libgsraster.so")
-SOURCES = ["gs_api.hip", "gs_binning.hip", "gs_render.hip", "gs_surrogate.hip", "gs_head.hip"]
+SOURCES = ["gs_api.hip", "gs_binning.hip", "gs_render.hip", "gs_surrogate.hip", "gs_head.hip",
+           "gs_probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

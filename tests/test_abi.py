@@ -117,3 +117,15 @@ def test_head_and_psnr_host_validation():
     assert L.gs_psnr_y(arr, 1, fake, fake, -1, fake, fake, None) == N.GS_E_INVALID
     assert L.gs_psnr_y(arr, 1, None, fake, 0, fake, fake, None) == N.GS_E_INVALID
     assert L.gs_psnr_y(arr, 0, fake, fake, 0, fake, fake, None) == N.GS_E_INVALID
+
+
+def test_valu_probe_host_validation():
+    """The ALU probe rejects its arguments on the host before any launch."""
+    from paper_2501_06838_amd import _native as N
+    L = N.lib()
+    fake = ctypes.c_void_p(16)  # never dereferenced: every call below fails validation
+    assert L.gs_valu_probe(3, 1, 1, fake, None) == N.GS_E_INVALID
+    assert L.gs_valu_probe(-1, 1, 1, fake, None) == N.GS_E_INVALID
+    assert L.gs_valu_probe(0, 0, 1, fake, None) == N.GS_E_INVALID
+    assert L.gs_valu_probe(0, 1, 0, fake, None) == N.GS_E_INVALID
+    assert L.gs_valu_probe(0, 1, 1, None, None) == N.GS_E_INVALID

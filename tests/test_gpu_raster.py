@@ -431,3 +431,16 @@ def test_graph_replay_matches_eager():
         for a, b in zip(gr_g, gr_e):
             assert torch.allclose(a, b, rtol=1e-5, atol=1e-6 * b.abs().max().item())
     graph.close()
+
+
+def test_valu_probe_runs_every_kind():
+    """The roofline probe: each kind writes a finite value per thread (the
+    chains stay bounded: FMAs contract towards 1, exp2(-x) stays in (0, 1])."""
+    from paper_2501_06838_amd import _native as N
+    from paper_2501_06838_amd.raster import _ptr, _stream
+    out = torch.full((64 * 256,), float("nan"), device="cuda")
+    for kind in (0, 1, 2):
+        say("valu probe", kind)
+        N.check(N.lib().gs_valu_probe(kind, 64, 64, _ptr(out), _stream()), "probe")
+        torch.cuda.synchronize()
+        assert torch.isfinite(out).all()
