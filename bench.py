@@ -122,7 +122,7 @@ def cpu_model():
 
 
 def host_threads():
-    """Cores this process may run on (the GPU machine's CPU share), at most 16."""
+    """Cores this process may run on (its share of the host), at most 16."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:
