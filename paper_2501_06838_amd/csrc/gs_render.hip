@@ -59,7 +59,8 @@ struct TileShape {
 // the budget follows the workgroups the LDS fits per CU: eight with 64 or 96
 // Gaussians per round (64 VGPRs), seven with 112 (72), six with 128 (80); a
 // few values spill, outside the pixel loops.  The forward kernel at 16 x 16
-// holds eight workgroups per CU up to 128 Gaussians per round.  Elsewhere
+// holds eight workgroups per CU up to 112 Gaussians per round and seven with
+// 128 (its LDS).  Elsewhere
 // (and for the elliptical supports, whose FP64 mask building needs more) the
 // compiler's own register count decides.
 template <int T, int B, bool kEll>
@@ -69,7 +70,7 @@ struct BwdOccupancy {
                                    : B == 112             ? 7
                                    : B == 128             ? 6
                                                           : 1;
-    static constexpr int kFwdMinWaves = (T != 16 || kEll || B > 128) ? 1 : 8;
+    static constexpr int kFwdMinWaves = (T != 16 || kEll || B > 128) ? 1 : B == 128 ? 7 : 8;
 };
 
 // Persistent tile kernels: a grid of the resident workgroups walks the items
@@ -95,15 +96,17 @@ __device__ __forceinline__ void run_persistent(int64_t n_items, Body body) {
 // order, into a list of 40-byte records:
 //   l0 = {z1, z2 at the block's first pixel, a, e}
 //   l1 = {g, A0, A1, A2}
-//   l2 = {pixel mask lo, pixel mask hi}.
+//   mk = pixel mask, its low 32 bits (lanes 0-31) in mk[0], its high
+//        32 bits (lanes 32-63) in mk[1].
 // For the block's pixel (dx, dy): z1 = z1_0 + a dx, z2 = z2_0 + e dy - g dx, and the
 // Gaussian's contribution is A_c exp2(-(z1^2 + z2^2)) where the mask is set.
 template <int T, int B>
 struct StageLds {
     static constexpr int NB = TileShape<T>::kBlocks;
+    static_assert(B % 4 == 0, "the forward reads four mask halves per LDS load");
     float4 l0[NB][B];
     float4 l1[NB][B];
-    uint2 l2[NB][B];
+    alignas(16) uint32_t mk[2][NB][B];  // mask halves: [0] lanes 0-31, [1] lanes 32-63
     int scount[NB];
     int wcount[TileShape<T>::kWaves][NB];
     uint8_t slot[NB][B];  // staged Gaussian t's position in block j's list
@@ -267,7 +270,8 @@ __device__ __forceinline__ StagedMine stage_round(StageLds<T, B>& st,
             const float Yb = (kyr + (float)by) - r.fy;
             st.l0[j][pos] = make_float4(r.a * Xb, r.e * Yb - r.g * Xb, r.a, r.e);
             st.l1[j][pos] = make_float4(r.g, r.A[0], r.A[1], r.A[2]);
-            st.l2[j][pos] = make_uint2((uint32_t)my_mask[j], (uint32_t)(my_mask[j] >> 32));
+            st.mk[0][j][pos] = (uint32_t)my_mask[j];
+            st.mk[1][j][pos] = (uint32_t)(my_mask[j] >> 32);
             st.slot[j][t] = (uint8_t)pos;
             mine.touch |= 1u << j;
         }
@@ -279,7 +283,8 @@ __device__ __forceinline__ StagedMine stage_round(StageLds<T, B>& st,
         if (c & 1) {  // an odd list gets an empty record (zero mask, zero amplitude)
             st.l0[t][c] = make_float4(0.f, 0.f, 0.f, 0.f);
             st.l1[t][c] = make_float4(0.f, 0.f, 0.f, 0.f);
-            st.l2[t][c] = make_uint2(0u, 0u);
+            st.mk[0][t][c] = 0u;
+            st.mk[1][t][c] = 0u;
         }
     }
     __syncthreads();
@@ -287,51 +292,49 @@ __device__ __forceinline__ StagedMine stage_round(StageLds<T, B>& st,
 }
 
 // Forward sums of one round: lane = pixel of the wave's blocks, the block's
-// records in list order (wave-uniform), out-of-box lanes masked by the SGPR
-// lane mask.
+// records in list order (wave-uniform coefficients).  Each lane reads its own
+// half of the records' pixel masks (four records per LDS read) and clears its
+// weight where its bit is 0: a sign-extended one-bit field ANDed into the
+// weight's bits, which gives the same +0 as a select.
 template <int T, int B>
 __device__ __forceinline__ void fwd_round(const StageLds<T, B>& st,
                                           float (&acc)[TileShape<T>::kBlocksPerWave][3]) {
     using S = TileShape<T>;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const float lxf = (float)(lane & 7), lyf = (float)(lane >> 3);
+    const int bit = lane & 31;
 #pragma unroll
     for (int m = 0; m < S::kBlocksPerWave; ++m) {
         const int j = wave + S::kWaves * m;
-        // records in pairs (an odd list ends with the staging's empty
-        // record), two pairs per iteration, so LDS reads and sums overlap
-        auto pair = [&](int q) {
+        const uint32_t* mk = st.mk[lane >> 5][j];
+        auto rec = [&](int q, uint32_t mh) {
             const float4 a0 = st.l0[j][q], a1 = st.l1[j][q];
-            const float4 b0 = st.l0[j][q + 1], b1 = st.l1[j][q + 1];
-            const uint32_t alo = __builtin_amdgcn_readfirstlane(st.l2[j][q].x);
-            const uint32_t ahi = __builtin_amdgcn_readfirstlane(st.l2[j][q].y);
-            const uint32_t blo = __builtin_amdgcn_readfirstlane(st.l2[j][q + 1].x);
-            const uint32_t bhi = __builtin_amdgcn_readfirstlane(st.l2[j][q + 1].y);
-            const uint64_t amask = ((uint64_t)ahi << 32) | alo;
-            const uint64_t bmask = ((uint64_t)bhi << 32) | blo;
-            const float za1 = __builtin_fmaf(a0.z, lxf, a0.x);
-            const float za2 = __builtin_fmaf(a0.w, lyf, __builtin_fmaf(-a1.x, lxf, a0.y));
-            const float zb1 = __builtin_fmaf(b0.z, lxf, b0.x);
-            const float zb2 = __builtin_fmaf(b0.w, lyf, __builtin_fmaf(-b1.x, lxf, b0.y));
-            float wa = fast_exp2(-(za1 * za1 + za2 * za2));
-            float wb = fast_exp2(-(zb1 * zb1 + zb2 * zb2));
-            wa = __builtin_amdgcn_inverse_ballot_w64(amask) ? wa : 0.f;
-            wb = __builtin_amdgcn_inverse_ballot_w64(bmask) ? wb : 0.f;
-            acc[m][0] += a1.y * wa;
-            acc[m][1] += a1.z * wa;
-            acc[m][2] += a1.w * wa;
-            acc[m][0] += b1.y * wb;
-            acc[m][1] += b1.z * wb;
-            acc[m][2] += b1.w * wb;
+            const float z1 = __builtin_fmaf(a0.z, lxf, a0.x);
+            const float z2 = __builtin_fmaf(a0.w, lyf, __builtin_fmaf(-a1.x, lxf, a0.y));
+            const float w = fast_exp2(-(z1 * z1 + z2 * z2));
+            const uint32_t keep = (uint32_t)__builtin_amdgcn_sbfe((int32_t)mh, bit, 1);
+            const float wm = __uint_as_float(__float_as_uint(w) & keep);
+            acc[m][0] += a1.y * wm;
+            acc[m][1] += a1.z * wm;
+            acc[m][2] += a1.w * wm;
         };
+        // records four at a time (an odd list ends with the staging's empty
+        // record, so a list is walked in pairs)
         const int cnt = __builtin_amdgcn_readfirstlane(st.scount[j]);  // uniform
         const int cntp = (cnt + 1) & ~1;
         int q = 0;
         for (; q + 4 <= cntp; q += 4) {
-            pair(q);
-            pair(q + 2);
+            const uint4 mh = *reinterpret_cast<const uint4*>(mk + q);
+            rec(q, mh.x);
+            rec(q + 1, mh.y);
+            rec(q + 2, mh.z);
+            rec(q + 3, mh.w);
         }
-        if (q < cntp) pair(q);  // uniform
+        if (q < cntp) {  // uniform
+            const uint2 mh = *reinterpret_cast<const uint2*>(mk + q);
+            rec(q, mh.x);
+            rec(q + 1, mh.y);
+        }
     }
 }
 
@@ -420,8 +423,8 @@ __device__ __forceinline__ void bwd_round(BwdLds<T, B>& sm) {
         }
         if (!active) { j = 0; pos = 0; }
         const float4 c0 = sm.st.l0[j][pos], c1 = sm.st.l1[j][pos];
-        const uint2 c2 = sm.st.l2[j][pos];
-        const uint32_t mlo = active ? c2.x : 0u, mhi = active ? c2.y : 0u;
+        const uint32_t mlo = active ? sm.st.mk[0][j][pos] : 0u;
+        const uint32_t mhi = active ? sm.st.mk[1][j][pos] : 0u;
         const int bx = (j % S::kBlocksX) * 8, by = (j / S::kBlocksX) * 8;
         // block-local rows and columns the wave's boxes cover
         uint32_t cm = mlo | mhi;
