@@ -37,11 +37,14 @@ __device__ __forceinline__ int tile_image(const Table& imgs, int n_img, int64_t 
 
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
-__device__ __forceinline__ uint64_t rows_mask(int r0, int r1) {
-    // bits [8 r0, 8 (r1 + 1)) of a 64-bit word, 0 <= r0 <= r1 <= 7
-    const uint64_t hi = (r1 >= 7) ? ~0ull : ((1ull << (8 * (r1 + 1))) - 1ull);
-    const uint64_t lo = (1ull << (8 * r0)) - 1ull;
-    return hi & ~lo;
+// v + the value of the lane that the DPP control kCtrl names (all lanes
+// active, so every lane reads a valid partner), for an FP64 value moved as
+// its two 32-bit halves.
+template <int kCtrl>
+__device__ __forceinline__ double dpp_add(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), kCtrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), kCtrl, 0xF, 0xF, false);
+    return v + __hiloint2double(hi, lo);
 }
 
 template <int T>
@@ -125,7 +128,7 @@ template <int T, int B>
 struct BwdLds {
     StageLds<T, B> st;
     float4 gt[T * T];       // upstream gradient of the tile, {g0, g1, g2, 0}
-    double lpart[TileShape<T>::kWaves];
+    double lpart[4 * TileShape<T>::kWaves];  // per row of 16 lanes
 };
 
 // What a staging thread keeps about its Gaussian for the backward's sums.
@@ -231,23 +234,41 @@ __device__ __forceinline__ StagedMine stage_round(StageLds<T, B>& st,
             // every listed record is elliptical
             if (lx0 <= lx1 && ly0 <= ly1)
                 ellipse_masks<T>(eparams[mine.gid], ti.im.scale, ti, lx0, lx1, ly0, ly1, my_mask);
-        } else {
+        } else if (lx0 <= lx1 && ly0 <= ly1) {
+            // the box's tile columns and tile rows as bit sets; per block
+            // column its 8 column bits repeated in every byte, per block row
+            // its rows 0-3 and 4-7 as bytes of ones; a block's mask is their AND
+            const uint32_t tc = (~0u << lx0) & (~0u >> (31 - lx1));
+            const uint32_t tr = (~0u << ly0) & (~0u >> (31 - ly1));
+            uint32_t rep[S::kBlocksX], rlo[S::kBlocksX], rhi[S::kBlocksX];
+#pragma unroll
+            for (int b = 0; b < S::kBlocksX; ++b) {
+                const uint32_t c8 = (tc >> (8 * b)) & 255u;
+                const uint32_t c16 = c8 | (c8 << 8);
+                rep[b] = c16 | (c16 << 16);
+                const uint32_t r8 = (tr >> (8 * b)) & 255u;
+                // bit k of a nibble to byte k (k = 0..3), then each byte 1 -> 255
+                const uint32_t l1 = ((r8 & 15u) * 0x00204081u) & 0x01010101u;
+                const uint32_t h1 = ((r8 >> 4) * 0x00204081u) & 0x01010101u;
+                rlo[b] = (l1 << 8) - l1;
+                rhi[b] = (h1 << 8) - h1;
+            }
 #pragma unroll
             for (int j = 0; j < NB; ++j) {
-                const int bx = (j % S::kBlocksX) * 8, by = (j / S::kBlocksX) * 8;
-                const int c0 = max(lx0, bx) - bx, c1 = min(lx1, bx + 7) - bx;
-                const int r0 = max(ly0, by) - by, r1 = min(ly1, by + 7) - by;
-                if (c0 <= c1 && r0 <= r1) {
-                    if (cull) {
-                        const float Xb = (kxr + (float)bx) - r.fx;
-                        const float Yb = (kyr + (float)by) - r.fy;
-                        if (box_qlow(r.a, r.e, r.g, r.a * Xb, r.e * Yb - r.g * Xb, (float)c0,
-                                     (float)c1, (float)r0, (float)r1) > kQCull)
-                            continue;
-                    }
-                    const uint64_t cols = ((1ull << (c1 - c0 + 1)) - 1ull) << c0;
-                    my_mask[j] = (cols * 0x0101010101010101ull) & rows_mask(r0, r1);
+                const int jx = j % S::kBlocksX, jy = j / S::kBlocksX;
+                const uint32_t lo = rep[jx] & rlo[jy], hi = rep[jx] & rhi[jy];
+                if ((lo | hi) == 0u) continue;
+                if (cull) {
+                    const int bx = jx * 8, by = jy * 8;
+                    const int c0 = max(lx0, bx) - bx, c1 = min(lx1, bx + 7) - bx;
+                    const int r0 = max(ly0, by) - by, r1 = min(ly1, by + 7) - by;
+                    const float Xb = (kxr + (float)bx) - r.fx;
+                    const float Yb = (kyr + (float)by) - r.fy;
+                    if (box_qlow(r.a, r.e, r.g, r.a * Xb, r.e * Yb - r.g * Xb, (float)c0,
+                                 (float)c1, (float)r0, (float)r1) > kQCull)
+                        continue;
                 }
+                my_mask[j] = ((uint64_t)hi << 32) | lo;
             }
         }
     }
@@ -352,27 +373,29 @@ __device__ __forceinline__ void fwd_round(const StageLds<T, B>& st,
 // One lane's eight backward sums over the block-local pixels [cx0, cx1] x
 // [ry0, ry1] (the pass's union of boxes; kFull: the whole block, no bounds
 // checks).  The lane's own box is a rectangle: a column outside it gets a far
-// z1 (its weight underflows to 0, and 0 times the finite z is 0), a row
-// outside it a zero weight.  Column by column: z1 is constant down a column,
-// so the z1 moments follow from the column's sums of H w, H w z2 and
-// H w z2^2 (H = sum_c A_c G_c).  rec0 = {z1, z2 at the block's first pixel,
-// a, e}, rec1 = {g, A0, A1, A2}.
+// z1 and a row outside it a far z2 (1e19: the squares stay finite, the
+// weight underflows to 0, and 0 times the finite z is 0), so no pixel needs a
+// select.  Column by column: z1 is constant down a column, so the z1 moments
+// follow from the column's sums of H w, H w z2 and H w z2^2
+// (H = sum_c A_c G_c).  rec0 = {z1, z2 at the block's first pixel, a, e},
+// rec1 = {g, A0, A1, A2}.  kMask (elliptical supports): the record's pixel
+// mask decides every pixel instead.
 template <int T, bool kFull, bool kMask>
 __device__ __forceinline__ void bwd_columns(const float4* __restrict__ gcol, uint32_t colset,
                                             uint32_t rows, uint32_t mlo, uint32_t mhi, int cx0,
                                             int cx1, int ry0, int ry1, float4 rec0, float4 rec1,
                                             float (&m)[8]) {
+    constexpr float kFar = 1e19f;
     const float a = rec0.z, e = rec0.w, gg = rec1.x;
-    bool rv[8];
+    float zr[8];  // e ry inside the lane's rows, far outside
 #pragma unroll
-    for (int ry = 0; ry < 8; ++ry) rv[ry] = (rows >> ry) & 1u;
+    for (int ry = 0; ry < 8; ++ry)
+        zr[ry] = (kMask || ((rows >> ry) & 1u)) ? e * (float)ry : kFar;
 #pragma unroll
     for (int cx = 0; cx < 8; ++cx) {
         if (!kFull && (cx < cx0 || cx > cx1)) continue;  // uniform
-        // kMask: the record's pixel mask decides every pixel (elliptical
-        // supports); a rectangular box gives the same bits either way
         const float z1 = (kMask || ((colset >> cx) & 1u)) ? __builtin_fmaf(a, (float)cx, rec0.x)
-                                                          : 1e19f;
+                                                          : kFar;
         const float z1sq = z1 * z1;
         const float zb = __builtin_fmaf(-gg, (float)cx, rec0.y);
         float sa = 0.f, sb = 0.f, sc = 0.f;
@@ -380,12 +403,9 @@ __device__ __forceinline__ void bwd_columns(const float4* __restrict__ gcol, uin
         for (int ry = 0; ry < 8; ++ry) {
             if (!kFull && (ry < ry0 || ry > ry1)) continue;  // uniform
             const float4 G = gcol[ry * T + cx];
-            const float z2 = __builtin_fmaf(e, (float)ry, zb);
+            const float z2 = zr[ry] + zb;
             float w = fast_exp2(-__builtin_fmaf(z2, z2, z1sq));
-            if (kMask)
-                w = (((ry < 4 ? mlo : mhi) >> (8 * (ry & 3) + cx)) & 1u) ? w : 0.f;
-            else
-                w = rv[ry] ? w : 0.f;
+            if (kMask) w = (((ry < 4 ? mlo : mhi) >> (8 * (ry & 3) + cx)) & 1u) ? w : 0.f;
             m[0] = __builtin_fmaf(G.x, w, m[0]);
             m[1] = __builtin_fmaf(G.y, w, m[1]);
             m[2] = __builtin_fmaf(G.z, w, m[2]);
@@ -426,33 +446,41 @@ __device__ __forceinline__ void bwd_round(BwdLds<T, B>& sm) {
         const uint32_t mlo = active ? sm.st.mk[0][j][pos] : 0u;
         const uint32_t mhi = active ? sm.st.mk[1][j][pos] : 0u;
         const int bx = (j % S::kBlocksX) * 8, by = (j / S::kBlocksX) * 8;
-        // block-local rows and columns the wave's boxes cover
+        // the lane's block-local columns (bits of cm) and rows (bits of rows):
+        // its pixels are row-convex, so its rows run from the first to the
+        // last nonzero byte of the mask
         uint32_t cm = mlo | mhi;
         cm |= cm >> 16;
         cm |= cm >> 8;
-        uint32_t rows = 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            rows |= ((mlo >> (8 * k)) & 255u) ? (1u << k) : 0u;
-            rows |= ((mhi >> (8 * k)) & 255u) ? (1u << (k + 4)) : 0u;
+        cm &= 255u;
+        const uint64_t mm = ((uint64_t)mhi << 32) | mlo;
+        uint32_t rows = 0u;
+        if (mm != 0ull) {
+            const int r0 = __builtin_ctzll(mm) >> 3, r1 = (63 - __builtin_clzll(mm)) >> 3;
+            rows = (255u << r0) & (255u >> (7 - r1));
         }
-        uint32_t any = (cm & 255u) | (rows << 8);
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) any |= (uint32_t)__shfl_xor((int)any, o, 64);
-        any = __builtin_amdgcn_readfirstlane(any);
-        const int cx0 = __builtin_ctz(any & 255u), cx1 = 31 - __builtin_clz(any & 255u);
-        const int ry0 = __builtin_ctz(any >> 8), ry1 = 31 - __builtin_clz(any >> 8);
-        const uint32_t colset = cm & 255u;
         const float4* gcol = &sm.gt[by * T + bx];
         float m[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        if constexpr (kEll)  // elliptical supports: the pixel mask decides
-            bwd_columns<T, false, true>(gcol, colset, rows, mlo, mhi, cx0, cx1, ry0, ry1, c0,
-                                        c1, m);
-        else if (cx0 == 0 && cx1 == 7 && ry0 == 0 && ry1 == 7)  // uniform: the whole block
-            bwd_columns<T, true, false>(gcol, colset, rows, mlo, mhi, 0, 7, 0, 7, c0, c1, m);
-        else
-            bwd_columns<T, false, false>(gcol, colset, rows, mlo, mhi, cx0, cx1, ry0, ry1, c0,
-                                         c1, m);
+        // the pass walks the bounding box of its lanes' boxes: the whole block
+        // when some lane has column 0, some column 7, some row 0 and some row 7
+        const bool full = __ballot(cm & 1u) != 0ull && __ballot(cm & 128u) != 0ull &&
+                          __ballot(rows & 1u) != 0ull && __ballot(rows & 128u) != 0ull;
+        if (!kEll && full) {  // uniform
+            bwd_columns<T, true, false>(gcol, cm, rows, mlo, mhi, 0, 7, 0, 7, c0, c1, m);
+        } else {
+            uint32_t any = cm | (rows << 8);
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) any |= (uint32_t)__shfl_xor((int)any, o, 64);
+            any = __builtin_amdgcn_readfirstlane(any);
+            const int cx0 = __builtin_ctz(any & 255u), cx1 = 31 - __builtin_clz(any & 255u);
+            const int ry0 = __builtin_ctz(any >> 8), ry1 = 31 - __builtin_clz(any >> 8);
+            if constexpr (kEll)  // elliptical supports: the pixel mask decides
+                bwd_columns<T, false, true>(gcol, cm, rows, mlo, mhi, cx0, cx1, ry0, ry1, c0, c1,
+                                            m);
+            else
+                bwd_columns<T, false, false>(gcol, cm, rows, mlo, mhi, cx0, cx1, ry0, ry1, c0,
+                                             c1, m);
+        }
         const float m0 = m[0], m1 = m[1], m2 = m[2], m3 = m[3], m4 = m[4], m5 = m[5],
                     m6 = m[6], m7 = m[7];
         if (active) {
@@ -556,12 +584,18 @@ template <int T, int B>
 __device__ __forceinline__ void tile_loss_sum(BwdLds<T, B>& sm, double lsum,
                                               double* __restrict__ tile_loss, int64_t tile) {
     constexpr int NW = TileShape<T>::kWaves;
-    for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o, 64);
-    if ((threadIdx.x & 63) == 0) sm.lpart[threadIdx.x >> 6] = lsum;
+    // butterflies within each row of 16 lanes (lane pairs i^1, i^2, then the
+    // mirrored halves of 8 and of 16): every lane of a row ends with the same
+    // row sum, with no LDS round trip
+    lsum = dpp_add<0xB1>(lsum);   // quad_perm [1, 0, 3, 2]
+    lsum = dpp_add<0x4E>(lsum);   // quad_perm [2, 3, 0, 1]
+    lsum = dpp_add<0x141>(lsum);  // row_half_mirror
+    lsum = dpp_add<0x140>(lsum);  // row_mirror
+    if ((threadIdx.x & 15) == 0) sm.lpart[threadIdx.x >> 4] = lsum;
     __syncthreads();
     if (threadIdx.x == 0) {
         double sum = 0.0;
-        for (int k = 0; k < NW; ++k) sum += sm.lpart[k];
+        for (int k = 0; k < 4 * NW; ++k) sum += sm.lpart[k];
         tile_loss[tile] = sum;
     }
 }
