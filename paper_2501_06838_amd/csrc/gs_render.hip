@@ -493,9 +493,10 @@ __device__ __forceinline__ void bwd_round(BwdLds<T, B>& sm) {
 }
 
 // The round's sums per (tile, Gaussian): blocks added in ascending order,
-// stored per sorted pair (or added with global atomics).  Ends with a barrier.
+// stored per sorted pair (or added with global atomics).  Ends with a barrier
+// unless it is the tile's last round (the LDS is not read again).
 template <int T, int B>
-__device__ __forceinline__ void bwd_round_store(BwdLds<T, B>& sm, StagedMine mine, int base,
+__device__ __forceinline__ void bwd_round_store(BwdLds<T, B>& sm, StagedMine mine, bool last,
                                                 int nb, float* __restrict__ moments,
                                                 float4* __restrict__ partials,
                                                 int atomic_grads) {
@@ -528,7 +529,7 @@ __device__ __forceinline__ void bwd_round_store(BwdLds<T, B>& sm, StagedMine min
             dst[1] = v;
         }
     }
-    __syncthreads();
+    if (!last) __syncthreads();  // uniform
 }
 
 template <int T, typename Table>
@@ -653,7 +654,8 @@ __device__ __forceinline__ void bwd_tile(
         const int nb = min(B, ti.rg.y - base);
         const StagedMine mine = stage_round<T, B, kEll>(sm.st, svals, recs, offsets, eparams, ti, base, nb);
         bwd_round<T, B, kEll>(sm);
-        bwd_round_store<T, B>(sm, mine, base, nb, moments, partials, atomic_grads);
+        bwd_round_store<T, B>(sm, mine, base + B >= ti.rg.y, nb, moments, partials,
+                              atomic_grads);
     }
 }
 
@@ -714,7 +716,7 @@ __device__ __forceinline__ void fused_tile(
     if (ti.rg.y <= ti.rg.x) return;  // uniform
     if (one_round) {
         bwd_round<T, B, kEll>(sm);
-        bwd_round_store<T, B>(sm, mine, ti.rg.x, ti.rg.y - ti.rg.x, moments, partials,
+        bwd_round_store<T, B>(sm, mine, true, ti.rg.y - ti.rg.x, moments, partials,
                               atomic_grads);
         return;
     }
@@ -722,7 +724,8 @@ __device__ __forceinline__ void fused_tile(
         const int nb = min(B, ti.rg.y - base);
         mine = stage_round<T, B, kEll>(sm.st, svals, recs, offsets, eparams, ti, base, nb);
         bwd_round<T, B, kEll>(sm);
-        bwd_round_store<T, B>(sm, mine, base, nb, moments, partials, atomic_grads);
+        bwd_round_store<T, B>(sm, mine, base + B >= ti.rg.y, nb, moments, partials,
+                              atomic_grads);
     }
 }
 
