@@ -50,23 +50,18 @@ FLOPEQ_BWD = 48.0
 BYTES_PER_PX = 24.0
 BYTES_PER_GAUSS = 108.0
 
-# Counters of one fused tile-kernel launch (k_render_fused) on the headline
-# workload at tile 16, LDS batch 96, from rocprofv3 --pmc passes (FETCH_SIZE,
-# then WRITE_SIZE, KiB per dispatch), each scaled by what the same counter
-# reads for a plain 256 MiB device copy (factors below); and the same
-# kernel's VALU counters: busy = SQ_ACTIVE_INST_VALU x 4 / 1,024 SIMDs /
-# (GRBM_GUI_ACTIVE / 8 XCDs).  Valid only while the render sources hash to
-# `sources`; otherwise reported as null.
 # Counter readings of k_render_fused on config2a per launch configuration
-# (rocprofv3 --pmc runs, averaged per dispatch; summaries and commands in
-# profiles/config2a_k_render_fused_traffic.md), valid while the
-# render sources hash to `sources`.  The factors scale FETCH_SIZE and
-# WRITE_SIZE by what the counters read for a plain copy of known size.
-PROFILE = {"workload": "config2a", "sources": "240d766f5e6d0038",
+# (rocprofv3 --pmc runs, FETCH_SIZE then WRITE_SIZE, KiB per dispatch
+# averaged; summaries and commands in
+# profiles/config2a_k_render_fused_traffic.md), valid while the render
+# sources hash to `sources` (otherwise reported as null).  The factors scale
+# FETCH_SIZE and WRITE_SIZE by what the counters read for a plain 256 MiB
+# device copy.
+PROFILE = {"workload": "config2a", "sources": "0fd317bab16fbe6d",
            "launches": {
-               (16, 96, 0): {"fetch_kib": 41638.6, "write_kib": 108977.5},
-               (16, 112, 0): {"fetch_kib": 37878.7, "write_kib": 95027.5},
-               (16, 128, 0): {"fetch_kib": 37862.4, "write_kib": 95008.6}},
+               (16, 96, 0): {"fetch_kib": 41152.2, "write_kib": 164374.8},
+               (16, 112, 0): {"fetch_kib": 37853.5, "write_kib": 95029.3},
+               (16, 128, 0): {"fetch_kib": 37822.1, "write_kib": 95012.4}},
            "fetch_factor": 2.313, "write_factor": 1.157}
 PROFILE_SOURCES = ("paper_2501_06838_amd/csrc/gs_render.hip",
                    "paper_2501_06838_amd/csrc/gs_internal.h")
