@@ -752,37 +752,74 @@ __global__ __launch_bounds__(kBlockG) void k_place(
     }
 }
 
+// The smaller and the larger of a lane's value and the value of lane
+// (lane ^ d), d in {1, 2, 4, 8, 16, 32}, without an LDS round trip: DPP lane
+// moves within rows of 16 (d = 4 as a quad reversal then a half-row mirror,
+// d = 8 as a rotation by 8 within the row), the row and half-wave swaps of
+// gfx950 for 16 and 32 (each lane then holds both values of its pair).
+template <int kD>
+__device__ __forceinline__ void xor_minmax(uint32_t v, uint32_t& lo, uint32_t& hi) {
+    if constexpr (kD == 16 || kD == 32) {
+        const auto r = kD == 16 ? __builtin_amdgcn_permlane16_swap(v, v, false, false)
+                                : __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        lo = min((uint32_t)r[0], (uint32_t)r[1]);
+        hi = max((uint32_t)r[0], (uint32_t)r[1]);
+    } else {
+        const int x = (int)v;
+        int p;
+        if constexpr (kD == 1) {
+            p = __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+        } else if constexpr (kD == 2) {
+            p = __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+        } else if constexpr (kD == 4) {
+            const int q = __builtin_amdgcn_update_dpp(0, x, 0x1B, 0xF, 0xF, false);  // [3,2,1,0]
+            p = __builtin_amdgcn_update_dpp(0, q, 0x141, 0xF, 0xF, false);  // row_half_mirror
+        } else {
+            static_assert(kD == 8, "lane distance");
+            p = __builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false);  // row_ror:8
+        }
+        lo = min(v, (uint32_t)p);
+        hi = max(v, (uint32_t)p);
+    }
+}
+
 // Ascending bitonic sort of 64 K values held K per lane across the wave:
 // element i = 64 k + lane is v[k] of that lane.  Partners closer than 64 are
 // exchanged across lanes, farther ones between a lane's own registers.
-template <int K>
-__device__ __forceinline__ void wave_sort(uint32_t (&v)[K]) {
-    const int lane = threadIdx.x & 63;
+template <int K, int kS, int kD>
+__device__ __forceinline__ void bitonic_step(uint32_t (&v)[K], int lane) {
+    if constexpr (kD >= 64) {
+        constexpr int kd = kD >> 6;
 #pragma unroll
-    for (int s = 2; s <= 64 * K; s <<= 1) {
+        for (int k = 0; k < K; ++k) {
+            if (k & kd) continue;
+            const bool up = (((k << 6) | lane) & kS) == 0;
+            const uint32_t lo = min(v[k], v[k | kd]), hi = max(v[k], v[k | kd]);
+            v[k] = up ? lo : hi;
+            v[k | kd] = up ? hi : lo;
+        }
+    } else {
 #pragma unroll
-        for (int d = s >> 1; d > 0; d >>= 1) {
-            if (d >= 64) {
-                const int kd = d >> 6;
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    if (k & kd) continue;
-                    const bool up = (((k << 6) | lane) & s) == 0;
-                    const uint32_t lo = min(v[k], v[k | kd]), hi = max(v[k], v[k | kd]);
-                    v[k] = up ? lo : hi;
-                    v[k | kd] = up ? hi : lo;
-                }
-            } else {
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    const uint32_t p = (uint32_t)__shfl_xor((int)v[k], d, 64);
-                    const bool up = (((k << 6) | lane) & s) == 0;
-                    const bool low = (lane & d) == 0;
-                    v[k] = (low == up) ? min(v[k], p) : max(v[k], p);
-                }
-            }
+        for (int k = 0; k < K; ++k) {
+            uint32_t lo, hi;
+            xor_minmax<kD>(v[k], lo, hi);
+            const bool up = (((k << 6) | lane) & kS) == 0;
+            const bool low = (lane & kD) == 0;
+            v[k] = (low == up) ? lo : hi;
         }
     }
+    if constexpr (kD > 1) bitonic_step<K, kS, kD / 2>(v, lane);
+}
+
+template <int K, int kS>
+__device__ __forceinline__ void bitonic_stage(uint32_t (&v)[K], int lane) {
+    bitonic_step<K, kS, kS / 2>(v, lane);
+    if constexpr (kS < 64 * K) bitonic_stage<K, kS * 2>(v, lane);
+}
+
+template <int K>
+__device__ __forceinline__ void wave_sort(uint32_t (&v)[K]) {
+    bitonic_stage<K, 2>(v, threadIdx.x & 63);
 }
 
 // One wave sorts seg[0, n), n <= 64 K, in registers and writes it back.
