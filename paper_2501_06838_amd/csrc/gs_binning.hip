@@ -28,8 +28,62 @@ namespace gs {
 
 namespace {
 
+// Cross-lane steps on 64-bit values without LDS round trips (all 64 lanes
+// active).  dpp64: the value of the lane that the DPP control names, moved as
+// two 32-bit halves (0 where the control names no lane or the row is masked
+// off).  swap64: the pair {value of lane l, value of lane l ^ kD} in lane
+// order, kD = 16 or 32, from the gfx950 row and half-wave swaps.
+template <int kCtrl, int kRowMask = 0xF>
+__device__ __forceinline__ int64_t dpp64(int64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, kCtrl,
+                                                              kRowMask, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(
+        0, (int)(uint32_t)((uint64_t)v >> 32), kCtrl, kRowMask, 0xF, false);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+template <int kD>
+__device__ __forceinline__ void swap64(int64_t v, int64_t& r0, int64_t& r1) {
+    const uint32_t lo = (uint32_t)v, hi = (uint32_t)((uint64_t)v >> 32);
+    const auto a = kD == 16 ? __builtin_amdgcn_permlane16_swap(lo, lo, false, false)
+                            : __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto b = kD == 16 ? __builtin_amdgcn_permlane16_swap(hi, hi, false, false)
+                            : __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    r0 = (int64_t)(((uint64_t)(uint32_t)b[0] << 32) | (uint32_t)a[0]);
+    r1 = (int64_t)(((uint64_t)(uint32_t)b[1] << 32) | (uint32_t)a[1]);
+}
+
+// Butterfly over the wave: every lane ends with op over all 64 lanes
+// (partners at lane distance 1, 2, 4, 8 by DPP: quad permutes, a quad
+// reversal followed by a half-row mirror, a rotation by 8 within the row;
+// 16 and 32 by the swaps).
+template <typename Op>
+__device__ __forceinline__ int64_t wave_butterfly(int64_t v, Op op) {
+    v = op(v, dpp64<0xB1>(v));                // quad_perm [1, 0, 3, 2]
+    v = op(v, dpp64<0x4E>(v));                // quad_perm [2, 3, 0, 1]
+    v = op(v, dpp64<0x141>(dpp64<0x1B>(v)));  // quad_perm [3, 2, 1, 0], row_half_mirror
+    v = op(v, dpp64<0x128>(v));               // row_ror:8
+    int64_t r0, r1;
+    swap64<16>(v, r0, r1);
+    v = op(r0, r1);
+    swap64<32>(v, r0, r1);
+    return op(r0, r1);
+}
+
 __device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return wave_butterfly(v, [](int64_t a, int64_t b) { return a + b; });
+}
+
+// Inclusive scan of one value per lane across the wave: shifts by 1, 2, 4, 8
+// within each row of 16, then each row adds the totals of the rows before it
+// (lane 15 into rows 1 and 3, then lane 31 into rows 2 and 3).
+__device__ __forceinline__ int64_t wave_inclusive_scan_i64(int64_t v) {
+    v += dpp64<0x111>(v);       // row_shr:1
+    v += dpp64<0x112>(v);       // row_shr:2
+    v += dpp64<0x114>(v);       // row_shr:4
+    v += dpp64<0x118>(v);       // row_shr:8
+    v += dpp64<0x142, 0xA>(v);  // row_bcast:15
+    v += dpp64<0x143, 0xC>(v);  // row_bcast:31
     return v;
 }
 
@@ -37,10 +91,7 @@ __device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
 // kBlockG threads.  `tmp` holds kBlockG / 64 entries.
 __device__ __forceinline__ int64_t block_inclusive_scan(int64_t v, int64_t* tmp) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int o = 1; o < 64; o <<= 1) {
-        int64_t u = __shfl_up(v, o, 64);
-        if (lane >= o) v += u;
-    }
+    v = wave_inclusive_scan_i64(v);
     if (lane == 63) tmp[wave] = v;
     __syncthreads();
     int64_t carry = 0;
@@ -378,10 +429,8 @@ __global__ __launch_bounds__(kBlockG) void k_emit(
         hi = tb + (int64_t)ty1 * tiles_x + tx1;
     }
     // the block's tile window
-    for (int o = 32; o > 0; o >>= 1) {
-        lo = min(lo, (int64_t)__shfl_xor(lo, o, 64));
-        hi = max(hi, (int64_t)__shfl_xor(hi, o, 64));
-    }
+    lo = wave_butterfly(lo, [](int64_t a, int64_t b) { return min(a, b); });
+    hi = wave_butterfly(hi, [](int64_t a, int64_t b) { return max(a, b); });
     if (lane == 0) { win[0][wave] = lo; win[1][wave] = hi; }
     __syncthreads();
     int64_t wlo = win[0][0], whi = win[1][0];
@@ -559,18 +608,11 @@ __global__ __launch_bounds__(kBlockG) void k_ranges(const uint32_t* __restrict__
 __device__ __forceinline__ int64_t scan_block_inclusive(int64_t v, int64_t* tmp) {
     constexpr int NW = kScanThreads / 64;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int o = 1; o < 64; o <<= 1) {
-        const int64_t u = __shfl_up(v, o, 64);
-        if (lane >= o) v += u;
-    }
+    v = wave_inclusive_scan_i64(v);
     if (lane == 63) tmp[wave] = v;
     __syncthreads();
     if (wave == 0) {
-        int64_t x = lane < NW ? tmp[lane] : 0;
-        for (int o = 1; o < NW; o <<= 1) {
-            const int64_t u = __shfl_up(x, o, 64);
-            if (lane >= o) x += u;
-        }
+        const int64_t x = wave_inclusive_scan_i64(lane < NW ? tmp[lane] : 0);
         if (lane < NW) tmp[lane] = x;  // inclusive over waves
     }
     __syncthreads();
