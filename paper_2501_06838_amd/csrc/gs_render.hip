@@ -59,19 +59,18 @@ struct TileShape {
 
 // Waves per SIMD the tile kernels are compiled for (their register
 // budget).  The backward and fused kernels are latency bound, so at 16 x 16
-// the budget follows the workgroups the LDS fits per CU: eight with 64
-// Gaussians per round (64 VGPRs), seven with 96 or 112 (72: at 96 the LDS
-// would fit eight, but the 64-VGPR budget spilled in the pixel loops' set-up
-// and ran 2-3% slower), six with 128 (80); a few values spill, outside the
-// pixel loops.  The forward kernel at 16 x 16 holds eight workgroups per CU
-// up to 112 Gaussians per round and seven with 128 (its LDS).  Elsewhere
+// the budget follows the workgroups the LDS fits per CU: eight with 64 or 96
+// Gaussians per round (64 VGPRs), seven with 112 (72), six with 128 (80); a
+// few values spill, outside the pixel loops.  The forward kernel at 16 x 16
+// holds eight workgroups per CU up to 112 Gaussians per round and seven with
+// 128 (its LDS).  Elsewhere
 // (and for the elliptical supports, whose FP64 mask building needs more) the
 // compiler's own register count decides.
 template <int T, int B, bool kEll>
 struct BwdOccupancy {
     static constexpr int kMinWaves = (T != 16 || kEll) ? 1
-                                   : B == 64              ? 8
-                                   : (B == 96 || B == 112) ? 7
+                                   : (B == 64 || B == 96) ? 8
+                                   : B == 112             ? 7
                                    : B == 128             ? 6
                                                           : 1;
     static constexpr int kFwdMinWaves = (T != 16 || kEll || B > 128) ? 1 : B == 128 ? 7 : 8;
