@@ -261,9 +261,13 @@ def tile_kernel_times(B, plan, ws, out, reps):
 
 def valu_probe(torch, blocks=4096, iters=4096):
     """The library's vector-ALU probe (gs_valu_probe, compiled like the tile
-    kernels: packed FP32 off): FMA rate, exp2 rate and the render-shaped mix
-    (five FMA-class operations and one exp2 per step), each from HIP events
-    around launches of `blocks` workgroups after an untimed launch."""
+    kernels: packed FP32 off): FMA rate, exp2 rate, the render-shaped mix
+    (five FMA-class operations and one exp2 per step), and the issue cost of
+    three lane-mask forms next to one FMA per step (a select on an SGPR-pair
+    mask, a select on a mask read with readfirstlane, a one-bit field
+    extract ANDed into the value), as SIMD cycles per wave64 step taking
+    the FMA-only step as 4 cycles; each from HIP events around launches of
+    `blocks` workgroups after an untimed launch."""
     from paper_2501_06838_amd import _native as N
     from paper_2501_06838_amd.raster import _ptr, _stream
     out = torch.empty(blocks * 256, device="cuda")
@@ -271,17 +275,24 @@ def valu_probe(torch, blocks=4096, iters=4096):
     stream = torch.cuda.current_stream()
     steps = float(blocks) * 256 * iters * 8  # lane-steps per launch (8 chains)
     res = {"blocks": blocks, "threads": 256, "iters": iters, "chains": 8}
-    for kind in (0, 1, 2):
+    ms = {}
+    for kind in range(6):
         def fn(k=kind):
             N.check(L.gs_valu_probe(k, blocks, iters, _ptr(out), _stream()), "valu probe")
         fn()
-        rate = steps / (kernel_ms(torch, stream, fn, 3) * 1e-3)
+        ms[kind] = kernel_ms(torch, stream, fn, 3)
+        rate = steps / (ms[kind] * 1e-3)
         if kind == 0:
             res["fma_tflops"] = round(2 * rate / 1e12, 2)
         elif kind == 1:
             res["exp2_per_s"] = round(rate, -9)
-        else:
+        elif kind == 2:
             res["mix_steps_per_s"] = round(rate, -9)
+    res["mask_step_cycles"] = {
+        "fma_only": 4.0,
+        "fma_select_sgpr_mask": round(4.0 * ms[3] / ms[0], 2),
+        "fma_readfirstlane_mask_select": round(4.0 * ms[4] / ms[0], 2),
+        "fma_bit_extract_and": round(4.0 * ms[5] / ms[0], 2)}
     return res
 
 
@@ -742,7 +753,8 @@ def main():
     probe = valu_probe(torch)
     roofline["measured_fma_tflops"] = probe["fma_tflops"]
     roofline["frac_of_measured_fma"] = round(fused_tflops / probe["fma_tflops"], 4)
-    log(f"valu probe: FMA {probe['fma_tflops']} TFLOP/s, exp2 {probe['exp2_per_s']:.3g}/s")
+    log(f"valu probe: FMA {probe['fma_tflops']} TFLOP/s, exp2 {probe['exp2_per_s']:.3g}/s, "
+        f"mask step cycles {probe['mask_step_cycles']}")
 
     others = None
     if not args.no_others:

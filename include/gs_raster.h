@@ -520,10 +520,14 @@ gs_status gs_graph_destroy(gs_graph graph);
  * independent FP32 chains of `iters` steps.  kind 0: one FMA per chain and
  * step (2 FLOP); kind 1: one exp2 per chain and step; kind 2: five FMA-class
  * operations and one exp2 per chain and step (the shape of the render's
- * per-pixel work).  The caller times the launch on `stream` and owns `out`
- * (device, blocks x 256 floats, overwritten).  Compiled like every kernel of
- * the library (packed FP32 instructions disabled).  GS_E_INVALID for kind
- * outside 0..2, blocks or iters below 1, or a NULL out. */
+ * per-pixel work); kinds 3-5: one FMA per chain and step followed by a lane
+ * mask, a select on an SGPR-pair mask (3), a select on a mask read with
+ * readfirstlane (4), a one-bit field extract ANDed into the value (5), so
+ * that a mask's cost is the step time minus kind 0's.  The caller times the
+ * launch on `stream` and owns `out` (device, blocks x 256 floats,
+ * overwritten).  Compiled like every kernel of the library (packed FP32
+ * instructions disabled).  GS_E_INVALID for kind outside 0..5, blocks or
+ * iters below 1, or a NULL out. */
 gs_status gs_valu_probe(int32_t kind, int32_t blocks, int32_t iters, float* out, void* stream);
 
 #ifdef __cplusplus

@@ -124,7 +124,7 @@ def test_valu_probe_host_validation():
     from paper_2501_06838_amd import _native as N
     L = N.lib()
     fake = ctypes.c_void_p(16)  # never dereferenced: every call below fails validation
-    assert L.gs_valu_probe(3, 1, 1, fake, None) == N.GS_E_INVALID
+    assert L.gs_valu_probe(6, 1, 1, fake, None) == N.GS_E_INVALID
     assert L.gs_valu_probe(-1, 1, 1, fake, None) == N.GS_E_INVALID
     assert L.gs_valu_probe(0, 0, 1, fake, None) == N.GS_E_INVALID
     assert L.gs_valu_probe(0, 1, 0, fake, None) == N.GS_E_INVALID

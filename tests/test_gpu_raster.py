@@ -435,11 +435,12 @@ def test_graph_replay_matches_eager():
 
 def test_valu_probe_runs_every_kind():
     """The roofline probe: each kind writes a finite value per thread (the
-    chains stay bounded: FMAs contract towards 1, exp2(-x) stays in (0, 1])."""
+    chains stay bounded: FMAs contract towards 1, exp2(-x) stays in (0, 1],
+    a mask leaves the value or replaces it by c or 0)."""
     from paper_2501_06838_amd import _native as N
     from paper_2501_06838_amd.raster import _ptr, _stream
     out = torch.full((64 * 256,), float("nan"), device="cuda")
-    for kind in (0, 1, 2):
+    for kind in range(6):
         say("valu probe", kind)
         N.check(N.lib().gs_valu_probe(kind, 64, 64, _ptr(out), _stream()), "probe")
         torch.cuda.synchronize()
